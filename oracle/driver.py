@@ -1,0 +1,126 @@
+"""One DC-LNO density build, in the order of the paper's procedure (Sec. II.C, (i)-(v)).
+
+(i)   LNOs of every atom from the previous density matrix (skipped for plain DC);
+(ii)  cluster matrices with PAO/LNO blocks for every atom;
+(iii) the cluster eigenproblems;
+(iv)  one chemical potential for all clusters;
+(v)   density rows of every atom.
+Clusters are independent, so (ii)-(iii) and (v) run in a process pool, one cluster per
+task, each worker on one BLAS thread.
+"""
+from __future__ import annotations
+
+import os
+import time
+import multiprocessing as mp
+
+import numpy as np
+
+from .regions import plan_regions
+from .lno import all_lnos
+from .cluster import solve_cluster
+from .density import bisect_mu, density_rows, band_energy_and_count
+
+_G = {}
+
+
+def _init_worker():
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        pass
+
+
+def _solve(i):
+    out = solve_cluster(_G["sys"], _G["regions"][i], _G["us"], _G["ranks"], keep_rows=_G["keep_rows"])
+    if _G["mu"] is not None:
+        mu, kT = _G["mu"], _G["kT"]
+        if "rows" not in out:
+            out = solve_cluster(_G["sys"], _G["regions"][i], _G["us"], _G["ranks"], keep_rows=True)
+        out["D"] = density_rows(out["rows"][int(_G["regions"][i].center)], out["rows"], out["eps"], mu, kT)
+        del out["rows"]
+    return i, out
+
+
+def _map(fn, items, workers):
+    if workers <= 1 or len(items) <= 1:
+        return [fn(i) for i in items]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers, initializer=_init_worker) as pool:
+        return pool.map(fn, items, chunksize=max(1, len(items) // (8 * workers)))
+
+
+def default_workers():
+    return int(os.environ.get("LDC_ORACLE_WORKERS", min(16, os.cpu_count() or 1)))
+
+
+def density_build(sysd, dprev=None, fixed_rank=None, mu=None, clusters=None, workers=None,
+                  lno=None, regions=None, verbose=False):
+    """One density build.
+
+    dprev: previous density matrix (BSR values) for the LNOs; None or lno=False gives plain
+    DC.  fixed_rank: None, int, or per-atom array overriding the LNO rank rule.  mu: if
+    given, no bisection; density rows at this chemical potential.  clusters: restrict to
+    these atoms (needs mu for density rows).  Returns a dict with D (BSR values, rows of
+    the computed clusters), mu, e_band, n_e, spectra {i: (eps, w)}, ranks, us, regions,
+    dims, iters and timings.
+    """
+    t0 = time.time()
+    kT = sysd["kT"]
+    g = float(sysd.get("spin_g", 2))
+    if lno is None:
+        lno = bool(sysd.get("lno", True)) and dprev is not None
+    if regions is None:
+        regions = plan_regions(sysd, lno=lno)
+    us = ranks = None
+    if lno:
+        us, _, ranks = all_lnos(sysd, dprev, fixed_rank=fixed_rank)
+    t_lno = time.time()
+    n = sysd["n_atoms"]
+    idx = list(range(n)) if clusters is None else [int(c) for c in clusters]
+    workers = default_workers() if workers is None else workers
+    # keep the coefficient rows in one pass when they fit comfortably in memory
+    est = 0
+    for i in idx[: min(len(idx), 8)]:
+        r = regions[i]
+        est += 8 * 9 * (r.n_fna + 1) * 9 * len(r.members)
+    est = est / max(1, min(len(idx), 8)) * len(idx)
+    keep_rows = est < 3e9
+    _G.update(sys=sysd, regions=regions, us=us, ranks=ranks, keep_rows=keep_rows and mu is None,
+              mu=mu, kT=kT)
+    res = dict(_map(_solve, idx, workers))
+    t_solve = time.time()
+    spectra = {i: (res[i]["eps"], res[i]["w"]) for i in idx}
+    iters = 0
+    if mu is None:
+        if clusters is not None:
+            raise ValueError("a cluster subset needs an explicit chemical potential")
+        mu, iters = bisect_mu([spectra[i] for i in idx], sysd["n_electrons"], kT, g)
+        if keep_rows:
+            for i in idx:
+                r = res[i]
+                res[i]["D"] = density_rows(r["rows"][i], r["rows"], r["eps"], mu, kT)
+        else:
+            _G.update(mu=mu)
+            res2 = dict(_map(_solve, idx, workers))
+            for i in idx:
+                res[i]["D"] = res2[i]["D"]
+    t_mu = time.time()
+    dvals = np.zeros_like(sysd["S"])
+    row_ptr, col, blk_off, n_orb = sysd["row_ptr"], sysd["col"], sysd["blk_off"], sysd["n_orb"]
+    for i in idx:
+        dblk = res[i]["D"]
+        for b in range(row_ptr[i], row_ptr[i + 1]):
+            j = int(col[b])
+            dvals[blk_off[b]: blk_off[b] + n_orb[i] * n_orb[j]] = dblk[j].ravel()
+    e_band, n_e = band_energy_and_count(sysd, dvals, g)
+    e_spec = g * sum(float(np.sum(0.5 * (1 - np.tanh(0.5 * (spectra[i][0] - mu) / kT)) * spectra[i][0] * spectra[i][1]))
+                     for i in idx)
+    out = dict(D=dvals, mu=mu, e_band=e_band, n_e=n_e, e_band_spectral=e_spec, spectra=spectra,
+               ranks=ranks, us=us, regions=regions, dims={i: res[i]["dim"] for i in idx}, iters=iters,
+               times=dict(lno=t_lno - t0, solve=t_solve - t_lno, mu_rows=t_mu - t_solve, total=time.time() - t0))
+    if verbose:
+        print(f"[oracle] {sysd.get('name')} clusters={len(idx)} mu={mu:.12f} e_band={e_band:.10f} "
+              f"times={out['times']}", flush=True)
+    return out
