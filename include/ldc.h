@@ -1,0 +1,158 @@
+/*
+ * ldc.h -- C ABI of the MI355X (gfx950) DC-LNO density-build library (libldc.so).
+ *
+ * Method: O(N) divide-conquer with localized natural orbitals (Ozaki, Fukuda & Jiang,
+ * arXiv 1809.05637).  For every atom i a truncated cluster (all atoms within r_L) is
+ * solved as a small generalized eigenproblem; atoms far from i (the long region) are
+ * represented by a few LNOs each; one chemical potential is shared by all clusters and
+ * atom i's density-matrix rows come from its own cluster.
+ *
+ * Matrix layout shared by every entry point (H, S, previous and output density):
+ *   variable-size block-sparse rows, one block per atom pair, images folded onto the pair
+ *   (Gamma-point supercell).  Row i holds blocks (i, j) for j in the structural overlap
+ *   pattern of i, j ascending, the diagonal block included; the pattern is symmetric.
+ *   Block (i, j) is an M_i x M_j row-major float64 array; blocks are stored back to back
+ *   in row order, so block b starts at the prefix sum of the sizes of blocks 0..b-1.
+ *   H and S must be symmetric (H_ji = H_ij^T) and S positive definite.
+ *
+ * Memory: pointers named d_* are device pointers owned by the caller; the library never
+ * frees or writes caller inputs.  All other pointers are host pointers.  The plan owns
+ * its device workspaces (cluster matrices, LNO table, spectra, tracked projections).
+ *
+ * Ordering: every call is enqueued on the plan's HIP stream (set at creation or with
+ * ldc_plan_set_stream) in call order.  Entry points that return host values (ranks_out,
+ * mu_out, ...) synchronize that stream before returning.  Errors raised inside kernels
+ * (non-positive Cholesky pivot, unconverged eigensolver, ...) are reported by the next
+ * call that synchronizes; ldc_last_error then names the first failing cluster/atom.
+ *
+ * Errors: functions return ldc_status; nothing is thrown across the ABI.  After an error
+ * the plan stays usable for new calls.
+ */
+#ifndef LDC_H
+#define LDC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ldc_plan_s *ldc_plan_t;
+
+typedef enum {
+  LDC_OK = 0,
+  LDC_ERR_ARG = 1,          /* invalid argument (null pointer, bad size, bad pattern) */
+  LDC_ERR_NOT_SPD = 2,      /* a cluster overlap matrix has a non-positive Cholesky pivot */
+  LDC_ERR_EIG_NOCONV = 3,   /* an eigensolver (Lambda or cluster) did not converge */
+  LDC_ERR_MU_BRACKET = 4,   /* electron count outside (0, g * sum of weights) */
+  LDC_ERR_RANK = 5,         /* an LNO basis is rank deficient or a rank is out of range */
+  LDC_ERR_OOM = 6,          /* device memory allocation failed */
+  LDC_ERR_DEVICE = 7,       /* a HIP runtime call failed */
+  LDC_ERR_STATE = 8,        /* call order violated (e.g. ldc_density before ldc_solve) */
+  LDC_ERR_LIMIT = 9         /* a size exceeds a compiled limit (orbitals per atom, members) */
+} ldc_status;
+
+/* Plan options.  Zero-initialised fields take the defaults shown. */
+typedef struct {
+  double r_L;          /* cluster radius (same length unit as the positions); required > 0 */
+  double kappa;        /* buffer fraction of the short region, Sec. III (iii); default 0.3
+                          is used when kappa < 0 */
+  double dist_tol;     /* relative tolerance for sphere membership; 0 -> 1e-9 */
+  double shell_tol;    /* relative tolerance grouping equal distances into shells; 0 -> 1e-8 */
+  int spin_g;          /* spin factor g in N_e = g Tr(D S) (Eq. 13); 0 -> 2 */
+  int workgroups;      /* persistent workgroups per per-cluster kernel; 0 -> 2 x CUs */
+} ldc_options;
+
+/* LNO rank rule (Sec. II.B step (iii), Eq. 22): k_j = clamp(#{Re lambda >= lambda_th},
+ * k_min, k_max); a cut through a complex-conjugate pair of eigenvalues moves past the pair
+ * (or before it when k_max forbids).  fixed_rank (host, n_atoms entries, or NULL): entries
+ * >= 0 replace the count for that atom (the pair rule still applies). */
+typedef struct {
+  double lambda_th;
+  int k_min;
+  int k_max;               /* < 0: M_j */
+  const int *fixed_rank;
+} ldc_rank_rule;
+
+typedef struct {
+  int n_atoms;
+  int n_basis;             /* sum of M_i */
+  int nnzb;                /* number of blocks in the pattern */
+  int max_members;         /* largest cluster (atoms) */
+  int max_dim_pao;         /* largest cluster dimension with PAOs everywhere (plain DC) */
+  int lno_mode;            /* 1 after ldc_lno with a previous density, 0 for plain DC */
+  size_t device_bytes;     /* device memory held by the plan */
+} ldc_plan_info;
+
+/* Build the per-geometry plan (Sec. III (i)-(iv)): cluster of every atom (all atoms within
+ * r_L by minimum-image distance on periodic axes), first neighbours F_i = the pattern row
+ * of i, short region = smallest neighbour shell holding >= N_F + kappa N_S atoms (F_i always
+ * short), long region = the rest.  Uploads the index tables and allocates the workspaces.
+ *   pos: n_atoms x 3 positions; cell: 3 x 3 row-major lattice (only the diagonal is used:
+ *   orthorhombic cells); periodic: 3 flags; n_orb: M_i (1..16); row_ptr (n_atoms+1) and
+ *   col (nnzb): the block pattern; stream: hipStream_t or NULL for the default stream. */
+ldc_status ldc_plan_create(ldc_plan_t *out, int n_atoms, const double *pos, const double *cell,
+                           const int *periodic, const int *n_orb, int nnzb, const int *row_ptr,
+                           const int *col, const ldc_options *opt, void *stream);
+ldc_status ldc_plan_destroy(ldc_plan_t plan);
+ldc_status ldc_plan_set_stream(ldc_plan_t plan, void *stream);
+ldc_status ldc_plan_query(ldc_plan_t plan, ldc_plan_info *info);
+
+/* Host-only planner (no device work, no GPU needed): the members of every atom's cluster,
+ * exactly as ldc_plan_create computes them, in the library's member order.
+ *   member_ptr: host array of n_atoms + 1 offsets; members, is_long: host arrays of capacity
+ *   cap.  Returns LDC_ERR_LIMIT (and the needed size in member_ptr[n_atoms]) if cap is too
+ *   small. */
+ldc_status ldc_regions(int n_atoms, const double *pos, const double *cell, const int *periodic, const int *n_orb,
+                       int nnzb, const int *row_ptr, const int *col, const ldc_options *opt, int cap,
+                       int *member_ptr, int *members, int *is_long);
+
+/* Members of atom's cluster in the library's order (long atoms, short atoms outside F_i,
+ * F_i without i, then i).  members/is_long: host arrays of capacity >= max_members;
+ * n_members, n_long: host scalars.  Any output pointer may be NULL. */
+ldc_status ldc_plan_cluster(ldc_plan_t plan, int atom, int *members, int *is_long, int *n_members,
+                            int *n_long);
+
+/* (b) LNOs (Sec. II.B (i)-(iii)): Lambda_j = sum_k rho_jk S_kj (Eq. 17), its nonsymmetric
+ * eigendecomposition (Eq. 20) via Hessenberg reduction and Francis double-shift QR, the
+ * kept span of eigenvalues ranked by real part (Eq. 22, rank rule above), made
+ * S_jj-orthonormal.  d_Dprev == NULL selects plain DC (no long region) for the next
+ * ldc_solve.  ranks_out (host, n_atoms) may be NULL; when given, the call synchronizes. */
+ldc_status ldc_lno(ldc_plan_t plan, const double *d_S, const double *d_Dprev, const ldc_rank_rule *rule,
+                   int *ranks_out);
+
+/* (a)+(c)+(d): gather every cluster's H^(i), S^(i) with PAO-PAO, PAO-LNO and LNO-LNO
+ * blocks (Eq. 26) and solve H^(i) c = eps S^(i) c (Sec. II.C (ii)-(iii)): Cholesky of S^(i),
+ * reduction to standard form, Householder tridiagonalization and divide-and-conquer on the
+ * tridiagonal matrix.  Keeps eps^(i), the centre weights w_mu = sum_{alpha in i}
+ * c_{i alpha,mu} (S^(i) c_mu)_{i alpha} and what the density rows need inside the plan. */
+ldc_status ldc_solve(ldc_plan_t plan, const double *d_H, const double *d_S);
+
+/* (e): common chemical potential by bisection on N(mu) = g sum_i sum_mu f((eps-mu)/kT) w
+ * (Sec. II.C (iv)) from [min eps - 40 kT, max eps + 40 kT] until hi - lo <= 4e-16 max(1,|mid|)
+ * (at most 200 halvings), then density rows rho_{i alpha, j beta} = sum_mu f c_{i alpha,mu}
+ * c_{j beta,mu} for every j in the pattern row of i (Eq. 24 with Eq. 27) written to d_D_out
+ * (same layout as S).  e_band = g sum_ij tr(D_ij H_ji) needs the H passed to ldc_solve
+ * (still valid on the device); n_e = g Tr(D S).  Synchronizes. */
+ldc_status ldc_density(ldc_plan_t plan, double n_electrons, double kT, double *d_D_out, double *mu_out,
+                       double *e_band_out, double *n_e_out);
+
+/* Density rows at a given chemical potential (no bisection); otherwise as ldc_density. */
+ldc_status ldc_density_at(ldc_plan_t plan, double mu, double kT, double *d_D_out, double *e_band_out,
+                          double *n_e_out);
+
+/* Copy one cluster's spectrum (eps ascending, weights) to host arrays of capacity
+ * >= max_dim_pao; *dim receives its dimension.  Synchronizes. */
+ldc_status ldc_cluster_spectrum(ldc_plan_t plan, int atom, double *eps, double *w, int *dim);
+
+/* Message and failing cluster/atom (-1 if none) of the last error on this plan. */
+const char *ldc_last_error(ldc_plan_t plan, int *cluster_id);
+
+/* Library version string. */
+const char *ldc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LDC_H */

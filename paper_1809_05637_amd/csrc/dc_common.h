@@ -1,0 +1,145 @@
+// Records and the product Z y of the divide-and-conquer tridiagonal eigensolver (shared
+// by the forward pass and the density step).
+#pragma once
+
+#include "dev_common.h"
+
+namespace ldc {
+
+struct DcRec {
+  // per-level base pointers (length n each)
+  double *rc, *rs, *dK, *zt, *tau, *nrm;
+  int *perm, *kpos, *oo, *ra, *rb, *orig, *cnt;
+};
+
+__device__ inline DcRec dc_rec(double *dcd, int *dci, int n, int l) {
+  DcRec r;
+  double *b = dcd + 6LL * n * l;
+  r.rc = b;
+  r.rs = b + n;
+  r.dK = b + 2 * n;
+  r.zt = b + 3 * n;
+  r.tau = b + 4 * n;
+  r.nrm = b + 5 * n;
+  int *ib = dci + 7LL * n * l;
+  r.perm = ib;
+  r.kpos = ib + n;
+  r.oo = ib + 2 * n;
+  r.ra = ib + 3 * n;
+  r.rb = ib + 4 * n;
+  r.orig = ib + 5 * n;
+  r.cnt = ib + 6 * n;
+  return r;
+}
+
+// Workspace of the tridiagonal solver inside a cluster's vector region.
+struct DcWs {
+  double *lam, *G0, *G1, *Ds, *zs, *zK, *rhov, *dcd;
+  int *dci;
+};
+
+__device__ inline DcWs dc_ws(double *cv, int *ci, int nb) {
+  const VecLayout vl = VecLayout::make(nb);
+  DcWs w;
+  w.lam = cv + vl.lam;
+  w.G0 = cv + vl.G0;
+  w.G1 = cv + vl.G1;
+  w.Ds = cv + vl.y0;
+  w.zs = cv + vl.y0 + nb;
+  w.zK = cv + vl.y0 + 2 * nb;
+  w.rhov = cv + vl.y0 + 3 * nb;
+  w.dcd = cv + vl.dc;
+  w.dci = ci;
+  return w;
+}
+
+// y (n rows, ny columns, row stride kMaxOrb) in final eigenvalue order -> Z y in the
+// tridiagonal index order.  ya/yb: ping-pong buffers; the result ends in the returned one.
+__device__ inline double *dc_apply(int n, int ny, DcWs ws, double *ya, double *yb) {
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  int L = 0;
+  while ((1 << L) < n) ++L;
+  for (int l = L - 1; l >= 0; --l) {
+    const int size = 1 << l, span = 2 * size;
+    const DcRec R = dc_rec(ws.dcd, ws.dci, n, l);
+    const int nmerge = (n + span - 1) / span;
+    // T1: output order -> element order
+    for (long long e = tid; e < (long long)n * ny; e += nthr) {
+      const int q = (int)(e / ny), cc = (int)(e % ny);
+      const int lo = q - q % span;
+      if (R.cnt[lo] < 0) {
+        yb[(long long)q * kMaxOrb + cc] = ya[(long long)q * kMaxOrb + cc];
+        continue;
+      }
+      yb[(long long)(lo + R.oo[q]) * kMaxOrb + cc] = ya[(long long)q * kMaxOrb + cc];
+    }
+    __syncthreads();
+    // T2: secular eigenvectors (and deflated identities) -> sorted-pole order
+    for (int q = tid; q < n; q += nthr) {
+      const int lo = q - q % span;
+      const int kp = R.cnt[lo];
+      if (kp < 0) {
+        for (int cc = 0; cc < ny; ++cc) ya[(long long)q * kMaxOrb + cc] = yb[(long long)q * kMaxOrb + cc];
+        continue;
+      }
+      const int j = q - lo;
+      double acc[kMaxOrb];
+      if (j < kp) {
+#pragma unroll
+        for (int cc = 0; cc < kMaxOrb; ++cc) acc[cc] = 0.0;
+        const double *dK = R.dK + lo;
+        const double dj = dK[j], zj = R.zt[lo + j];
+        for (int t = 0; t < kp; ++t) {
+          const double u = zj / (((dj - dK[R.orig[lo + t]]) - R.tau[lo + t]) * R.nrm[lo + t]);
+          const double *y = yb + (long long)(lo + t) * kMaxOrb;
+#pragma unroll
+          for (int cc = 0; cc < kMaxOrb; ++cc)
+            if (cc < ny) acc[cc] += u * y[cc];
+        }
+      } else {
+        const double *y = yb + (long long)(lo + j) * kMaxOrb;
+#pragma unroll
+        for (int cc = 0; cc < kMaxOrb; ++cc) acc[cc] = (cc < ny) ? y[cc] : 0.0;
+      }
+      const int pos = R.kpos[lo + j];
+#pragma unroll
+      for (int cc = 0; cc < kMaxOrb; ++cc)
+        if (cc < ny) ya[(long long)(lo + pos) * kMaxOrb + cc] = acc[cc];
+    }
+    __syncthreads();
+    // T3: deflation rotations, reverse order
+    for (int e = tid; e < nmerge * ny; e += nthr) {
+      const int mi = e / ny, cc = e % ny;
+      const int lo = mi * span;
+      if (R.cnt[lo] < 0) continue;
+      const int nrot = R.cnt[lo + 1];
+      for (int r = nrot - 1; r >= 0; --r) {
+        const long long pa = (long long)(lo + R.ra[lo + r]) * kMaxOrb + cc;
+        const long long pb = (long long)(lo + R.rb[lo + r]) * kMaxOrb + cc;
+        const double c_ = R.rc[lo + r], s_ = R.rs[lo + r];
+        const double a = ya[pa], b = ya[pb];
+        ya[pa] = c_ * a - s_ * b;
+        ya[pb] = s_ * a + c_ * b;
+      }
+    }
+    __syncthreads();
+    // T4: undo the sort
+    for (long long e = tid; e < (long long)n * ny; e += nthr) {
+      const int q = (int)(e / ny), cc = (int)(e % ny);
+      const int lo = q - q % span;
+      if (R.cnt[lo] < 0) {
+        yb[(long long)q * kMaxOrb + cc] = ya[(long long)q * kMaxOrb + cc];
+        continue;
+      }
+      yb[(long long)(lo + R.perm[q]) * kMaxOrb + cc] = ya[(long long)q * kMaxOrb + cc];
+    }
+    __syncthreads();
+    double *t = ya;
+    ya = yb;
+    yb = t;
+  }
+  return ya;
+}
+
+
+}  // namespace ldc

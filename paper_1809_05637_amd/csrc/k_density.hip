@@ -1,0 +1,266 @@
+// Common chemical potential and density rows (Sec. II.C (iv)-(v); Eq. 13, 16, 24, 27).
+//
+// N(mu) = g sum_i sum_mu f((eps_mu - mu)/kT) w_mu is evaluated by a grid of workgroups
+// (one partial per workgroup, fixed cluster assignment) and combined in order by a
+// one-workgroup kernel that also performs the bisection update, so every run takes the
+// same decisions.  Density rows of atom i: with C = L^{-T} Q Z the cluster eigenvectors,
+//   rho^(i)(:, i) = C f C_i^T = L^{-T} Q Z (f o u),  u = Z^T Q^T L^{-1} E_i = C_i^T,
+// so only the tracked u, the merge records (Z y), the stored reflectors (Q r) and the
+// trailing rows of L (P = F_i placed last) are needed.
+#include "dc_common.h"
+
+namespace ldc {
+
+// state layout of Plan::d_mu
+enum { MU_LO = 0, MU_HI, MU_DONE, MU_IT, MU_SUMW, MU_NE, MU_KT, MU_G, MU_MU, MU_BAD };
+
+__global__ void __launch_bounds__(256) mu_partial_kernel(int mode, int n_clusters, const double *__restrict__ vec,
+                                                         const long long *__restrict__ vec_off,
+                                                         const int *__restrict__ dmax, const int *__restrict__ dim,
+                                                         const double *__restrict__ state,
+                                                         double *__restrict__ partial) {
+  __shared__ double red[8];
+  if (mode == 1 && state[MU_DONE] != 0.0) return;
+  const double kT = state[MU_KT];
+  const double mid = 0.5 * (state[MU_LO] + state[MU_HI]);
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  if (mode == 0) {
+    a0 = 1e300;
+    a1 = -1e300;
+  }
+  for (int c = blockIdx.x; c < n_clusters; c += gridDim.x) {
+    const VecLayout vl = VecLayout::make(dmax[c]);
+    const double *lam = vec + vec_off[c] + vl.lam;
+    const double *w = vec + vec_off[c] + vl.w;
+    const int n = dim[c];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      if (mode == 0) {
+        a0 = fmin(a0, lam[i]);
+        a1 = fmax(a1, lam[i]);
+        a2 += w[i];
+      } else {
+        a2 += fermi((lam[i] - mid) / kT) * w[i];
+      }
+    }
+  }
+  const double s = block_sum(a2, red);
+  double mn = 0.0, mx = 0.0;
+  if (mode == 0) {
+    mn = -block_max(-a0, red);
+    mx = block_max(a1, red);
+  }
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x * 4 + 0] = mn;
+    partial[blockIdx.x * 4 + 1] = mx;
+    partial[blockIdx.x * 4 + 2] = s;
+  }
+}
+
+__global__ void mu_finalize_kernel(int mode, int nparts, double *__restrict__ state, const double *__restrict__ partial,
+                                   DevStatus *st) {
+  if (threadIdx.x != 0) return;
+  if (mode == 1 && state[MU_DONE] != 0.0) return;
+  double s = 0.0, mn = 1e300, mx = -1e300;
+  for (int b = 0; b < nparts; ++b) {
+    s += partial[b * 4 + 2];
+    mn = fmin(mn, partial[b * 4 + 0]);
+    mx = fmax(mx, partial[b * 4 + 1]);
+  }
+  const double kT = state[MU_KT], g = state[MU_G], ne = state[MU_NE];
+  double lo, hi;
+  if (mode == 0) {
+    lo = mn - 40.0 * kT;
+    hi = mx + 40.0 * kT;
+    state[MU_SUMW] = s;
+    state[MU_IT] = 0.0;
+    state[MU_DONE] = 0.0;
+    state[MU_BAD] = 0.0;
+    if (!(ne > 0.0 && ne < g * s)) {
+      state[MU_BAD] = 1.0;
+      state[MU_DONE] = 1.0;
+      report(st, LDC_ERR_MU_BRACKET, -1);
+    }
+  } else {
+    lo = state[MU_LO];
+    hi = state[MU_HI];
+    const double mid = 0.5 * (lo + hi);
+    if (g * s < ne) lo = mid;
+    else hi = mid;
+    state[MU_IT] += 1.0;
+  }
+  state[MU_LO] = lo;
+  state[MU_HI] = hi;
+  const double mid = 0.5 * (lo + hi);
+  state[MU_MU] = mid;
+  if (hi - lo <= 4e-16 * fmax(1.0, fabs(mid)) || state[MU_IT] >= 200.0) state[MU_DONE] = 1.0;
+}
+
+// Density rows of every cluster at mu = state[MU_MU].
+__global__ void __launch_bounds__(256) density_kernel(
+    int n_clusters, const int *__restrict__ order, double *__restrict__ mat, const long long *__restrict__ mat_off,
+    double *__restrict__ vec, const long long *__restrict__ vec_off, int *__restrict__ ivec,
+    const long long *__restrict__ ivec_off, const int *__restrict__ dmax, const int *__restrict__ dim,
+    const int *__restrict__ n_orb, const int *__restrict__ p_rows, const int *__restrict__ mem_ptr,
+    const int *__restrict__ mem_atom, const int *__restrict__ fna_ptr, const int *__restrict__ fna_blk,
+    const long long *__restrict__ blk_off, const double *__restrict__ state, const double *__restrict__ H,
+    const double *__restrict__ S, double *__restrict__ Dout, double *__restrict__ partial) {
+  __shared__ double red[16 * 17];
+  __shared__ double sred[8];
+  __shared__ int foff[kMaxMembers + 1];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const double mu = state[MU_MU], kT = state[MU_KT];
+  for (int s = blockIdx.x; s < n_clusters; s += gridDim.x) {
+    const int c = order[s];
+    const int n = dim[c], ld = n;
+    const int M = n_orb[c];
+    const int p = p_rows[c];
+    double *cv = vec + vec_off[c];
+    const VecLayout vl = VecLayout::make(dmax[c]);
+    DcWs ws;
+    ws.lam = cv + vl.lam;
+    ws.G0 = cv + vl.G0;
+    ws.G1 = cv + vl.G1;
+    ws.Ds = ws.zs = ws.zK = ws.rhov = nullptr;
+    ws.dcd = cv + vl.dc;
+    ws.dci = ivec + ivec_off[c];
+    const double *A = mat + mat_off[c];
+    const double *L = A + (long long)dmax[c] * dmax[c];
+    const double *tt = cv + vl.tau;
+    double *ya = cv + vl.y0, *yb = cv + vl.y1;
+    __syncthreads();
+    // y = f o u
+    for (long long e = tid; e < (long long)n * M; e += nthr) {
+      const int i = (int)(e / M), a = (int)(e % M);
+      ya[(long long)i * kMaxOrb + a] = fermi((ws.lam[i] - mu) / kT) * ws.G0[(long long)i * kTrack + a];
+    }
+    __syncthreads();
+    double *r = dc_apply(n, M, ws, ya, yb);
+    // r <- Q r = H_0 (H_1 (... H_{n-2} r))
+    for (int k = n - 2; k >= 0; --k) {
+      const double tau = tt[k];
+      if (tau == 0.0) continue;
+      const double *vk = A + (long long)k * ld;
+      double part[kMaxOrb];
+#pragma unroll
+      for (int a = 0; a < kMaxOrb; ++a) part[a] = 0.0;
+      for (int i = k + 1 + tid; i < n; i += nthr) {
+        const double vi = (i == k + 1) ? 1.0 : vk[i];
+        const double *ri = r + (long long)i * kMaxOrb;
+#pragma unroll
+        for (int a = 0; a < kMaxOrb; ++a)
+          if (a < M) part[a] += vi * ri[a];
+      }
+#pragma unroll
+      for (int a = 0; a < kMaxOrb; ++a) {
+        if (a < M) {
+          const double t = wave_sum(part[a]);
+          if ((tid & 63) == 0) red[(tid >> 6) * 16 + a] = t;
+        }
+      }
+      __syncthreads();
+      double sa[kMaxOrb];
+#pragma unroll
+      for (int a = 0; a < kMaxOrb; ++a) {
+        double acc = 0.0;
+        if (a < M)
+          for (int w = 0; w < (nthr >> 6); ++w) acc += red[w * 16 + a];
+        sa[a] = tau * acc;
+      }
+      for (int i = k + 1 + tid; i < n; i += nthr) {
+        const double vi = (i == k + 1) ? 1.0 : vk[i];
+        double *ri = r + (long long)i * kMaxOrb;
+#pragma unroll
+        for (int a = 0; a < kMaxOrb; ++a)
+          if (a < M) ri[a] -= sa[a] * vi;
+      }
+      __syncthreads();
+    }
+    // x_P = L_PP^{-T} r_P (P = the last p rows), backward substitution
+    const int b0 = n - p;
+    for (int g = n - 1; g >= b0; --g) {
+      const int a = tid & 15, part = tid >> 4;
+      double acc = 0.0;
+      if (a < M)
+        for (int t = g + 1 + part; t < n; t += 16) acc += L[(long long)g * ld + t] * r[(long long)t * kMaxOrb + a];
+      red[part * 17 + a] = acc;
+      __syncthreads();
+      if (tid < M) {
+        double sacc = 0.0;
+        for (int q = 0; q < 16; ++q) sacc += red[q * 17 + tid];
+        r[(long long)g * kMaxOrb + tid] = (r[(long long)g * kMaxOrb + tid] - sacc) / L[(long long)g * ld + g];
+      }
+      __syncthreads();
+    }
+    // scatter D(i, j) for j in F_i (members F \ {i} then i, last in the member list)
+    const int fb = fna_ptr[c], nf = fna_ptr[c + 1] - fb;
+    const int mend = mem_ptr[c + 1];
+    if (tid == 0) {
+      foff[0] = 0;
+      for (int q = 0; q < nf; ++q) foff[q + 1] = foff[q] + n_orb[mem_atom[mend - nf + q]];
+    }
+    __syncthreads();
+    double eh = 0.0, es = 0.0;
+    for (int e = tid; e < p * M; e += nthr) {
+      const int prow = e / M, a = e % M;
+      int q = 0;
+      while (foff[q + 1] <= prow) ++q;
+      const int j = mem_atom[mend - nf + q];
+      const int mj = n_orb[j];
+      const int be = prow - foff[q];
+      const long long o = blk_off[fna_blk[fb + q]] + (long long)a * mj + be;
+      const double dv = r[(long long)(b0 + prow) * kMaxOrb + a];
+      Dout[o] = dv;
+      eh += dv * H[o];
+      es += dv * S[o];
+    }
+    eh = block_sum(eh, sred);
+    es = block_sum(es, sred);
+    if (tid == 0) {
+      partial[2 * c] = eh;
+      partial[2 * c + 1] = es;
+    }
+  }
+}
+
+__global__ void sum_pairs_kernel(int n, const double *__restrict__ partial, double *__restrict__ out) {
+  __shared__ double red[8];
+  double a = 0.0, b = 0.0;
+  // fixed order: thread t sums clusters t, t + 256, ...; then a fixed tree
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    a += partial[2 * c];
+    b += partial[2 * c + 1];
+  }
+  a = block_sum(a, red);
+  b = block_sum(b, red);
+  if (threadIdx.x == 0) {
+    out[0] = a;
+    out[1] = b;
+  }
+}
+
+void launch_mu_init(Plan &p, double kT) {
+  (void)kT;
+  hipLaunchKernelGGL(mu_partial_kernel, dim3(p.workgroups), dim3(kWG), 0, p.stream, 0, p.n_atoms, p.d_vec,
+                     p.d_vec_off, p.d_dmax, p.d_dim, p.d_mu, p.d_partial);
+  hipLaunchKernelGGL(mu_finalize_kernel, dim3(1), dim3(64), 0, p.stream, 0, p.workgroups, p.d_mu, p.d_partial,
+                     p.d_status);
+}
+
+void launch_mu_step(Plan &p, double, double, double) {
+  hipLaunchKernelGGL(mu_partial_kernel, dim3(p.workgroups), dim3(kWG), 0, p.stream, 1, p.n_atoms, p.d_vec,
+                     p.d_vec_off, p.d_dmax, p.d_dim, p.d_mu, p.d_partial);
+  hipLaunchKernelGGL(mu_finalize_kernel, dim3(1), dim3(64), 0, p.stream, 1, p.workgroups, p.d_mu, p.d_partial,
+                     p.d_status);
+}
+
+void launch_density(Plan &p, double, double *d_D, const double *d_H, const double *d_S, double) {
+  double *cl_partial = p.d_partial + 4 * p.workgroups;
+  hipLaunchKernelGGL(density_kernel, dim3(p.workgroups), dim3(kWG), 0, p.stream, p.n_atoms, p.d_order, p.d_mat,
+                     p.d_mat_off, p.d_vec, p.d_vec_off, p.d_ivec, p.d_ivec_off, p.d_dmax, p.d_dim, p.d_n_orb,
+                     p.d_p_rows, p.d_mem_ptr, p.d_mem_atom, p.d_fna_ptr, p.d_fna_blk, p.d_blk_off, p.d_mu, d_H, d_S,
+                     d_D, cl_partial);
+  hipLaunchKernelGGL(sum_pairs_kernel, dim3(1), dim3(kWG), 0, p.stream, p.n_atoms, cl_partial,
+                     p.d_mu + 16);
+}
+
+}  // namespace ldc

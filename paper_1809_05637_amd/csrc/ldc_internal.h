@@ -1,0 +1,147 @@
+// Internal declarations shared by the host code and the kernel launchers of libldc.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ldc.h"
+
+namespace ldc {
+
+constexpr int kMaxOrb = 16;        // orbitals per atom (compiled limit)
+constexpr int kMaxMembers = 1024;  // atoms per cluster (compiled limit)
+constexpr int kWG = 256;           // threads per workgroup of the per-cluster kernels
+constexpr int kTrack = 2 * kMaxOrb + 2;  // tracked columns in the tridiagonal solver
+
+// Device status word: [0] first error code, [1] failing cluster/atom.
+struct DevStatus {
+  int code;
+  int where;
+};
+
+// Per-cluster layout of the tridiagonal-solver records (all offsets in elements).
+// n = dimension bound of the cluster (plain-DC dimension), L = number of merge levels.
+struct DcLayout {
+  // doubles per level: rot_c, rot_s, dK, zt, tau, nrm  -> 6 n
+  // ints per level:    perm, kpos, oo, rot_a, rot_b, orig, cnt -> 7 n
+  static int levels(int n) {
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return l;
+  }
+};
+
+struct Plan {
+  int n_atoms = 0, nnzb = 0, n_basis = 0, mmax = 0;
+  ldc_options opt{};
+  hipStream_t stream = nullptr;
+  int n_cu = 0;
+  int workgroups = 0;
+
+  // host copies of the geometry and pattern
+  std::vector<int> n_orb, row_ptr, col;
+  std::vector<long long> blk_off;
+
+  // regions, in the library's member order: long, short \ F, F \ {i}, i
+  std::vector<int> mem_ptr, mem_atom, mem_long;
+  std::vector<int> pair_ptr, pair_ab, pair_blk;  // gather list: (a | b << 16), block index
+  std::vector<int> fna_ptr, fna_blk;             // P rows: block index of (i, j) per F member
+  std::vector<int> p_rows;                       // rows of the P block (sum of M over F_i)
+  std::vector<int> dmax;                         // plain-DC dimension (workspace bound)
+  std::vector<int> order;                        // processing order, largest first
+  int max_members = 0, max_dim = 0;
+
+  // device tables
+  int *d_n_orb = nullptr, *d_row_ptr = nullptr, *d_col = nullptr;
+  long long *d_blk_off = nullptr;
+  int *d_mem_ptr = nullptr, *d_mem_atom = nullptr, *d_mem_long = nullptr;
+  int *d_pair_ptr = nullptr, *d_pair_ab = nullptr, *d_pair_blk = nullptr;
+  int *d_fna_ptr = nullptr, *d_fna_blk = nullptr, *d_p_rows = nullptr;
+  int *d_dmax = nullptr, *d_order = nullptr;
+
+  // per-cluster workspaces
+  long long *d_mat_off = nullptr;   // H slot at off, S slot at off + dmax^2
+  long long *d_vec_off = nullptr;   // double vectors
+  long long *d_ivec_off = nullptr;  // int vectors
+  double *d_mat = nullptr, *d_vec = nullptr;
+  int *d_ivec = nullptr;
+  int *d_dim = nullptr;             // current reduced dimension per cluster
+
+  // LNO table
+  int lno_mode = 0;
+  int *d_rank = nullptr;
+  double *d_U = nullptr;            // n_atoms x kMaxOrb^2, U_j column-major M_j x k_j
+  double *d_lambda = nullptr;       // n_atoms x kMaxOrb^2 scratch (Lambda matrices)
+  int *d_fixed = nullptr;           // n_atoms fixed ranks (-1: rule)
+
+  // chemical potential state and reductions
+  double *d_mu = nullptr;           // [lo, hi, mid, done, n_at_mid, bracket checks...]
+  double *d_partial = nullptr;      // per-workgroup partial sums
+  int *d_counter = nullptr;
+  DevStatus *d_status = nullptr;
+
+  const double *last_H = nullptr, *last_S = nullptr;
+  int solved = 0;
+  size_t device_bytes = 0;
+  std::string msg;
+  int err_where = -1;
+};
+
+// vector workspace offsets inside a cluster's double region (n = dimension bound)
+struct VecLayout {
+  long long d, e, tau, lam, w, G0, G1, u, y0, y1, dc;
+  __host__ __device__ static VecLayout make(int n) {
+    VecLayout v;
+    long long o = 0;
+    v.d = o; o += n;
+    v.e = o; o += n;
+    v.tau = o; o += n;
+    v.lam = o; o += n;
+    v.w = o; o += n;
+    v.G0 = o; o += (long long)n * kTrack;
+    v.G1 = o; o += (long long)n * kTrack;
+    v.u = o; o += (long long)n * kMaxOrb;
+    v.y0 = o; o += (long long)n * kMaxOrb;
+    v.y1 = o; o += (long long)n * kMaxOrb;
+    v.dc = o;
+    return v;
+  }
+  __host__ __device__ static long long total(int n) {
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return make(n).dc + 6LL * n * (l > 0 ? l : 1);
+  }
+};
+
+struct IvecLayout {
+  __host__ __device__ static long long total(int n) {
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return 7LL * n * (l > 0 ? l : 1);
+  }
+};
+
+// host planner
+ldc_status build_regions(Plan &p, const double *pos, const double *cell, const int *periodic);
+
+// kernel launchers (each enqueues on p.stream)
+void launch_lambda(Plan &p, const double *d_S, const double *d_D);
+void launch_lno_eig(Plan &p, const double *d_S, double lambda_th, int k_min, int k_max);
+void launch_gather(Plan &p, const double *d_H, const double *d_S);
+void launch_potrf(Plan &p);
+void launch_sygst(Plan &p);
+void launch_sytrd(Plan &p);
+void launch_stedc(Plan &p);
+void launch_mu_init(Plan &p, double kT);
+void launch_mu_step(Plan &p, double n_electrons, double kT, double g);
+void launch_mu_fixed(Plan &p, double mu);
+void launch_density(Plan &p, double kT, double *d_D, const double *d_H, const double *d_S, double g);
+
+}  // namespace ldc
+
+struct ldc_plan_s {
+  ldc::Plan p;
+};
