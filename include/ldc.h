@@ -145,6 +145,20 @@ ldc_status ldc_density_at(ldc_plan_t plan, double mu, double kT, double *d_D_out
  * >= max_dim_pao; *dim receives its dimension.  Synchronizes. */
 ldc_status ldc_cluster_spectrum(ldc_plan_t plan, int atom, double *eps, double *w, int *dim);
 
+/* Reduced dimension of every cluster after the last ldc_solve (host array, n_atoms). */
+ldc_status ldc_cluster_dims(ldc_plan_t plan, int *dims);
+
+/* Stage timing with HIP events recorded on the plan's stream around each stage.
+ * Stages: 0 Lambda, 1 LNO eigensolve, 2 gather, 3 Cholesky, 4 standard form,
+ * 5 tridiagonalization, 6 tridiagonal eigensolve, 7 chemical potential, 8 density rows.
+ * ldc_profile(plan, 1) enables timing and clears the accumulated times; 0 disables it.
+ * ldc_stage_times fills ms (LDC_NUM_STAGES entries, summed over builds) and *builds (the
+ * number of completed ldc_density calls while enabled).  Synchronizes. */
+#define LDC_NUM_STAGES 9
+ldc_status ldc_profile(ldc_plan_t plan, int enable);
+ldc_status ldc_stage_times(ldc_plan_t plan, double *ms, int *builds);
+const char *ldc_stage_name(int stage);
+
 /* Message and failing cluster/atom (-1 if none) of the last error on this plan. */
 const char *ldc_last_error(ldc_plan_t plan, int *cluster_id);
 

@@ -24,6 +24,8 @@ _LIB = None
 STATUS = {0: "LDC_OK", 1: "LDC_ERR_ARG", 2: "LDC_ERR_NOT_SPD", 3: "LDC_ERR_EIG_NOCONV", 4: "LDC_ERR_MU_BRACKET",
           5: "LDC_ERR_RANK", 6: "LDC_ERR_OOM", 7: "LDC_ERR_DEVICE", 8: "LDC_ERR_STATE", 9: "LDC_ERR_LIMIT"}
 
+NUM_STAGES = 9
+
 c_int, c_double, c_void_p, c_size_t = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
 P_int = ctypes.POINTER(ctypes.c_int)
 P_double = ctypes.POINTER(ctypes.c_double)
@@ -79,6 +81,10 @@ def load():
         "ldc_density_at": (c_int, [c_void_p, c_double, c_double, c_void_p, P_double, P_double]),
         "ldc_cluster_spectrum": (c_int, [c_void_p, c_int, P_double, P_double, P_int]),
         "ldc_last_error": (ctypes.c_char_p, [c_void_p, P_int]),
+        "ldc_cluster_dims": (c_int, [c_void_p, P_int]),
+        "ldc_profile": (c_int, [c_void_p, c_int]),
+        "ldc_stage_times": (c_int, [c_void_p, P_double, P_int]),
+        "ldc_stage_name": (ctypes.c_char_p, [c_int]),
         "ldc_version": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -203,6 +209,23 @@ class Plan:
         self._check(self._lib.ldc_density_at(self._h, float(mu), float(kT), _ptr(D_out), ctypes.byref(eb),
                                              ctypes.byref(ne)))
         return eb.value, ne.value
+
+    def cluster_dims(self):
+        """Reduced dimension of every cluster after the last solve."""
+        d = np.zeros(self.n_atoms, dtype=np.int32)
+        self._check(self._lib.ldc_cluster_dims(self._h, d.ctypes.data_as(P_int)))
+        return d
+
+    def profile(self, enable=True):
+        """Enable (and reset) or disable per-stage HIP-event timing."""
+        self._check(self._lib.ldc_profile(self._h, 1 if enable else 0))
+
+    def stage_times(self):
+        """({stage name: ms summed over builds}, builds) since profiling was enabled."""
+        ms = np.zeros(NUM_STAGES)
+        b = c_int()
+        self._check(self._lib.ldc_stage_times(self._h, ms.ctypes.data_as(P_double), ctypes.byref(b)))
+        return {self._lib.ldc_stage_name(i).decode(): float(ms[i]) for i in range(NUM_STAGES)}, b.value
 
     def cluster_spectrum(self, atom):
         """(eps, w) of one cluster, copied to the host."""

@@ -53,6 +53,10 @@ void free_all(Plan &p) {
                   p.d_counter,  p.d_status};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
+  for (int s = 0; s < LDC_NUM_STAGES; ++s) {
+    if (p.ev_begin[s]) (void)hipEventDestroy(p.ev_begin[s]);
+    if (p.ev_end[s]) (void)hipEventDestroy(p.ev_end[s]);
+  }
 }
 
 // Reads and clears the device status word (synchronizes the stream).
@@ -76,9 +80,75 @@ ldc_status check_status(Plan &p) {
   return LDC_OK;
 }
 
+const char *kStageNames[LDC_NUM_STAGES] = {"lambda", "lno_eig", "gather", "potrf", "sygst",
+                                           "sytrd", "stedc", "mu", "density"};
+
+inline void stage_begin(Plan &p, int s) {
+  if (p.profile) (void)hipEventRecord(p.ev_begin[s], p.stream);
+}
+inline void stage_end(Plan &p, int s) {
+  if (p.profile) {
+    (void)hipEventRecord(p.ev_end[s], p.stream);
+    p.ev_pending[s] = 1;
+  }
+}
+// Adds the elapsed times of completed stages (events must have completed).
+void collect_stages(Plan &p) {
+  if (!p.profile) return;
+  for (int s = 0; s < LDC_NUM_STAGES; ++s) {
+    if (!p.ev_pending[s]) continue;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.ev_begin[s], p.ev_end[s]) == hipSuccess) p.stage_ms[s] += ms;
+    else (void)hipGetLastError();
+    p.ev_pending[s] = 0;
+  }
+}
+
 }  // namespace
 
 extern "C" {
+
+const char *ldc_stage_name(int stage) {
+  return (stage >= 0 && stage < LDC_NUM_STAGES) ? kStageNames[stage] : "unknown";
+}
+
+ldc_status ldc_profile(ldc_plan_t plan, int enable) {
+  if (!plan) return LDC_ERR_ARG;
+  Plan &p = plan->p;
+  HIPCHK(hipStreamSynchronize(p.stream));
+  if (enable && !p.ev_begin[0]) {
+    for (int s = 0; s < LDC_NUM_STAGES; ++s) {
+      HIPCHK(hipEventCreate(&p.ev_begin[s]));
+      HIPCHK(hipEventCreate(&p.ev_end[s]));
+    }
+  }
+  p.profile = enable ? 1 : 0;
+  for (int s = 0; s < LDC_NUM_STAGES; ++s) {
+    p.stage_ms[s] = 0.0;
+    p.ev_pending[s] = 0;
+  }
+  p.prof_builds = 0;
+  return LDC_OK;
+}
+
+ldc_status ldc_stage_times(ldc_plan_t plan, double *ms, int *builds) {
+  if (!plan || !ms) return LDC_ERR_ARG;
+  Plan &p = plan->p;
+  HIPCHK(hipStreamSynchronize(p.stream));
+  collect_stages(p);
+  for (int s = 0; s < LDC_NUM_STAGES; ++s) ms[s] = p.stage_ms[s];
+  if (builds) *builds = p.prof_builds;
+  return LDC_OK;
+}
+
+ldc_status ldc_cluster_dims(ldc_plan_t plan, int *dims) {
+  if (!plan || !dims) return LDC_ERR_ARG;
+  Plan &p = plan->p;
+  if (!p.solved) return LDC_ERR_STATE;
+  HIPCHK(hipStreamSynchronize(p.stream));
+  HIPCHK(hipMemcpy(dims, p.d_dim, sizeof(int) * p.n_atoms, hipMemcpyDeviceToHost));
+  return LDC_OK;
+}
 
 const char *ldc_version(void) { return kVersion; }
 
@@ -153,10 +223,10 @@ ldc_status ldc_plan_create(ldc_plan_t *out, int n_atoms, const double *pos, cons
     delete h;
     return LDC_ERR_DEVICE;
   }
-  if ((size_t)p.max_dim * (4 + ldc::kWG / 64) * sizeof(double) > 64 * 1024) {
+  if ((size_t)p.max_dim * (2 + ldc::kWG / 64) * sizeof(double) + 20 * 1024 > 64 * 1024) {
     free_all(p);
     delete h;
-    return LDC_ERR_LIMIT;  // tridiagonalization keeps 8 length-n vectors in LDS
+    return LDC_ERR_LIMIT;  // tridiagonalization keeps 6 length-n vectors in LDS
   }
   p.workgroups = opt->workgroups > 0 ? opt->workgroups : 2 * p.n_cu;
   p.workgroups = std::max(1, std::min(p.workgroups, n_atoms));
@@ -311,8 +381,12 @@ ldc_status ldc_lno(ldc_plan_t plan, const double *d_S, const double *d_Dprev, co
   if (rule->fixed_rank)
     for (int i = 0; i < p.n_atoms; ++i) fixed[i] = rule->fixed_rank[i];
   HIPCHK(hipMemcpyAsync(p.d_fixed, fixed.data(), sizeof(int) * p.n_atoms, hipMemcpyHostToDevice, p.stream));
+  stage_begin(p, 0);
   ldc::launch_lambda(p, d_S, d_Dprev);
+  stage_end(p, 0);
+  stage_begin(p, 1);
   ldc::launch_lno_eig(p, d_S, rule->lambda_th, rule->k_min, rule->k_max);
+  stage_end(p, 1);
   HIPCHK(hipGetLastError());
   // the host copy above must not outlive this call: wait for it
   HIPCHK(hipStreamSynchronize(p.stream));
@@ -328,11 +402,21 @@ ldc_status ldc_lno(ldc_plan_t plan, const double *d_S, const double *d_Dprev, co
 ldc_status ldc_solve(ldc_plan_t plan, const double *d_H, const double *d_S) {
   if (!plan || !d_H || !d_S) return LDC_ERR_ARG;
   Plan &p = plan->p;
+  stage_begin(p, 2);
   ldc::launch_gather(p, d_H, d_S);
+  stage_end(p, 2);
+  stage_begin(p, 3);
   ldc::launch_potrf(p);
+  stage_end(p, 3);
+  stage_begin(p, 4);
   ldc::launch_sygst(p);
+  stage_end(p, 4);
+  stage_begin(p, 5);
   ldc::launch_sytrd(p);
+  stage_end(p, 5);
+  stage_begin(p, 6);
   ldc::launch_stedc(p);
+  stage_end(p, 6);
   HIPCHK(hipGetLastError());
   p.last_H = d_H;
   p.last_S = d_S;
@@ -365,6 +449,7 @@ ldc_status ldc_density(ldc_plan_t plan, double n_electrons, double kT, double *d
   st[6] = kT;
   st[7] = g;
   HIPCHK(hipMemcpyAsync(p.d_mu, st, sizeof(st), hipMemcpyHostToDevice, p.stream));
+  stage_begin(p, 7);
   ldc::launch_mu_init(p, kT);
   int iters = 0;
   while (true) {
@@ -376,9 +461,17 @@ ldc_status ldc_density(ldc_plan_t plan, double n_electrons, double kT, double *d
     HIPCHK(hipStreamSynchronize(p.stream));
     if (chk[2] != 0.0 || iters >= 256) break;
   }
+  stage_end(p, 7);
+  stage_begin(p, 8);
   ldc::launch_density(p, kT, d_D_out, p.last_H, p.last_S, g);
+  stage_end(p, 8);
   HIPCHK(hipGetLastError());
-  return finish_density(p, g, mu_out, e_band_out, n_e_out);
+  ldc_status s = finish_density(p, g, mu_out, e_band_out, n_e_out);
+  if (p.profile) {
+    collect_stages(p);
+    p.prof_builds += 1;
+  }
+  return s;
 }
 
 ldc_status ldc_density_at(ldc_plan_t plan, double mu, double kT, double *d_D_out, double *e_band_out,

@@ -8,6 +8,7 @@
 // so only the tracked u, the merge records (Z y), the stored reflectors (Q r) and the
 // trailing rows of L (P = F_i placed last) are needed.
 #include "dc_common.h"
+#include "wg_qapply.h"
 
 namespace ldc {
 
@@ -107,6 +108,7 @@ __global__ void __launch_bounds__(256) density_kernel(
   __shared__ double red[16 * 17];
   __shared__ double sred[8];
   __shared__ int foff[kMaxMembers + 1];
+  __shared__ double qlds[kQapplyLds];
   const int tid = threadIdx.x, nthr = blockDim.x;
   const double mu = state[MU_MU], kT = state[MU_KT];
   for (int s = blockIdx.x; s < n_clusters; s += gridDim.x) {
@@ -135,46 +137,8 @@ __global__ void __launch_bounds__(256) density_kernel(
     }
     __syncthreads();
     double *r = dc_apply(n, M, ws, ya, yb);
-    // r <- Q r = H_0 (H_1 (... H_{n-2} r))
-    for (int k = n - 2; k >= 0; --k) {
-      const double tau = tt[k];
-      if (tau == 0.0) continue;
-      const double *vk = A + (long long)k * ld;
-      double part[kMaxOrb];
-#pragma unroll
-      for (int a = 0; a < kMaxOrb; ++a) part[a] = 0.0;
-      for (int i = k + 1 + tid; i < n; i += nthr) {
-        const double vi = (i == k + 1) ? 1.0 : vk[i];
-        const double *ri = r + (long long)i * kMaxOrb;
-#pragma unroll
-        for (int a = 0; a < kMaxOrb; ++a)
-          if (a < M) part[a] += vi * ri[a];
-      }
-#pragma unroll
-      for (int a = 0; a < kMaxOrb; ++a) {
-        if (a < M) {
-          const double t = wave_sum(part[a]);
-          if ((tid & 63) == 0) red[(tid >> 6) * 16 + a] = t;
-        }
-      }
-      __syncthreads();
-      double sa[kMaxOrb];
-#pragma unroll
-      for (int a = 0; a < kMaxOrb; ++a) {
-        double acc = 0.0;
-        if (a < M)
-          for (int w = 0; w < (nthr >> 6); ++w) acc += red[w * 16 + a];
-        sa[a] = tau * acc;
-      }
-      for (int i = k + 1 + tid; i < n; i += nthr) {
-        const double vi = (i == k + 1) ? 1.0 : vk[i];
-        double *ri = r + (long long)i * kMaxOrb;
-#pragma unroll
-        for (int a = 0; a < kMaxOrb; ++a)
-          if (a < M) ri[a] -= sa[a] * vi;
-      }
-      __syncthreads();
-    }
+    // r <- Q r (compact WY panels, T factors stored by the tridiagonalization)
+    wg_apply_q(A, ld, n, tt, cv + vl.u, false, r, kMaxOrb, M, false, qlds);
     // x_P = L_PP^{-T} r_P (P = the last p rows), backward substitution
     const int b0 = n - p;
     for (int g = n - 1; g >= b0; --g) {

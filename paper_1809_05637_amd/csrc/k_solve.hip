@@ -3,6 +3,9 @@
 // tridiagonalization.  One 256-thread workgroup per cluster; workgroups walk the clusters
 // largest-first with a fixed stride (persistent launch, deterministic assignment).
 #include "wg_blas.h"
+#include "wg_qapply.h"
+
+#include <algorithm>
 
 namespace ldc {
 
@@ -238,22 +241,84 @@ __global__ void __launch_bounds__(256) sygst_kernel(int n_clusters, const int *_
 }
 
 // ---------------------------------------------------------------------------------------
-// Householder tridiagonalization of A (lower triangle, column-major, ld = n):
+// Partial products of y = A v for the symmetric m x m matrix held in the lower triangle of
+// A (column-major, leading dimension lda), streamed by whole columns.  Wave w takes the
+// column groups {c, c + nw, c + 2 nw, c + 3 nw}, c = w + 4 nw g: rows from c upward are read
+// in 64-row chunks (SU chunks x 4 columns in flight per lane); for every row the four
+// columns' contributions to y(r) are summed in a register and added to the wave's private
+// partial row my (LDS, no workgroup barrier needed), and each column's stored part feeds
+// y(c) through one wave reduction.  The caller sums the nw partial rows.
+constexpr int SU = 4;
+constexpr int SC = 4;
+__device__ void wg_symv_lower_partial(const double *__restrict__ A, int lda, int m, const double *v, double *my) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int r = lane; r < m; r += 64) my[r] = 0.0;
+  for (int c0 = wave; c0 < m; c0 += SC * nw) {
+    int cj[SC];
+    double vc[SC], acc[SC];
+    const double *col[SC];
+#pragma unroll
+    for (int j = 0; j < SC; ++j) {
+      cj[j] = c0 + j * nw;
+      vc[j] = cj[j] < m ? v[cj[j]] : 0.0;
+      acc[j] = 0.0;
+      col[j] = A + (long long)(cj[j] < m ? cj[j] : c0) * lda;
+    }
+    for (int r0 = c0; r0 < m; r0 += 64 * SU) {
+      double a[SU][SC];
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int r = r0 + u * 64 + lane;
+#pragma unroll
+        for (int j = 0; j < SC; ++j) a[u][j] = (r < m && r >= cj[j]) ? col[j][r] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int r = r0 + u * 64 + lane;
+        if (r < m) {
+          const double vr = v[r];
+          double t = 0.0;
+#pragma unroll
+          for (int j = 0; j < SC; ++j) {
+            t += a[u][j] * vc[j];
+            if (r > cj[j]) acc[j] += a[u][j] * vr;
+          }
+          my[r] += t;
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < SC; ++j) {
+      const double t = wave_sum(acc[j]);
+      if (lane == 0 && cj[j] < m) my[cj[j]] += t;
+    }
+  }
+}
+
+// Householder tridiagonalization of A (lower triangle, column-major, ld = n), blocked:
 // Q^T A Q = T with Q = H_0 H_1 ... H_{n-2}, H_k = I - tau_k v_k v_k^T, v_k(k+1) = 1 and
-// v_k(k+2:) stored in A(k+2:, k).  One pass per column: the trailing lower triangle gets the
-// previous rank-2 update and feeds the product with the new reflector in the same sweep.
-// The tracked columns X = [L^{-1} E_i | L^T E_i] (E_i: the centre atom's unit columns)
-// are initialised here and replaced by Q^T X, row-major with stride kTrack.
+// v_k(k+2:) stored in A(k+2:, k).  Panels of NBT columns: inside a panel each column takes
+// the updates of the panel's earlier reflectors from the n x NBT blocks V, W (row-major, so
+// a row's coefficients are one contiguous load), its reflector is generated, and
+// w = tau (A v - V (W^T v) - W (V^T v)) - (tau/2)(w^T v) v uses the trailing matrix as left
+// by the previous panel; after the panel the trailing matrix gets A -= V W^T + W V^T (two
+// tiled MFMA GEMMs on its lower triangle).
+// The tracked columns X = [L^{-1} E_i | L^T E_i] (E_i: the centre atom's unit columns) are
+// initialised here and replaced by Q^T X (row-major, stride kTrack).
+constexpr int NBT = 32;
 __global__ void __launch_bounds__(256) sytrd_kernel(int n_clusters, const int *__restrict__ order,
                                                     double *__restrict__ mat, const long long *__restrict__ mat_off,
                                                     double *__restrict__ vec, const long long *__restrict__ vec_off,
                                                     const int *__restrict__ dmax, const int *__restrict__ dim,
                                                     const int *__restrict__ n_orb, int nmax) {
   extern __shared__ double sh[];
-  double *vprev = sh, *wprev = sh + nmax, *v = sh + 2 * nmax, *prow = sh + 3 * nmax, *pacc = sh + 4 * nmax;
-  __shared__ double red[2 * kTrack * 4 + 8];
-  __shared__ double scal[4];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  double *v = sh, *y = sh + nmax, *yw = sh + 2 * nmax;
+  __shared__ double red[8];
+  __shared__ double coef[2 * NBT];
+  __shared__ double dpart[4 * 64];
+  __shared__ double rowk[2 * NBT];
+  __shared__ double gl[kGemmLds];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6, nthr = blockDim.x;
   for (int s = blockIdx.x; s < n_clusters; s += gridDim.x) {
     const int c = order[s];
     const int n = dim[c], ld = n;
@@ -264,144 +329,164 @@ __global__ void __launch_bounds__(256) sytrd_kernel(int n_clusters, const int *_
     const VecLayout vl = VecLayout::make(dmax[c]);
     double *cv = vec + vec_off[c];
     double *dd = cv + vl.d, *ee = cv + vl.e, *tt = cv + vl.tau, *X = cv + vl.G0;
+    double *Vp = cv + vl.G1;  // n x NBT, row-major
+    double *Wp = cv + vl.y0;  // n x NBT, row-major (spans y0 and y1)
     __syncthreads();
-    // tracked columns: X_u = L^{-1} E_i (nonzero in the last M rows), X_v = L^T E_i
-    for (long long e = tid; e < (long long)n * kTrack; e += blockDim.x) X[e] = 0.0;
-    for (int i = tid; i < nmax; i += blockDim.x) {
-      vprev[i] = 0.0;
-      wprev[i] = 0.0;
-      v[i] = 0.0;
-      prow[i] = 0.0;
+    for (long long e = tid; e < (long long)n * kTrack; e += nthr) X[e] = 0.0;
+    for (long long e = tid; e < (long long)n * NBT; e += nthr) {
+      Vp[e] = 0.0;
+      Wp[e] = 0.0;
     }
-    for (int i = tid; i < nw * nmax; i += blockDim.x) pacc[i] = 0.0;
     __syncthreads();
     const int b0 = n - M;
     if (tid < M) {
-      const int al = tid;
       // column al of the inverse of the trailing M x M block of L
-      double col[kMaxOrb];
-      for (int r = 0; r < M; ++r) col[r] = 0.0;
-      col[al] = 1.0 / L[(long long)(b0 + al) * ld + b0 + al];
-      for (int r = al + 1; r < M; ++r) {
-        double acc = 0.0;
-        for (int t = al; t < r; ++t) acc += L[(long long)(b0 + t) * ld + b0 + r] * col[t];
-        col[r] = -acc / L[(long long)(b0 + r) * ld + b0 + r];
+      const int al = tid;
+      double inv[kMaxOrb];
+#pragma unroll
+      for (int r = 0; r < kMaxOrb; ++r) inv[r] = 0.0;
+      for (int r = al; r < M; ++r) {
+        double acc = (r == al) ? 1.0 : 0.0;
+        for (int t = al; t < r; ++t) {
+          double it = 0.0;
+#pragma unroll
+          for (int q = 0; q < kMaxOrb; ++q)
+            if (q == t) it = inv[q];
+          acc -= L[(long long)(b0 + t) * ld + b0 + r] * it;
+        }
+        const double val = acc / L[(long long)(b0 + r) * ld + b0 + r];
+#pragma unroll
+        for (int q = 0; q < kMaxOrb; ++q)
+          if (q == r) inv[q] = val;
+        X[(long long)(b0 + r) * kTrack + al] = val;
       }
-      for (int r = 0; r < M; ++r) X[(long long)(b0 + r) * kTrack + al] = col[r];
     }
-    for (long long e = tid; e < (long long)n * M; e += blockDim.x) {
+    for (long long e = tid; e < (long long)n * M; e += nthr) {
       const int r = (int)(e % n), al = (int)(e / n);
       if (r <= b0 + al) X[(long long)r * kTrack + M + al] = L[(long long)r * ld + b0 + al];
     }
     __syncthreads();
-    for (int k = 0; k + 1 < n; ++k) {
-      // (1) previous rank-2 update on column k
-      for (int i = k + tid; i < n; i += blockDim.x)
-        A[(long long)k * ld + i] -= vprev[i] * wprev[k] + wprev[i] * vprev[k];
-      __syncthreads();
-      // (2) reflector from A(k+1:, k)
-      double part = 0.0;
-      for (int i = k + 2 + tid; i < n; i += blockDim.x) {
-        const double a = A[(long long)k * ld + i];
-        part += a * a;
-      }
-      const double sigma = block_sum(part, red);
-      const double alpha = A[(long long)k * ld + k + 1];
-      double beta, tau, sc;
-      if (sigma == 0.0) {
-        tau = 0.0;
-        beta = alpha;
-        sc = 0.0;
-      } else {
-        beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
-        tau = (beta - alpha) / beta;
-        sc = 1.0 / (alpha - beta);
-      }
-      for (int i = tid; i < n; i += blockDim.x) {
-        double vi = 0.0;
-        if (i == k + 1) vi = 1.0;
-        else if (i > k + 1) {
-          vi = A[(long long)k * ld + i] * sc;
-          A[(long long)k * ld + i] = vi;
-        }
-        v[i] = vi;
-      }
-      if (tid == 0) {
-        dd[k] = A[(long long)k * ld + k];
-        ee[k] = beta;
-        tt[k] = tau;
-      }
-      __syncthreads();
-      // (3) trailing lower triangle: apply the previous update and accumulate A22 v
-      for (int i0 = k + 1 + wave * 64; i0 < n; i0 += blockDim.x) {
-        const int i = i0 + lane;
-        const bool rowok = i < n;
-        const double vpi = rowok ? vprev[i] : 0.0, wpi = rowok ? wprev[i] : 0.0, vi = rowok ? v[i] : 0.0;
-        double racc = 0.0;
-        const int jend = min(i0 + 63, n - 1);
-        for (int j = k + 1; j <= jend; ++j) {
-          double cp = 0.0;
-          if (rowok && i >= j) {
-            double *pa = A + (long long)j * ld + i;
-            const double a = *pa - (vpi * wprev[j] + wpi * vprev[j]);
-            *pa = a;
-            racc += a * v[j];
-            if (i > j) cp = a * vi;
+    for (int j0 = 0; j0 + 1 < n; j0 += NBT) {
+      const int j1 = min(j0 + NBT, n - 1);
+      const int nbp = j1 - j0;
+      for (int i = 0; i < nbp; ++i) {
+        const int k = j0 + i;
+        // (1) column k takes the panel's earlier updates
+        if (i > 0) {
+          if (tid < 2 * NBT) rowk[tid] = (tid < NBT) ? Wp[(long long)k * NBT + tid] : Vp[(long long)k * NBT + tid - NBT];
+          __syncthreads();
+          for (int r = k + tid; r < n; r += nthr) {
+            const double *vr = Vp + (long long)r * NBT;
+            const double *wr = Wp + (long long)r * NBT;
+            double acc = 0.0;
+#pragma unroll 8
+            for (int t = 0; t < i; ++t) acc += vr[t] * rowk[t] + wr[t] * rowk[NBT + t];
+            A[(long long)k * ld + r] -= acc;
           }
-          cp = wave_sum(cp);
-          if (lane == 0) pacc[wave * nmax + j] += cp;
         }
-        if (rowok) prow[i] = racc;
-      }
-      __syncthreads();
-      // (4) p = tau A22 v, w = p - (tau/2)(p.v) v
-      double pv = 0.0;
-      for (int i = k + 1 + tid; i < n; i += blockDim.x) {
-        double p = prow[i];
-        for (int w = 0; w < nw; ++w) p += pacc[w * nmax + i];
-        p *= tau;
-        prow[i] = p;
-        pv += p * v[i];
-      }
-      pv = block_sum(pv, red);
-      for (int i = tid; i < n; i += blockDim.x) {
-        if (i > k) {
-          wprev[i] = prow[i] - 0.5 * tau * pv * v[i];
-          vprev[i] = v[i];
+        __syncthreads();
+        // (2) reflector from A(k+1:, k)
+        double part = 0.0;
+        for (int r = k + 2 + tid; r < n; r += nthr) {
+          const double a = A[(long long)k * ld + r];
+          part += a * a;
+        }
+        const double sigma = block_sum(part, red);
+        const double alpha = A[(long long)k * ld + k + 1];
+        double beta, tau, sc;
+        if (sigma == 0.0) {
+          tau = 0.0;
+          beta = alpha;
+          sc = 0.0;
         } else {
-          wprev[i] = 0.0;
-          vprev[i] = 0.0;
+          beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+          tau = (beta - alpha) / beta;
+          sc = 1.0 / (alpha - beta);
         }
-        for (int w = 0; w < nw; ++w) pacc[w * nmax + i] = 0.0;
+        for (int r = tid; r < n; r += nthr) {
+          double vr = 0.0;
+          if (r == k + 1) vr = 1.0;
+          else if (r > k + 1) {
+            vr = A[(long long)k * ld + r] * sc;
+            A[(long long)k * ld + r] = vr;
+          }
+          v[r] = vr;
+          Vp[(long long)r * NBT + i] = vr;
+        }
+        if (tid == 0) {
+          dd[k] = A[(long long)k * ld + k];
+          ee[k] = beta;
+          tt[k] = tau;
+        }
+        __syncthreads();
+        if (tau == 0.0) {
+          for (int r = tid; r < n; r += nthr) Wp[(long long)r * NBT + i] = 0.0;
+          __syncthreads();
+          continue;
+        }
+        const int m = n - k - 1;
+        // (3) per-wave partial rows of A(k+1:, k+1:) v(k+1:); before that every wave forms
+        //     partial sums of W(:,t)^T v (lanes 0..31) and V(:,t)^T v (lanes 32..63) over
+        //     its share of the rows (row-major V, W: one contiguous row segment per step)
+        {
+          const double *base = (lane < NBT) ? (Wp + lane) : (Vp + lane - NBT);
+          double acc = 0.0;
+          if ((lane & (NBT - 1)) < i) {
+#pragma unroll 4
+            for (int r = k + 1 + wave; r < n; r += nw) acc += base[(long long)r * NBT] * v[r];
+          }
+          dpart[wave * 64 + lane] = acc;
+        }
+        wg_symv_lower_partial(A + (long long)(k + 1) * ld + k + 1, ld, m, v + k + 1, yw + wave * nmax);
+        __syncthreads();
+        if (tid < 64) {
+          double a = 0.0;
+          for (int w = 0; w < nw; ++w) a += dpart[w * 64 + tid];
+          coef[tid] = a;
+        }
+        __syncthreads();
+        // (4) w = tau (A v - V (W^T v) - W (V^T v)); w -= (tau/2)(w^T v) v
+        double wvp = 0.0;
+        for (int r = k + 1 + tid; r < n; r += nthr) {
+          double acc = 0.0;
+          for (int w = 0; w < nw; ++w) acc += yw[w * nmax + r - k - 1];
+          const double *vr = Vp + (long long)r * NBT;
+          const double *wr = Wp + (long long)r * NBT;
+#pragma unroll 8
+          for (int t = 0; t < i; ++t) acc -= vr[t] * coef[t] + wr[t] * coef[NBT + t];
+          acc *= tau;
+          y[r] = acc;
+          wvp += acc * v[r];
+        }
+        const double wv = block_sum(wvp, red);
+        const double al = -0.5 * tau * wv;
+        for (int r = k + 1 + tid; r < n; r += nthr) Wp[(long long)r * NBT + i] = y[r] + al * v[r];
+        __syncthreads();
       }
-      // (5) tracked columns: X(k+1:, :) -= tau v (v^T X(k+1:, :))
-      if (tau != 0.0) {
-        double pc[kTrack];
-#pragma unroll
-        for (int q = 0; q < kTrack; ++q) pc[q] = 0.0;
-        for (int i = k + 1 + tid; i < n; i += blockDim.x) {
-          const double vi = v[i];
-          for (int q = 0; q < nt; ++q) pc[q] += vi * X[(long long)i * kTrack + q];
-        }
-        __syncthreads();
-        for (int q = 0; q < nt; ++q) {
-          const double t = wave_sum(pc[q]);
-          if (lane == 0) red[wave * kTrack + q] = t;
-        }
-        __syncthreads();
-        for (int e = tid; e < (n - k - 1) * nt; e += blockDim.x) {
-          const int i = k + 1 + e / nt, q = e % nt;
-          double sq = 0.0;
-          for (int w = 0; w < nw; ++w) sq += red[w * kTrack + q];
-          X[(long long)i * kTrack + q] -= tau * sq * v[i];
-        }
+      // trailing update A(j1:, j1:) -= V2 W2^T + W2 V2^T (lower triangle)
+      const int m2 = n - j1;
+      if (m2 > 0) {
+        double *C = A + (long long)j1 * ld + j1;
+        wg_gemm_sub<true, true, true, true>(C, ld, Vp + (long long)j1 * NBT, NBT, Wp + (long long)j1 * NBT, NBT, m2,
+                                            m2, nbp, gl);
+        wg_gemm_sub<true, true, true, true>(C, ld, Wp + (long long)j1 * NBT, NBT, Vp + (long long)j1 * NBT, NBT, m2,
+                                            m2, nbp, gl);
+      }
+      // the next panel starts from zero V, W
+      for (long long e = tid; e < (long long)n * NBT; e += nthr) {
+        Vp[e] = 0.0;
+        Wp[e] = 0.0;
       }
       __syncthreads();
     }
     if (tid == 0) {
       dd[n - 1] = A[(long long)(n - 1) * ld + n - 1];
-      if (n >= 1) ee[n - 1] = 0.0;
+      ee[n - 1] = 0.0;
     }
+    // tracked columns: X <- Q^T X, panel by panel in compact WY form (T factors kept for
+    // the density step)
+    __syncthreads();
+    wg_apply_q(A, ld, n, tt, cv + vl.u, true, X, kTrack, nt, true, sh);
   }
 }
 
@@ -424,7 +509,7 @@ void launch_sygst(Plan &p) {
 
 void launch_sytrd(Plan &p) {
   const int nmax = p.max_dim;
-  const size_t lds = sizeof(double) * (size_t)nmax * (4 + kWG / 64);
+  const size_t lds = sizeof(double) * std::max((size_t)nmax * (2 + kWG / 64), (size_t)kQapplyLds);
   hipLaunchKernelGGL(sytrd_kernel, dim3(p.workgroups), dim3(kWG), lds, p.stream, p.n_atoms, p.d_order, p.d_mat,
                      p.d_mat_off, p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb, nmax);
 }

@@ -83,6 +83,13 @@ struct Plan {
   int *d_counter = nullptr;
   DevStatus *d_status = nullptr;
 
+  // stage timing (HIP events on the plan's stream)
+  int profile = 0;
+  hipEvent_t ev_begin[LDC_NUM_STAGES] = {}, ev_end[LDC_NUM_STAGES] = {};
+  int ev_pending[LDC_NUM_STAGES] = {};
+  double stage_ms[LDC_NUM_STAGES] = {};
+  int prof_builds = 0;
+
   const double *last_H = nullptr, *last_S = nullptr;
   int solved = 0;
   size_t device_bytes = 0;
@@ -103,7 +110,7 @@ struct VecLayout {
     v.w = o; o += n;
     v.G0 = o; o += (long long)n * kTrack;
     v.G1 = o; o += (long long)n * kTrack;
-    v.u = o; o += (long long)n * kMaxOrb;
+    v.u = o; o += (long long)(n + 32) * 32;  // compact-WY T factors, one 32 x 32 block per panel
     v.y0 = o; o += (long long)n * kMaxOrb;
     v.y1 = o; o += (long long)n * kMaxOrb;
     v.dc = o;

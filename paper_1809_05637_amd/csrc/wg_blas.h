@@ -13,26 +13,37 @@ constexpr int GPAD = 1;   // LDS padding (doubles)
 // LDS needed by wg_gemm_sub: 2 * GK * (GT + GPAD) doubles.
 constexpr int kGemmLds = 2 * GK * (GT + GPAD);
 
+typedef double ldc_double4 __attribute__((ext_vector_type(4)));
+
 // C[m x n] -= A[m x k] * op(B), op(B) = B^T (B: n x k) if TRANS_B else B (B: k x n).
 // LOWER: only output tiles that touch the lower triangle (tile row >= tile column) are
 // computed (the strictly-upper part of diagonal tiles is computed too and must be unused).
-template <bool TRANS_B, bool LOWER>
+// 64 x 64 output tiles; each of the 4 waves owns a 32 x 32 quarter as 2 x 2 blocks of
+// v_mfma_f64_16x16x4 (FP64 matrix cores).  Operands are swapped so that each output
+// register covers 16 consecutive rows of one column (coalesced column-major stores):
+// the instruction's A operand takes op(B) (lane l: op(B)[k0 + l/16][c0 + l%16]) and its B
+// operand takes A (lane l: A[r0 + l%16][k0 + l/16]); register r of lane l then holds
+// C[r0 + l%16][c0 + 4 r + l/16].
+// A_RM / B_RM: A (resp. B) stored row-major with row stride lda (ldb) instead of
+// column-major with leading dimension lda (ldb).
+template <bool TRANS_B, bool LOWER, bool A_RM = false, bool B_RM = false>
 __device__ void wg_gemm_sub(double *C, int ldc, const double *A, int lda, const double *B, int ldb, int m, int n,
                             int k, double *lds) {
   double *As = lds;                  // [GK][GT+GPAD]
   double *Bs = lds + GK * (GT + GPAD);
-  const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int li = lane & 15, lk = lane >> 4;
   const int mt = (m + GT - 1) / GT, nt = (n + GT - 1) / GT;
   for (int tile = 0; tile < mt * nt; ++tile) {
     const int ti = tile / nt, tj = tile % nt;
     if (LOWER && tj > ti) continue;
     const int r0 = ti * GT, c0 = tj * GT;
-    double acc[4][4];
+    ldc_double4 acc[2][2];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+      for (int b = 0; b < 2; ++b) acc[a][b] = ldc_double4{0.0, 0.0, 0.0, 0.0};
     for (int k0 = 0; k0 < k; k0 += GK) {
       __syncthreads();
 #pragma unroll
@@ -40,7 +51,8 @@ __device__ void wg_gemm_sub(double *C, int ldc, const double *A, int lda, const 
         const int e = tid + 256 * q;
         const int row = e & 63, kk = e >> 6;
         const int gr = r0 + row, gk = k0 + kk;
-        As[kk * (GT + GPAD) + row] = (gr < m && gk < k) ? A[(long long)gk * lda + gr] : 0.0;
+        As[kk * (GT + GPAD) + row] =
+            (gr < m && gk < k) ? (A_RM ? A[(long long)gr * lda + gk] : A[(long long)gk * lda + gr]) : 0.0;
       }
       if (TRANS_B) {
 #pragma unroll
@@ -48,7 +60,8 @@ __device__ void wg_gemm_sub(double *C, int ldc, const double *A, int lda, const 
           const int e = tid + 256 * q;
           const int col = e & 63, kk = e >> 6;
           const int gc = c0 + col, gk = k0 + kk;
-          Bs[kk * (GT + GPAD) + col] = (gc < n && gk < k) ? B[(long long)gk * ldb + gc] : 0.0;
+          Bs[kk * (GT + GPAD) + col] =
+              (gc < n && gk < k) ? (B_RM ? B[(long long)gc * ldb + gk] : B[(long long)gk * ldb + gc]) : 0.0;
         }
       } else {
 #pragma unroll
@@ -56,31 +69,35 @@ __device__ void wg_gemm_sub(double *C, int ldc, const double *A, int lda, const 
           const int e = tid + 256 * q;
           const int kk = e & 15, col = e >> 4;
           const int gc = c0 + col, gk = k0 + kk;
-          Bs[kk * (GT + GPAD) + col] = (gc < n && gk < k) ? B[(long long)gc * ldb + gk] : 0.0;
+          Bs[kk * (GT + GPAD) + col] =
+              (gc < n && gk < k) ? (B_RM ? B[(long long)gk * ldb + gc] : B[(long long)gc * ldb + gk]) : 0.0;
         }
       }
       __syncthreads();
-#pragma unroll 4
-      for (int kk = 0; kk < GK; ++kk) {
-        double av[4], bv[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) av[a] = As[kk * (GT + GPAD) + tx + 16 * a];
+      for (int s4 = 0; s4 < GK / 4; ++s4) {
+        const int kr = (4 * s4 + lk) * (GT + GPAD);
+        double af[2], bf[2];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) bv[b] = Bs[kk * (GT + GPAD) + ty + 16 * b];
+        for (int a = 0; a < 2; ++a) af[a] = As[kr + wr * 32 + a * 16 + li];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 2; ++b) bf[b] = Bs[kr + wc * 32 + b * 16 + li];
 #pragma unroll
-          for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[b], af[a], acc[a][b], 0, 0, 0);
       }
     }
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int gc = c0 + ty + 16 * b;
-      if (gc >= n) continue;
+    for (int a = 0; a < 2; ++a) {
+      const int gr = r0 + wr * 32 + a * 16 + li;
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const int gr = r0 + tx + 16 * a;
-        if (gr < m) C[(long long)gc * ldc + gr] -= acc[a][b];
+      for (int b = 0; b < 2; ++b) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gc = c0 + wc * 32 + b * 16 + 4 * r + lk;
+          if (gr < m && gc < n) C[(long long)gc * ldc + gr] -= acc[a][b][r];
+        }
       }
     }
   }

@@ -1,0 +1,146 @@
+// Products with the orthogonal factor Q = H_0 H_1 ... H_{n-2} of the Householder
+// tridiagonalization, H_k = I - tau_k v_k v_k^T, v_k(0:k) = 0, v_k(k+1) = 1, v_k(k+2:) stored
+// in A(k+2:, k) (column-major, leading dimension ld).  Reflectors are grouped in panels of
+// QP columns; a panel's product is I - V T V^T with T upper triangular (compact WY form):
+// T(a,a) = tau_a, T(0:a, a) = -tau_a T(0:a, 0:a) (V(:, 0:a)^T v_a).
+#pragma once
+
+#include "dev_common.h"
+
+namespace ldc {
+
+constexpr int QP = 32;      // reflectors per panel
+constexpr int QCH = 32;     // rows of V staged in LDS per step
+constexpr int QXC = 32;     // largest number of columns of X
+constexpr int QS = QP + 1;  // LDS row stride
+
+// LDS (doubles) needed by wg_apply_q.
+constexpr int kQapplyLds = QCH * QS + 3 * QP * QS;
+
+// X (n rows, ncol <= QXC columns, row-major with row stride ldx) <- Q^T X (transpose) or
+// Q X.  With make_T the panels' T factors are formed and stored in Tq (QP*QP per panel);
+// otherwise the stored ones are used.  Whole workgroup (256 threads); lds: kQapplyLds.
+__device__ void wg_apply_q(const double *__restrict__ A, int ld, int n, const double *__restrict__ tau, double *Tq,
+                           bool make_T, double *X, int ldx, int ncol, bool transpose, double *lds) {
+  const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, wave = tid >> 6;
+  double *Vc = lds;              // [QCH][QS]
+  double *G = Vc + QCH * QS;     // [QP][QS]  V^T V
+  double *T = G + QP * QS;       // [QP][QS]
+  double *Y = T + QP * QS;       // [QP][QS]  V^T X, then T' V^T X
+  constexpr int NACC = (QP * QP + QP * QXC) / 256;  // entries per thread (8)
+  const int npan = (n - 1 + QP - 1) / QP;           // reflectors 0..n-2
+  for (int pi = 0; pi < npan; ++pi) {
+    const int p = transpose ? pi : (npan - 1 - pi);
+    const int p0 = p * QP, nbp = min(QP, n - 1 - p0);
+    const int nG = make_T ? QP * QP : 0;
+    const int nE = nG + QP * ncol;
+    double acc[NACC];
+#pragma unroll
+    for (int q = 0; q < NACC; ++q) acc[q] = 0.0;
+    for (int r0 = p0 + 1; r0 < n; r0 += QCH) {
+      __syncthreads();
+      for (int e = tid; e < QCH * QP; e += nthr) {
+        const int rr = e % QCH, t = e / QCH;
+        const int r = r0 + rr, k = p0 + t;
+        double val = 0.0;
+        if (t < nbp && r < n) {
+          if (r == k + 1) val = 1.0;
+          else if (r > k + 1) val = A[(long long)k * ld + r];
+        }
+        Vc[rr * QS + t] = val;
+      }
+      __syncthreads();
+      const int rmax = min(QCH, n - r0);
+#pragma unroll
+      for (int q = 0; q < NACC; ++q) {
+        const int e = tid + q * 256;
+        if (e < nE) {
+          double s = 0.0;
+          if (e < nG) {
+            const int a = e / QP, b = e % QP;
+            if (a < b)
+              for (int rr = 0; rr < rmax; ++rr) s += Vc[rr * QS + a] * Vc[rr * QS + b];
+          } else {
+            const int a = (e - nG) / ncol, qq = (e - nG) % ncol;
+            const double *xc = X + (long long)r0 * ldx + qq;
+            for (int rr = 0; rr < rmax; ++rr) s += Vc[rr * QS + a] * xc[(long long)rr * ldx];
+          }
+          acc[q] += s;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NACC; ++q) {
+      const int e = tid + q * 256;
+      if (e < nE) {
+        if (e < nG) G[(e / QP) * QS + e % QP] = acc[q];
+        else Y[((e - nG) / ncol) * QS + (e - nG) % ncol] = acc[q];
+      }
+    }
+    __syncthreads();
+    double *Tp = Tq + (long long)p * QP * QP;
+    if (make_T) {
+      // lane a of wave 0 forms row a of T: T(a, i) = -tau_i sum_{b=a}^{i-1} T(a, b) G(b, i)
+      if (wave == 0 && lane < QP) {
+        const int a = lane;
+        for (int i = 0; i < QP; ++i) {
+          double t;
+          if (i >= nbp || i < a) t = 0.0;
+          else if (i == a) t = tau[p0 + i];
+          else {
+            double sacc = 0.0;
+            for (int b = a; b < i; ++b) sacc += T[a * QS + b] * G[b * QS + i];
+            t = -tau[p0 + i] * sacc;
+          }
+          T[a * QS + i] = t;
+          Tp[a * QP + i] = t;
+        }
+      }
+    } else {
+      for (int e = tid; e < QP * QP; e += nthr) T[(e / QP) * QS + e % QP] = Tp[e];
+    }
+    __syncthreads();
+    // Y <- T^T Y (transpose) or T Y
+    double z[(QP * QXC) / 256];
+#pragma unroll
+    for (int q = 0; q < (QP * QXC) / 256; ++q) {
+      const int e = tid + q * 256;
+      double s = 0.0;
+      if (e < QP * ncol) {
+        const int a = e / ncol, qq = e % ncol;
+        if (transpose) {
+          for (int b = 0; b <= a; ++b) s += T[b * QS + a] * Y[b * QS + qq];
+        } else {
+          for (int b = a; b < QP; ++b) s += T[a * QS + b] * Y[b * QS + qq];
+        }
+      }
+      z[q] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < (QP * QXC) / 256; ++q) {
+      const int e = tid + q * 256;
+      if (e < QP * ncol) Y[(e / ncol) * QS + e % ncol] = z[q];
+    }
+    __syncthreads();
+    // X(r, :) -= V(r, :) Y
+    for (int r = p0 + 1 + tid; r < n; r += nthr) {
+      double vr[QP];
+#pragma unroll
+      for (int t = 0; t < QP; ++t) {
+        const int k = p0 + t;
+        vr[t] = (t < nbp) ? ((r == k + 1) ? 1.0 : (r > k + 1 ? A[(long long)k * ld + r] : 0.0)) : 0.0;
+      }
+      double *xr = X + (long long)r * ldx;
+      for (int q = 0; q < ncol; ++q) {
+        double s = 0.0;
+#pragma unroll
+        for (int t = 0; t < QP; ++t) s += vr[t] * Y[t * QS + q];
+        xr[q] -= s;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace ldc
