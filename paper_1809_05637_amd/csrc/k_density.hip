@@ -139,22 +139,19 @@ __global__ void __launch_bounds__(256) density_kernel(
     double *r = dc_apply(n, M, ws, ya, yb);
     // r <- Q r (compact WY panels, T factors stored by the tridiagonalization)
     wg_apply_q(A, ld, n, tt, cv + vl.u, false, r, kMaxOrb, M, false, qlds);
-    // x_P = L_PP^{-T} r_P (P = the last p rows), backward substitution
+    // x_P = L_PP^{-T} r_P = ((L^{-1})_PP)^T r_P (P = the last p rows; the S slot holds L^{-1}):
+    // x(g) = sum_{t >= g} Linv(t, g) r(t), written to the other buffer
     const int b0 = n - p;
-    for (int g = n - 1; g >= b0; --g) {
-      const int a = tid & 15, part = tid >> 4;
+    double *xo = (r == ya) ? yb : ya;
+    for (int e = tid; e < p * M; e += nthr) {
+      const int g = b0 + e / M, a = e % M;
+      const double *lc = L + (long long)g * ld;
       double acc = 0.0;
-      if (a < M)
-        for (int t = g + 1 + part; t < n; t += 16) acc += L[(long long)g * ld + t] * r[(long long)t * kMaxOrb + a];
-      red[part * 17 + a] = acc;
-      __syncthreads();
-      if (tid < M) {
-        double sacc = 0.0;
-        for (int q = 0; q < 16; ++q) sacc += red[q * 17 + tid];
-        r[(long long)g * kMaxOrb + tid] = (r[(long long)g * kMaxOrb + tid] - sacc) / L[(long long)g * ld + g];
-      }
-      __syncthreads();
+      for (int t = g; t < n; ++t) acc += lc[t] * r[(long long)t * kMaxOrb + a];
+      xo[(long long)g * kMaxOrb + a] = acc;
     }
+    __syncthreads();
+    r = xo;
     // scatter D(i, j) for j in F_i (members F \ {i} then i, last in the member list)
     const int fb = fna_ptr[c], nf = fna_ptr[c + 1] - fb;
     const int mend = mem_ptr[c + 1];

@@ -178,65 +178,131 @@ __global__ void __launch_bounds__(256) potrf_kernel(int n_clusters, const int *_
   }
 }
 
-// X <- L^{-1} X for lower-triangular L (n x n) and X (n x n), both column-major, ld = n.
-__device__ void trsm_lower_left(double *X, const double *L, int n, double (*L11)[NB + 1], double *gl) {
+// 32 x 32 lower-triangular inverse in LDS: Li = L11^{-1} (column c by thread c, forward
+// substitution).  Entries above the diagonal of Li are set to zero.
+__device__ inline void lds_tri_inverse(double (*L11)[NB + 1], double (*Li)[NB + 1], int jb) {
   const int tid = threadIdx.x;
-  const int ld = n;
-  for (int j0 = 0; j0 < n; j0 += NB) {
-    const int jb = min(NB, n - j0);
-    __syncthreads();
-    for (int e = tid; e < NB * NB; e += blockDim.x) {
-      const int r = e % NB, q = e / NB;
-      L11[r][q] = (r < jb && q < jb && r >= q) ? L[(long long)(j0 + q) * ld + j0 + r] : 0.0;
-    }
-    __syncthreads();
-    for (int col = tid; col < n; col += blockDim.x) {
-      double *xc = X + (long long)col * ld + j0;
-      double x[NB];
-#pragma unroll
-      for (int q = 0; q < NB; ++q) x[q] = (q < jb) ? xc[q] : 0.0;
-#pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        double v = x[q];
-#pragma unroll
-        for (int t = 0; t < q; ++t) v -= L11[q][t] * x[t];
-        x[q] = (q < jb) ? v / L11[q][q] : 0.0;
+  if (tid < NB) {
+    const int c = tid;
+    for (int r = 0; r < NB; ++r) {
+      double val = 0.0;
+      if (c < jb && r < jb && r >= c) {
+        double acc = (r == c) ? 1.0 : 0.0;
+        for (int t = c; t < r; ++t) acc -= L11[r][t] * Li[t][c];
+        val = acc / L11[r][r];
       }
-#pragma unroll
-      for (int q = 0; q < NB; ++q)
-        if (q < jb) xc[q] = x[q];
+      Li[r][c] = val;
     }
-    __syncthreads();
-    if (j0 + jb < n)
-      wg_gemm_sub<false, false>(X + j0 + jb, ld, L + (long long)j0 * ld + j0 + jb, ld, X + j0, ld, n - j0 - jb, n, jb,
-                                gl);
   }
   __syncthreads();
 }
 
-// Standard form A = L^{-1} H L^{-T}: X = L^{-1} H, transpose, A = L^{-1} X^T (H slot).
+// Standard form (Sec. II.C (iii) via Cholesky): with S = L L^T,
+//   A = L^{-1} H L^{-T}.
+// 1. L^{-1} in place of L (block columns from the last: B21 <- -L22^{-1} L21 L11^{-1},
+//    L11 <- L11^{-1}); the strictly-upper part of the S slot is cleared first.
+// 2. W = L^{-1} H in place of H, block rows from the last (each block row only needs rows
+//    of H above it, which are still intact).
+// 3. A = L^{-1} W^T (lower part) in place of W, block rows from the last.
+// All products are MFMA GEMMs that skip the structurally zero part of L^{-1}.  The tracked
+// columns of the tridiagonal solver are set up here: X_u = L^{-1} E_i (the last M columns of
+// L^{-1}) and X_v = L^T E_i (the last M rows of L, taken before the inversion).
 __global__ void __launch_bounds__(256) sygst_kernel(int n_clusters, const int *__restrict__ order,
                                                     double *__restrict__ mat, const long long *__restrict__ mat_off,
-                                                    const int *__restrict__ dmax, const int *__restrict__ dim) {
+                                                    double *__restrict__ vec, const long long *__restrict__ vec_off,
+                                                    const int *__restrict__ dmax, const int *__restrict__ dim,
+                                                    const int *__restrict__ n_orb) {
   __shared__ double L11[NB][NB + 1];
+  __shared__ double Li[NB][NB + 1];
   __shared__ double gl[kGemmLds];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, nthr = blockDim.x;
   for (int s = blockIdx.x; s < n_clusters; s += gridDim.x) {
     const int c = order[s];
-    const int n = dim[c];
+    const int n = dim[c], ld = n;
+    const int M = n_orb[c];
     double *H = mat + mat_off[c];
-    const double *L = H + (long long)dmax[c] * dmax[c];
-    trsm_lower_left(H, L, n, L11, gl);
-    for (long long e = tid; e < (long long)n * n; e += blockDim.x) {
-      const int i = (int)(e % n), j = (int)(e / n);
-      if (i > j) {
-        const double t = H[(long long)j * n + i];
-        H[(long long)j * n + i] = H[(long long)i * n + j];
-        H[(long long)i * n + j] = t;
-      }
+    double *L = H + (long long)dmax[c] * dmax[c];
+    const VecLayout vl = VecLayout::make(dmax[c]);
+    double *cv = vec + vec_off[c];
+    double *X = cv + vl.G0;
+    double *tmp = cv + vl.G1;  // n x NB scratch (column-major, ld n)
+    const int b0 = n - M;
+    __syncthreads();
+    // tracked columns: X_v = L^T E_i (rows of L of the centre atom); X_u filled below
+    for (long long e = tid; e < (long long)n * kTrack; e += nthr) X[e] = 0.0;
+    __syncthreads();
+    for (long long e = tid; e < (long long)n * M; e += nthr) {
+      const int r = (int)(e % n), al = (int)(e / n);
+      if (r <= b0 + al) X[(long long)r * kTrack + M + al] = L[(long long)r * ld + b0 + al];
+    }
+    // clear the strictly-upper triangle of the S slot
+    for (long long e = tid; e < (long long)n * n; e += nthr) {
+      const int r = (int)(e % n), q = (int)(e / n);
+      if (r < q) L[e] = 0.0;
     }
     __syncthreads();
-    trsm_lower_left(H, L, n, L11, gl);
+    // 1. L <- L^{-1}
+    const int nblk = (n + NB - 1) / NB;
+    for (int bj = nblk - 1; bj >= 0; --bj) {
+      const int j = bj * NB, jb = min(NB, n - j);
+      for (int e = tid; e < NB * NB; e += nthr) {
+        const int r = e % NB, q = e / NB;
+        L11[r][q] = (r < jb && q < jb && r >= q) ? L[(long long)(j + q) * ld + j + r] : 0.0;
+      }
+      __syncthreads();
+      lds_tri_inverse(L11, Li, jb);
+      const int m = n - j - jb;
+      if (m > 0) {
+        // tmp = -L22^{-1} L21
+        wg_gemm_sub<false, false, false, false, true>(tmp, n, L + (long long)(j + jb) * ld + j + jb, ld,
+                                                       L + (long long)j * ld + j + jb, ld, m, jb, m, gl, 0);
+        // L21 <- tmp L11^{-1}
+        for (int r = tid; r < m; r += nthr) {
+          double row[NB];
+#pragma unroll
+          for (int q = 0; q < NB; ++q) row[q] = (q < jb) ? tmp[(long long)q * n + r] : 0.0;
+#pragma unroll 4
+          for (int q = 0; q < NB; ++q) {
+            if (q < jb) {
+              double acc = 0.0;
+#pragma unroll
+              for (int t = 0; t < NB; ++t) acc += row[t] * Li[t][q];
+              L[(long long)(j + q) * ld + j + jb + r] = acc;
+            }
+          }
+        }
+      }
+      for (int e = tid; e < NB * NB; e += nthr) {
+        const int r = e % NB, q = e / NB;
+        if (r < jb && q < jb && r >= q) L[(long long)(j + q) * ld + j + r] = Li[r][q];
+      }
+      __syncthreads();
+    }
+    // X_u = L^{-1} E_i: rows b0.. of the last M columns of L^{-1}
+    for (int e = tid; e < M * M; e += nthr) {
+      const int r = e % M, al = e / M;
+      X[(long long)(b0 + r) * kTrack + al] = (r >= al) ? L[(long long)(b0 + al) * ld + b0 + r] : 0.0;
+    }
+    // 2. W = L^{-1} H, block rows from the last (tmp holds -W_b, NB x n, ld NB)
+    for (int bj = nblk - 1; bj >= 0; --bj) {
+      const int r0 = bj * NB, jb = min(NB, n - r0), r1 = r0 + jb;
+      wg_gemm_sub<false, false, false, false, true>(tmp, NB, L + r0, ld, H, ld, jb, n, r1, gl, r0);
+      for (long long e = tid; e < (long long)jb * n; e += nthr) {
+        const int rr = (int)(e % jb), q = (int)(e / jb);
+        H[(long long)q * ld + r0 + rr] = -tmp[(long long)q * NB + rr];
+      }
+      __syncthreads();
+    }
+    // 3. A = L^{-1} W^T, lower part: block row b of A = L^{-1}(rows b, cols 0:r1) W(0:r1, 0:r1)^T
+    for (int bj = nblk - 1; bj >= 0; --bj) {
+      const int r0 = bj * NB, jb = min(NB, n - r0), r1 = r0 + jb;
+      wg_gemm_sub<true, false, false, false, true>(tmp, NB, L + r0, ld, H, ld, jb, r1, r1, gl, r0);
+      for (long long e = tid; e < (long long)jb * r1; e += nthr) {
+        const int rr = (int)(e % jb), q = (int)(e / jb);
+        H[(long long)q * ld + r0 + rr] = -tmp[(long long)q * NB + rr];
+      }
+      __syncthreads();
+    }
   }
 }
 
@@ -332,38 +398,9 @@ __global__ void __launch_bounds__(256) sytrd_kernel(int n_clusters, const int *_
     double *Vp = cv + vl.G1;  // n x NBT, row-major
     double *Wp = cv + vl.y0;  // n x NBT, row-major (spans y0 and y1)
     __syncthreads();
-    for (long long e = tid; e < (long long)n * kTrack; e += nthr) X[e] = 0.0;
     for (long long e = tid; e < (long long)n * NBT; e += nthr) {
       Vp[e] = 0.0;
       Wp[e] = 0.0;
-    }
-    __syncthreads();
-    const int b0 = n - M;
-    if (tid < M) {
-      // column al of the inverse of the trailing M x M block of L
-      const int al = tid;
-      double inv[kMaxOrb];
-#pragma unroll
-      for (int r = 0; r < kMaxOrb; ++r) inv[r] = 0.0;
-      for (int r = al; r < M; ++r) {
-        double acc = (r == al) ? 1.0 : 0.0;
-        for (int t = al; t < r; ++t) {
-          double it = 0.0;
-#pragma unroll
-          for (int q = 0; q < kMaxOrb; ++q)
-            if (q == t) it = inv[q];
-          acc -= L[(long long)(b0 + t) * ld + b0 + r] * it;
-        }
-        const double val = acc / L[(long long)(b0 + r) * ld + b0 + r];
-#pragma unroll
-        for (int q = 0; q < kMaxOrb; ++q)
-          if (q == r) inv[q] = val;
-        X[(long long)(b0 + r) * kTrack + al] = val;
-      }
-    }
-    for (long long e = tid; e < (long long)n * M; e += nthr) {
-      const int r = (int)(e % n), al = (int)(e / n);
-      if (r <= b0 + al) X[(long long)r * kTrack + M + al] = L[(long long)r * ld + b0 + al];
     }
     __syncthreads();
     for (int j0 = 0; j0 + 1 < n; j0 += NBT) {
@@ -504,7 +541,7 @@ void launch_potrf(Plan &p) {
 
 void launch_sygst(Plan &p) {
   hipLaunchKernelGGL(sygst_kernel, dim3(p.workgroups), dim3(kWG), 0, p.stream, p.n_atoms, p.d_order, p.d_mat,
-                     p.d_mat_off, p.d_dmax, p.d_dim);
+                     p.d_mat_off, p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb);
 }
 
 void launch_sytrd(Plan &p) {

@@ -25,10 +25,12 @@ typedef double ldc_double4 __attribute__((ext_vector_type(4)));
 // operand takes A (lane l: A[r0 + l%16][k0 + l/16]); register r of lane l then holds
 // C[r0 + l%16][c0 + 4 r + l/16].
 // A_RM / B_RM: A (resp. B) stored row-major with row stride lda (ldb) instead of
-// column-major with leading dimension lda (ldb).
-template <bool TRANS_B, bool LOWER, bool A_RM = false, bool B_RM = false>
+// column-major with leading dimension lda (ldb).  OVERWRITE: C = -A op(B) (C is not read).
+// a_diag >= 0: A is zero above its a_diag-th superdiagonal (A[r][kk] = 0 for kk > r + a_diag),
+// so each tile row only runs over the K range that can be nonzero.
+template <bool TRANS_B, bool LOWER, bool A_RM = false, bool B_RM = false, bool OVERWRITE = false>
 __device__ void wg_gemm_sub(double *C, int ldc, const double *A, int lda, const double *B, int ldb, int m, int n,
-                            int k, double *lds) {
+                            int k, double *lds, int a_diag = -1) {
   double *As = lds;                  // [GK][GT+GPAD]
   double *Bs = lds + GK * (GT + GPAD);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -44,7 +46,8 @@ __device__ void wg_gemm_sub(double *C, int ldc, const double *A, int lda, const 
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b) acc[a][b] = ldc_double4{0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < k; k0 += GK) {
+    const int kend = (a_diag >= 0) ? min(k, r0 + GT + a_diag) : k;
+    for (int k0 = 0; k0 < kend; k0 += GK) {
       __syncthreads();
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -96,7 +99,10 @@ __device__ void wg_gemm_sub(double *C, int ldc, const double *A, int lda, const 
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int gc = c0 + wc * 32 + b * 16 + 4 * r + lk;
-          if (gr < m && gc < n) C[(long long)gc * ldc + gr] -= acc[a][b][r];
+          if (gr < m && gc < n) {
+            if (OVERWRITE) C[(long long)gc * ldc + gr] = -acc[a][b][r];
+            else C[(long long)gc * ldc + gr] -= acc[a][b][r];
+          }
         }
       }
     }
