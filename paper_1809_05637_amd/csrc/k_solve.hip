@@ -103,13 +103,78 @@ __global__ void __launch_bounds__(256) gather_kernel(int n_clusters, const int *
 }
 
 // ---------------------------------------------------------------------------------------
+// Rows times a small triangular factor held in LDS:
+//   dst(r, q) = sum_t src(r, t) F(q, t)   (F_T: F(t, q)),  r < m, q < jb,
+// with F = Li (NB x NB, padded with zeros).  src and dst are column-major (leading
+// dimensions lds_, ldd) and may be the same memory: rows are staged through LDS (64 per
+// step, buffer of 64 (NB + 1) doubles) before they are overwritten.  Thread (rr, q0) forms
+// the outputs (rr, q0 + 4 j).
+template <bool F_T>
+__device__ void wg_rows_times_small(const double *src, int lds_, double *dst, int ldd, int m, int jb,
+                                    const double (*Li)[NB + 1], double *stage) {
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int rr = tid & 63, q0 = tid >> 6;
+  for (int r0 = 0; r0 < m; r0 += 64) {
+    const int rows = min(64, m - r0);
+    __syncthreads();
+    for (int e = tid; e < 64 * NB; e += nthr) {
+      const int r = e & 63, t = e >> 6;
+      stage[r * (NB + 1) + t] = (r < rows && t < jb) ? src[t * lds_ + r0 + r] : 0.0;
+    }
+    __syncthreads();
+    double acc[NB / 4];
+#pragma unroll
+    for (int j = 0; j < NB / 4; ++j) acc[j] = 0.0;
+#pragma unroll 2
+    for (int t = 0; t < NB; ++t) {
+      const double a = stage[rr * (NB + 1) + t];
+#pragma unroll
+      for (int j = 0; j < NB / 4; ++j) {
+        const int q = q0 + 4 * j;
+        acc[j] += a * (F_T ? Li[q][t] : Li[t][q]);
+      }
+    }
+    if (rr < rows) {
+#pragma unroll
+      for (int j = 0; j < NB / 4; ++j) {
+        const int q = q0 + 4 * j;
+        if (q < jb) dst[q * ldd + r0 + rr] = acc[j];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// 32 x 32 lower-triangular inverse in LDS: Li = L11^{-1} (column c by thread c, forward
+// substitution).  Entries above the diagonal of Li are set to zero.
+__device__ inline void lds_tri_inverse(double (*L11)[NB + 1], double (*Li)[NB + 1], int jb) {
+  const int tid = threadIdx.x;
+  if (tid < NB) {
+    const int c = tid;
+    for (int r = 0; r < NB; ++r) {
+      double val = 0.0;
+      if (c < jb && r < jb && r >= c) {
+        double acc = (r == c) ? 1.0 : 0.0;
+        for (int t = c; t < r; ++t) acc -= L11[r][t] * Li[t][c];
+        val = acc / L11[r][r];
+      }
+      Li[r][c] = val;
+    }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------------------
 // Blocked right-looking Cholesky S^(i) = L L^T (lower; the strictly-upper part is left as
-// it was).  A non-positive pivot reports LDC_ERR_NOT_SPD for the cluster.
-__global__ void __launch_bounds__(256) potrf_kernel(int n_clusters, const int *__restrict__ order,
-                                                    double *__restrict__ mat, const long long *__restrict__ mat_off,
-                                                    const int *__restrict__ dmax, const int *__restrict__ dim,
-                                                    DevStatus *st) {
+// it was).  Per panel: unblocked factor of the diagonal block in LDS, its inverse, the
+// panel below as L21 = A21 L11^{-T}, and the trailing update A22 -= L21 L21^T (MFMA GEMM).
+// A non-positive pivot reports LDC_ERR_NOT_SPD for the cluster.
+__global__ void __launch_bounds__(256, 2) potrf_kernel(int n_clusters, const int *__restrict__ order,
+                                                       double *__restrict__ mat, const long long *__restrict__ mat_off,
+                                                       const int *__restrict__ dmax, const int *__restrict__ dim,
+                                                       DevStatus *st) {
   __shared__ double L11[NB][NB + 1];
+  __shared__ double Li[NB][NB + 1];
   __shared__ double gl[kGemmLds];
   __shared__ int bad;
   const int tid = threadIdx.x;
@@ -151,50 +216,17 @@ __global__ void __launch_bounds__(256) potrf_kernel(int n_clusters, const int *_
       }
       __syncthreads();
       if (bad) break;
-      for (int r = j0 + jb + tid; r < n; r += blockDim.x) {
-        double x[NB];
-#pragma unroll
-        for (int q = 0; q < NB; ++q) x[q] = (q < jb) ? S[(long long)(j0 + q) * ld + r] : 0.0;
-#pragma unroll
-        for (int q = 0; q < NB; ++q) {
-          double v = x[q];
-#pragma unroll
-          for (int t = 0; t < q; ++t) v -= x[t] * L11[q][t];
-          x[q] = (q < jb) ? v / L11[q][q] : 0.0;
-        }
-#pragma unroll
-        for (int q = 0; q < NB; ++q)
-          if (q < jb) S[(long long)(j0 + q) * ld + r] = x[q];
-      }
-      __syncthreads();
-      if (j0 + jb < n) {
-        double *L21 = S + (long long)j0 * ld + j0 + jb;
-        wg_gemm_sub<true, true>(S + (long long)(j0 + jb) * ld + j0 + jb, ld, L21, ld, L21, ld, n - j0 - jb, n - j0 - jb,
-                                jb, gl);
+      const int m = n - j0 - jb;
+      if (m > 0) {
+        lds_tri_inverse(L11, Li, jb);
+        double *P = S + (long long)j0 * ld + j0 + jb;
+        wg_rows_times_small<true>(P, ld, P, ld, m, jb, Li, gl);
+        wg_gemm_sub<true, true>(S + (long long)(j0 + jb) * ld + j0 + jb, ld, P, ld, P, ld, m, m, jb, gl);
       }
     }
     __syncthreads();
     if (bad && tid == 0) report(st, LDC_ERR_NOT_SPD, c);
   }
-}
-
-// 32 x 32 lower-triangular inverse in LDS: Li = L11^{-1} (column c by thread c, forward
-// substitution).  Entries above the diagonal of Li are set to zero.
-__device__ inline void lds_tri_inverse(double (*L11)[NB + 1], double (*Li)[NB + 1], int jb) {
-  const int tid = threadIdx.x;
-  if (tid < NB) {
-    const int c = tid;
-    for (int r = 0; r < NB; ++r) {
-      double val = 0.0;
-      if (c < jb && r < jb && r >= c) {
-        double acc = (r == c) ? 1.0 : 0.0;
-        for (int t = c; t < r; ++t) acc -= L11[r][t] * Li[t][c];
-        val = acc / L11[r][r];
-      }
-      Li[r][c] = val;
-    }
-  }
-  __syncthreads();
 }
 
 // Standard form (Sec. II.C (iii) via Cholesky): with S = L L^T,
@@ -207,7 +239,7 @@ __device__ inline void lds_tri_inverse(double (*L11)[NB + 1], double (*Li)[NB + 
 // All products are MFMA GEMMs that skip the structurally zero part of L^{-1}.  The tracked
 // columns of the tridiagonal solver are set up here: X_u = L^{-1} E_i (the last M columns of
 // L^{-1}) and X_v = L^T E_i (the last M rows of L, taken before the inversion).
-__global__ void __launch_bounds__(256) sygst_kernel(int n_clusters, const int *__restrict__ order,
+__global__ void __launch_bounds__(256, 2) sygst_kernel(int n_clusters, const int *__restrict__ order,
                                                     double *__restrict__ mat, const long long *__restrict__ mat_off,
                                                     double *__restrict__ vec, const long long *__restrict__ vec_off,
                                                     const int *__restrict__ dmax, const int *__restrict__ dim,
@@ -257,20 +289,7 @@ __global__ void __launch_bounds__(256) sygst_kernel(int n_clusters, const int *_
         wg_gemm_sub<false, false, false, false, true>(tmp, n, L + (long long)(j + jb) * ld + j + jb, ld,
                                                        L + (long long)j * ld + j + jb, ld, m, jb, m, gl, 0);
         // L21 <- tmp L11^{-1}
-        for (int r = tid; r < m; r += nthr) {
-          double row[NB];
-#pragma unroll
-          for (int q = 0; q < NB; ++q) row[q] = (q < jb) ? tmp[(long long)q * n + r] : 0.0;
-#pragma unroll 4
-          for (int q = 0; q < NB; ++q) {
-            if (q < jb) {
-              double acc = 0.0;
-#pragma unroll
-              for (int t = 0; t < NB; ++t) acc += row[t] * Li[t][q];
-              L[(long long)(j + q) * ld + j + jb + r] = acc;
-            }
-          }
-        }
+        wg_rows_times_small<false>(tmp, n, L + (long long)j * ld + j + jb, ld, m, jb, Li, gl);
       }
       for (int e = tid; e < NB * NB; e += nthr) {
         const int r = e % NB, q = e / NB;
@@ -364,26 +383,26 @@ __device__ void wg_symv_lower_partial(const double *__restrict__ A, int lda, int
 // Householder tridiagonalization of A (lower triangle, column-major, ld = n), blocked:
 // Q^T A Q = T with Q = H_0 H_1 ... H_{n-2}, H_k = I - tau_k v_k v_k^T, v_k(k+1) = 1 and
 // v_k(k+2:) stored in A(k+2:, k).  Panels of NBT columns: inside a panel each column takes
-// the updates of the panel's earlier reflectors from the n x NBT blocks V, W (row-major, so
-// a row's coefficients are one contiguous load), its reflector is generated, and
+// the updates of the panel's earlier reflectors from the n x 2 NBT block [V | W] (row-major,
+// so a row's coefficients are one contiguous load), its reflector is generated, and
 // w = tau (A v - V (W^T v) - W (V^T v)) - (tau/2)(w^T v) v uses the trailing matrix as left
-// by the previous panel; after the panel the trailing matrix gets A -= V W^T + W V^T (two
-// tiled MFMA GEMMs on its lower triangle).
+// by the previous panel; after the panel the trailing matrix gets A -= V W^T + W V^T (one
+// tiled MFMA GEMM over its lower triangle, [V | W] times [W | V]^T).
 // The tracked columns X = [L^{-1} E_i | L^T E_i] (E_i: the centre atom's unit columns) are
-// initialised here and replaced by Q^T X (row-major, stride kTrack).
+// replaced by Q^T X (row-major, stride kTrack).
 constexpr int NBT = 32;
-__global__ void __launch_bounds__(256) sytrd_kernel(int n_clusters, const int *__restrict__ order,
-                                                    double *__restrict__ mat, const long long *__restrict__ mat_off,
-                                                    double *__restrict__ vec, const long long *__restrict__ vec_off,
-                                                    const int *__restrict__ dmax, const int *__restrict__ dim,
-                                                    const int *__restrict__ n_orb, int nmax) {
+constexpr int VWS = 2 * NBT;  // row stride of [V | W]
+__global__ void __launch_bounds__(256, 2) sytrd_kernel(int n_clusters, const int *__restrict__ order,
+                                                       double *__restrict__ mat, const long long *__restrict__ mat_off,
+                                                       double *__restrict__ vec, const long long *__restrict__ vec_off,
+                                                       const int *__restrict__ dmax, const int *__restrict__ dim,
+                                                       const int *__restrict__ n_orb, int nmax) {
   extern __shared__ double sh[];
   double *v = sh, *y = sh + nmax, *yw = sh + 2 * nmax;
   __shared__ double red[8];
   __shared__ double coef[2 * NBT];
   __shared__ double dpart[4 * 64];
   __shared__ double rowk[2 * NBT];
-  __shared__ double gl[kGemmLds];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6, nthr = blockDim.x;
   for (int s = blockIdx.x; s < n_clusters; s += gridDim.x) {
     const int c = order[s];
@@ -391,33 +410,27 @@ __global__ void __launch_bounds__(256) sytrd_kernel(int n_clusters, const int *_
     const int M = n_orb[c];
     const int nt = 2 * M;
     double *A = mat + mat_off[c];
-    const double *L = A + (long long)dmax[c] * dmax[c];
     const VecLayout vl = VecLayout::make(dmax[c]);
     double *cv = vec + vec_off[c];
     double *dd = cv + vl.d, *ee = cv + vl.e, *tt = cv + vl.tau, *X = cv + vl.G0;
-    double *Vp = cv + vl.G1;  // n x NBT, row-major
-    double *Wp = cv + vl.y0;  // n x NBT, row-major (spans y0 and y1)
+    double *VW = cv + vl.G1;  // n x 2 NBT, row-major (spans G1 and u; u takes the T factors at the end)
     __syncthreads();
-    for (long long e = tid; e < (long long)n * NBT; e += nthr) {
-      Vp[e] = 0.0;
-      Wp[e] = 0.0;
-    }
+    for (long long e = tid; e < (long long)n * VWS; e += nthr) VW[e] = 0.0;
     __syncthreads();
     for (int j0 = 0; j0 + 1 < n; j0 += NBT) {
       const int j1 = min(j0 + NBT, n - 1);
       const int nbp = j1 - j0;
       for (int i = 0; i < nbp; ++i) {
         const int k = j0 + i;
-        // (1) column k takes the panel's earlier updates
+        // (1) column k takes the panel's earlier updates: A(:,k) -= V W(k,:)^T + W V(k,:)^T
         if (i > 0) {
-          if (tid < 2 * NBT) rowk[tid] = (tid < NBT) ? Wp[(long long)k * NBT + tid] : Vp[(long long)k * NBT + tid - NBT];
+          if (tid < VWS) rowk[tid] = VW[(long long)k * VWS + ((tid + NBT) & (VWS - 1))];
           __syncthreads();
           for (int r = k + tid; r < n; r += nthr) {
-            const double *vr = Vp + (long long)r * NBT;
-            const double *wr = Wp + (long long)r * NBT;
+            const double *vr = VW + (long long)r * VWS;
             double acc = 0.0;
 #pragma unroll 8
-            for (int t = 0; t < i; ++t) acc += vr[t] * rowk[t] + wr[t] * rowk[NBT + t];
+            for (int t = 0; t < i; ++t) acc += vr[t] * rowk[t] + vr[NBT + t] * rowk[NBT + t];
             A[(long long)k * ld + r] -= acc;
           }
         }
@@ -448,7 +461,7 @@ __global__ void __launch_bounds__(256) sytrd_kernel(int n_clusters, const int *_
             A[(long long)k * ld + r] = vr;
           }
           v[r] = vr;
-          Vp[(long long)r * NBT + i] = vr;
+          VW[(long long)r * VWS + i] = vr;
         }
         if (tid == 0) {
           dd[k] = A[(long long)k * ld + k];
@@ -457,20 +470,20 @@ __global__ void __launch_bounds__(256) sytrd_kernel(int n_clusters, const int *_
         }
         __syncthreads();
         if (tau == 0.0) {
-          for (int r = tid; r < n; r += nthr) Wp[(long long)r * NBT + i] = 0.0;
+          for (int r = tid; r < n; r += nthr) VW[(long long)r * VWS + NBT + i] = 0.0;
           __syncthreads();
           continue;
         }
         const int m = n - k - 1;
         // (3) per-wave partial rows of A(k+1:, k+1:) v(k+1:); before that every wave forms
         //     partial sums of W(:,t)^T v (lanes 0..31) and V(:,t)^T v (lanes 32..63) over
-        //     its share of the rows (row-major V, W: one contiguous row segment per step)
+        //     its share of the rows
         {
-          const double *base = (lane < NBT) ? (Wp + lane) : (Vp + lane - NBT);
+          const double *base = VW + ((lane + NBT) & (VWS - 1));
           double acc = 0.0;
           if ((lane & (NBT - 1)) < i) {
 #pragma unroll 4
-            for (int r = k + 1 + wave; r < n; r += nw) acc += base[(long long)r * NBT] * v[r];
+            for (int r = k + 1 + wave; r < n; r += nw) acc += base[(long long)r * VWS] * v[r];
           }
           dpart[wave * 64 + lane] = acc;
         }
@@ -487,33 +500,27 @@ __global__ void __launch_bounds__(256) sytrd_kernel(int n_clusters, const int *_
         for (int r = k + 1 + tid; r < n; r += nthr) {
           double acc = 0.0;
           for (int w = 0; w < nw; ++w) acc += yw[w * nmax + r - k - 1];
-          const double *vr = Vp + (long long)r * NBT;
-          const double *wr = Wp + (long long)r * NBT;
+          const double *vr = VW + (long long)r * VWS;
 #pragma unroll 8
-          for (int t = 0; t < i; ++t) acc -= vr[t] * coef[t] + wr[t] * coef[NBT + t];
+          for (int t = 0; t < i; ++t) acc -= vr[t] * coef[t] + vr[NBT + t] * coef[NBT + t];
           acc *= tau;
           y[r] = acc;
           wvp += acc * v[r];
         }
         const double wv = block_sum(wvp, red);
         const double al = -0.5 * tau * wv;
-        for (int r = k + 1 + tid; r < n; r += nthr) Wp[(long long)r * NBT + i] = y[r] + al * v[r];
+        for (int r = k + 1 + tid; r < n; r += nthr) VW[(long long)r * VWS + NBT + i] = y[r] + al * v[r];
         __syncthreads();
       }
-      // trailing update A(j1:, j1:) -= V2 W2^T + W2 V2^T (lower triangle)
+      // trailing update A(j1:, j1:) -= V2 W2^T + W2 V2^T (lower triangle); the GEMM stages
+      // its tiles in the LDS that held v, y and the partial rows
       const int m2 = n - j1;
       if (m2 > 0) {
-        double *C = A + (long long)j1 * ld + j1;
-        wg_gemm_sub<true, true, true, true>(C, ld, Vp + (long long)j1 * NBT, NBT, Wp + (long long)j1 * NBT, NBT, m2,
-                                            m2, nbp, gl);
-        wg_gemm_sub<true, true, true, true>(C, ld, Wp + (long long)j1 * NBT, NBT, Vp + (long long)j1 * NBT, NBT, m2,
-                                            m2, nbp, gl);
+        const double *P = VW + (long long)j1 * VWS;
+        wg_gemm_sub<true, true, true, true>(A + (long long)j1 * ld + j1, ld, P, VWS, P, VWS, m2, m2, VWS, sh, -1, NBT);
       }
       // the next panel starts from zero V, W
-      for (long long e = tid; e < (long long)n * NBT; e += nthr) {
-        Vp[e] = 0.0;
-        Wp[e] = 0.0;
-      }
+      for (long long e = tid; e < (long long)n * VWS; e += nthr) VW[e] = 0.0;
       __syncthreads();
     }
     if (tid == 0) {
@@ -546,7 +553,8 @@ void launch_sygst(Plan &p) {
 
 void launch_sytrd(Plan &p) {
   const int nmax = p.max_dim;
-  const size_t lds = sizeof(double) * std::max((size_t)nmax * (2 + kWG / 64), (size_t)kQapplyLds);
+  const size_t lds =
+      sizeof(double) * std::max({(size_t)nmax * (2 + kWG / 64), (size_t)kQapplyLds, (size_t)kGemmLds});
   hipLaunchKernelGGL(sytrd_kernel, dim3(p.workgroups), dim3(kWG), lds, p.stream, p.n_atoms, p.d_order, p.d_mat,
                      p.d_mat_off, p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb, nmax);
 }

@@ -123,20 +123,27 @@ __device__ void wg_apply_q(const double *__restrict__ A, int ld, int n, const do
       if (e < QP * ncol) Y[(e / ncol) * QS + e % ncol] = z[q];
     }
     __syncthreads();
-    // X(r, :) -= V(r, :) Y
-    for (int r = p0 + 1 + tid; r < n; r += nthr) {
-      double vr[QP];
-#pragma unroll
-      for (int t = 0; t < QP; ++t) {
-        const int k = p0 + t;
-        vr[t] = (t < nbp) ? ((r == k + 1) ? 1.0 : (r > k + 1 ? A[(long long)k * ld + r] : 0.0)) : 0.0;
+    // X(r, :) -= V(r, :) Y, with V staged in LDS by chunks of QCH rows
+    for (int r0 = p0 + 1; r0 < n; r0 += QCH) {
+      __syncthreads();
+      for (int e = tid; e < QCH * QP; e += nthr) {
+        const int rr = e % QCH, t = e / QCH;
+        const int r = r0 + rr, k = p0 + t;
+        double val = 0.0;
+        if (t < nbp && r < n) {
+          if (r == k + 1) val = 1.0;
+          else if (r > k + 1) val = A[(long long)k * ld + r];
+        }
+        Vc[rr * QS + t] = val;
       }
-      double *xr = X + (long long)r * ldx;
-      for (int q = 0; q < ncol; ++q) {
+      __syncthreads();
+      const int rmax = min(QCH, n - r0);
+      for (int e = tid; e < rmax * ncol; e += nthr) {
+        const int rr = e / ncol, q = e % ncol;
         double s = 0.0;
-#pragma unroll
-        for (int t = 0; t < QP; ++t) s += vr[t] * Y[t * QS + q];
-        xr[q] -= s;
+#pragma unroll 8
+        for (int t = 0; t < QP; ++t) s += Vc[rr * QS + t] * Y[t * QS + q];
+        X[(long long)(r0 + rr) * ldx + q] -= s;
       }
     }
     __syncthreads();
