@@ -327,55 +327,120 @@ __global__ void __launch_bounds__(256, 2) sygst_kernel(int n_clusters, const int
 
 // ---------------------------------------------------------------------------------------
 // Partial products of y = A v for the symmetric m x m matrix held in the lower triangle of
-// A (column-major, leading dimension lda), streamed by whole columns.  Wave w takes the
-// column groups {c, c + nw, c + 2 nw, c + 3 nw}, c = w + 4 nw g: rows from c upward are read
-// in 64-row chunks (SU chunks x 4 columns in flight per lane); for every row the four
-// columns' contributions to y(r) are summed in a register and added to the wave's private
-// partial row my (LDS, no workgroup barrier needed), and each column's stored part feeds
-// y(c) through one wave reduction.  The caller sums the nw partial rows.
-constexpr int SU = 4;
-constexpr int SC = 4;
+// A (column-major, leading dimension lda), streamed by whole columns.  The columns form
+// strips of SC; wave w takes the strips w, w + nw, ... and walks each from its diagonal
+// down in chunks of 64 SU rows (lane = row).  The loads of the next chunk are issued before
+// the current one is used (two chunks in flight per wave).  For every row the strip's
+// contribution to y(r) goes to the wave's private partial row my (LDS, no workgroup
+// barrier needed); each column's stored part feeds y(c) through one wave reduction per
+// strip.  The caller sums the nw partial rows.
+constexpr int SU = 2;
+constexpr int SC = 8;
 __device__ void wg_symv_lower_partial(const double *__restrict__ A, int lda, int m, const double *v, double *my) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int r = lane; r < m; r += 64) my[r] = 0.0;
-  for (int c0 = wave; c0 < m; c0 += SC * nw) {
-    int cj[SC];
-    double vc[SC], acc[SC];
-    const double *col[SC];
+  int s = wave, r0 = s * SC;
+  if (r0 >= m) return;
+  // Rows and columns past the end are clamped, so the loads are unconditional (all in
+  // flight together); entries outside the lower triangle are masked where they are used.
+  auto fetch = [&](int st, int rs, double (*a)[SC]) {
+    const int c0 = st * SC;
 #pragma unroll
-    for (int j = 0; j < SC; ++j) {
-      cj[j] = c0 + j * nw;
-      vc[j] = cj[j] < m ? v[cj[j]] : 0.0;
-      acc[j] = 0.0;
-      col[j] = A + (long long)(cj[j] < m ? cj[j] : c0) * lda;
-    }
-    for (int r0 = c0; r0 < m; r0 += 64 * SU) {
-      double a[SU][SC];
+    for (int u = 0; u < SU; ++u) {
+      const int r = rs + u * 64 + lane, rc = r < m ? r : m - 1;
 #pragma unroll
-      for (int u = 0; u < SU; ++u) {
-        const int r = r0 + u * 64 + lane;
-#pragma unroll
-        for (int j = 0; j < SC; ++j) a[u][j] = (r < m && r >= cj[j]) ? col[j][r] : 0.0;
+      for (int j = 0; j < SC; ++j) {
+        const int cc = c0 + j < m ? c0 + j : m - 1;
+        a[u][j] = A[cc * lda + rc];
       }
+    }
+  };
+  double cur[SU][SC], nxt[SU][SC], acc[SC], vc[SC];
+  fetch(s, r0, cur);
 #pragma unroll
-      for (int u = 0; u < SU; ++u) {
-        const int r = r0 + u * 64 + lane;
-        if (r < m) {
-          const double vr = v[r];
-          double t = 0.0;
+  for (int j = 0; j < SC; ++j) {
+    acc[j] = 0.0;
+    vc[j] = (r0 + j < m) ? v[r0 + j] : 0.0;
+  }
+  while (true) {
+    int ns = s, nr0 = r0 + 64 * SU;
+    if (nr0 >= m) {
+      ns = s + nw;
+      nr0 = ns * SC;
+    }
+    const bool more = nr0 < m;
+    if (more) fetch(ns, nr0, nxt);
+    const int c0 = s * SC;
 #pragma unroll
-          for (int j = 0; j < SC; ++j) {
-            t += a[u][j] * vc[j];
-            if (r > cj[j]) acc[j] += a[u][j] * vr;
-          }
-          my[r] += t;
+    for (int u = 0; u < SU; ++u) {
+      const int r = r0 + u * 64 + lane;
+      if (r < m) {
+        const double vr = v[r];
+        double t = 0.0;
+#pragma unroll
+        for (int j = 0; j < SC; ++j) {
+          const double x = (r >= c0 + j) ? cur[u][j] : 0.0;
+          t += x * vc[j];
+          if (r > c0 + j) acc[j] += x * vr;
         }
+        my[r] += t;
       }
     }
+    if (ns != s) {
 #pragma unroll
-    for (int j = 0; j < SC; ++j) {
-      const double t = wave_sum(acc[j]);
-      if (lane == 0 && cj[j] < m) my[cj[j]] += t;
+      for (int j = 0; j < SC; ++j) {
+        const double t = wave_sum(acc[j]);
+        if (lane == 0 && c0 + j < m) my[c0 + j] += t;
+        acc[j] = 0.0;
+        vc[j] = (more && nr0 + j < m) ? v[nr0 + j] : 0.0;
+      }
+    }
+    if (!more) break;
+    s = ns;
+    r0 = nr0;
+#pragma unroll
+    for (int u = 0; u < SU; ++u)
+#pragma unroll
+      for (int j = 0; j < SC; ++j) cur[u][j] = nxt[u][j];
+  }
+}
+
+constexpr int NBT = 32;        // panel width of the tridiagonalization
+constexpr int VWS = 2 * NBT;  // row stride of [V | W]
+
+// out(r) = [V | W](r, :) . cf for rows r in [r_begin, r_end) of the row-major n x 2 NBT block
+// [V | W] (cf: 2 NBT coefficients in LDS).  Eight lanes share a row (each reads 8 contiguous
+// doubles, whole cache lines per wave) and combine their parts with three shuffles; a
+// workgroup step covers 4 x 32 rows (loads of all four in flight together; rows past the end
+// are clamped).  f(r, value) is called by the first lane of each group.
+template <class F>
+__device__ void wg_rows_dot_vw(const double *__restrict__ VW, int r_begin, int r_end, const double *cf, F f) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int g = lane >> 3, sub = lane & 7;
+  static_assert(VWS == 64, "eight lanes of eight coefficients per row");
+  double c[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) c[q] = cf[sub * 8 + q];
+  constexpr int RU = 4;
+  for (int r0 = r_begin; r0 < r_end; r0 += RU * 8 * nw) {
+    double x[RU][8];
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int r = r0 + (u * nw + wave) * 8 + g, rc = r < r_end ? r : r_end - 1;
+      const double *row = VW + (long long)rc * VWS + sub * 8;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) x[u][q] = row[q];
+    }
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int r = r0 + (u * nw + wave) * 8 + g;
+      double part = 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) part += x[u][q] * c[q];
+      part += __shfl_xor(part, 1, 64);
+      part += __shfl_xor(part, 2, 64);
+      part += __shfl_xor(part, 4, 64);
+      if (sub == 0 && r < r_end) f(r, part);
     }
   }
 }
@@ -390,8 +455,6 @@ __device__ void wg_symv_lower_partial(const double *__restrict__ A, int lda, int
 // tiled MFMA GEMM over its lower triangle, [V | W] times [W | V]^T).
 // The tracked columns X = [L^{-1} E_i | L^T E_i] (E_i: the centre atom's unit columns) are
 // replaced by Q^T X (row-major, stride kTrack).
-constexpr int NBT = 32;
-constexpr int VWS = 2 * NBT;  // row stride of [V | W]
 __global__ void __launch_bounds__(256, 2) sytrd_kernel(int n_clusters, const int *__restrict__ order,
                                                        double *__restrict__ mat, const long long *__restrict__ mat_off,
                                                        double *__restrict__ vec, const long long *__restrict__ vec_off,
@@ -423,16 +486,12 @@ __global__ void __launch_bounds__(256, 2) sytrd_kernel(int n_clusters, const int
       for (int i = 0; i < nbp; ++i) {
         const int k = j0 + i;
         // (1) column k takes the panel's earlier updates: A(:,k) -= V W(k,:)^T + W V(k,:)^T
+        //     (the products run over all NBT columns: the columns >= i of V and W are zero)
         if (i > 0) {
           if (tid < VWS) rowk[tid] = VW[(long long)k * VWS + ((tid + NBT) & (VWS - 1))];
           __syncthreads();
-          for (int r = k + tid; r < n; r += nthr) {
-            const double *vr = VW + (long long)r * VWS;
-            double acc = 0.0;
-#pragma unroll 8
-            for (int t = 0; t < i; ++t) acc += vr[t] * rowk[t] + vr[NBT + t] * rowk[NBT + t];
-            A[(long long)k * ld + r] -= acc;
-          }
+          double *ak = A + (long long)k * ld;
+          wg_rows_dot_vw(VW, k, n, rowk, [&](int r, double x) { ak[r] -= x; });
         }
         __syncthreads();
         // (2) reflector from A(k+1:, k)
@@ -482,8 +541,19 @@ __global__ void __launch_bounds__(256, 2) sytrd_kernel(int n_clusters, const int
           const double *base = VW + ((lane + NBT) & (VWS - 1));
           double acc = 0.0;
           if ((lane & (NBT - 1)) < i) {
-#pragma unroll 4
-            for (int r = k + 1 + wave; r < n; r += nw) acc += base[(long long)r * VWS] * v[r];
+            // 16 rows per step; rows past the end are clamped and masked, so the loads are
+            // unconditional and issue back to back
+            for (int r0 = k + 1 + wave; r0 < n; r0 += 16 * nw) {
+              double a[16], b[16];
+#pragma unroll
+              for (int u = 0; u < 16; ++u) {
+                const int r = r0 + u * nw, rc = r < n ? r : n - 1;
+                a[u] = base[(long long)rc * VWS];
+                b[u] = r < n ? v[rc] : 0.0;
+              }
+#pragma unroll
+              for (int u = 0; u < 16; ++u) acc += a[u] * b[u];
+            }
           }
           dpart[wave * 64 + lane] = acc;
         }
@@ -497,16 +567,13 @@ __global__ void __launch_bounds__(256, 2) sytrd_kernel(int n_clusters, const int
         __syncthreads();
         // (4) w = tau (A v - V (W^T v) - W (V^T v)); w -= (tau/2)(w^T v) v
         double wvp = 0.0;
-        for (int r = k + 1 + tid; r < n; r += nthr) {
+        wg_rows_dot_vw(VW, k + 1, n, coef, [&](int r, double x) {
           double acc = 0.0;
           for (int w = 0; w < nw; ++w) acc += yw[w * nmax + r - k - 1];
-          const double *vr = VW + (long long)r * VWS;
-#pragma unroll 8
-          for (int t = 0; t < i; ++t) acc -= vr[t] * coef[t] + vr[NBT + t] * coef[NBT + t];
-          acc *= tau;
+          acc = (acc - x) * tau;
           y[r] = acc;
           wvp += acc * v[r];
-        }
+        });
         const double wv = block_sum(wvp, red);
         const double al = -0.5 * tau * wv;
         for (int r = k + 1 + tid; r < n; r += nthr) VW[(long long)r * VWS + NBT + i] = y[r] + al * v[r];

@@ -15,7 +15,7 @@ constexpr int QXC = 32;     // largest number of columns of X
 constexpr int QS = QP + 1;  // LDS row stride
 
 // LDS (doubles) needed by wg_apply_q.
-constexpr int kQapplyLds = QCH * QS + 3 * QP * QS;
+constexpr int kQapplyLds = QCH * QS + 3 * QP * QS + QCH * (QXC + 1);
 
 // X (n rows, ncol <= QXC columns, row-major with row stride ldx) <- Q^T X (transpose) or
 // Q X.  With make_T the panels' T factors are formed and stored in Tq (QP*QP per panel);
@@ -27,6 +27,7 @@ __device__ void wg_apply_q(const double *__restrict__ A, int ld, int n, const do
   double *G = Vc + QCH * QS;     // [QP][QS]  V^T V
   double *T = G + QP * QS;       // [QP][QS]
   double *Y = T + QP * QS;       // [QP][QS]  V^T X, then T' V^T X
+  double *Xc = Y + QP * QS;      // [QCH][QXC+1] rows of X
   constexpr int NACC = (QP * QP + QP * QXC) / 256;  // entries per thread (8)
   const int npan = (n - 1 + QP - 1) / QP;           // reflectors 0..n-2
   for (int pi = 0; pi < npan; ++pi) {
@@ -49,6 +50,10 @@ __device__ void wg_apply_q(const double *__restrict__ A, int ld, int n, const do
         }
         Vc[rr * QS + t] = val;
       }
+      for (int e = tid; e < QCH * ncol; e += nthr) {
+        const int rr = e / ncol, qq = e % ncol;
+        Xc[rr * (QXC + 1) + qq] = (r0 + rr < n) ? X[(long long)(r0 + rr) * ldx + qq] : 0.0;
+      }
       __syncthreads();
       const int rmax = min(QCH, n - r0);
 #pragma unroll
@@ -62,8 +67,7 @@ __device__ void wg_apply_q(const double *__restrict__ A, int ld, int n, const do
               for (int rr = 0; rr < rmax; ++rr) s += Vc[rr * QS + a] * Vc[rr * QS + b];
           } else {
             const int a = (e - nG) / ncol, qq = (e - nG) % ncol;
-            const double *xc = X + (long long)r0 * ldx + qq;
-            for (int rr = 0; rr < rmax; ++rr) s += Vc[rr * QS + a] * xc[(long long)rr * ldx];
+            for (int rr = 0; rr < rmax; ++rr) s += Vc[rr * QS + a] * Xc[rr * (QXC + 1) + qq];
           }
           acc[q] += s;
         }
