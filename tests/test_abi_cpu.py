@@ -66,3 +66,57 @@ def test_regions_paper_counts():
     rp, col, _ = synth.bsr_pattern(len(pos), bi, bj)
     ptr, mem, lng = ldc.regions(pos, cell, np.array([1, 1, 1]), np.full(len(pos), 13), rp, col, 8.7, 0.3)
     assert ptr[1] - ptr[0] == 465 and lng[: ptr[1]].sum() == 190
+
+
+def _plan_status(ldc, s, **over):
+    """Status of ldc_plan_create for system s with some arrays replaced (0 if it succeeded)."""
+    args = dict(pos=s["pos"], cell=s["cell"], periodic=s["periodic"], n_orb=s["n_orb"], row_ptr=s["row_ptr"],
+                col=s["col"], r_L=s["r_L"])
+    args.update(over)
+    try:
+        plan = ldc.Plan(args["pos"], args["cell"], args["periodic"], args["n_orb"], args["row_ptr"], args["col"],
+                        args["r_L"])
+    except ldc.LdcError as e:
+        return e.name
+    plan.close()
+    return "LDC_OK"
+
+
+def test_plan_create_rejects_bad_input_before_touching_the_device():
+    """Argument and pattern checks of ldc_plan_create run on the host, before any device
+    allocation: an empty system, a non-positive radius, a missing diagonal block, an
+    unsorted or asymmetric pattern and more orbitals per atom than the compiled limit."""
+    ldc = _lib()
+    s = synth.small("sc27")
+    n = s["n_atoms"]
+    assert _plan_status(ldc, s, n_orb=np.zeros(0, np.int32), row_ptr=np.zeros(1, np.int32),
+                        col=np.zeros(0, np.int32), pos=np.zeros((0, 3))) == "LDC_ERR_ARG"
+    assert _plan_status(ldc, s, r_L=0.0) == "LDC_ERR_ARG"
+    assert _plan_status(ldc, s, r_L=-1.0) == "LDC_ERR_ARG"
+    # drop the diagonal block of atom 0 (row 0 keeps its other blocks)
+    rp, col = s["row_ptr"].copy(), s["col"].copy()
+    keep = np.ones(len(col), bool)
+    keep[[b for b in range(rp[0], rp[1]) if col[b] == 0]] = False
+    rp2 = rp.copy()
+    rp2[1:] -= 1
+    assert _plan_status(ldc, s, row_ptr=rp2, col=col[keep]) == "LDC_ERR_ARG"
+    # unsorted columns in row 0
+    col_u = col.copy()
+    col_u[rp[0]], col_u[rp[0] + 1] = col[rp[0] + 1], col[rp[0]]
+    assert _plan_status(ldc, s, col=col_u) == "LDC_ERR_ARG"
+    # asymmetric: replace one off-diagonal entry of row 0 by a column that does not list 0
+    row0 = set(col[rp[0]:rp[1]].tolist())
+    far = next(j for j in range(n) if j not in row0)
+    col_a = col.copy()
+    b_off = next(b for b in range(rp[0], rp[1]) if col[b] != 0)
+    col_a[b_off] = far
+    order = np.argsort(col_a[rp[0]:rp[1]])
+    col_a[rp[0]:rp[1]] = col_a[rp[0]:rp[1]][order]
+    assert _plan_status(ldc, s, col=col_a) == "LDC_ERR_ARG"
+    # column index out of range
+    col_r = col.copy()
+    col_r[rp[1] - 1] = n
+    assert _plan_status(ldc, s, col=col_r) == "LDC_ERR_ARG"
+    # more orbitals per atom than compiled in (16)
+    assert _plan_status(ldc, s, n_orb=np.full(n, 17, np.int32)) == "LDC_ERR_LIMIT"
+    assert _plan_status(ldc, s, n_orb=np.zeros(n, np.int32)) == "LDC_ERR_ARG"

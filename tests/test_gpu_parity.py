@@ -126,3 +126,40 @@ def test_bracket_error_is_reported():
     mu, eb, ne = plan.density(s["n_electrons"], s["kT"], D)
     assert abs(ne - s["n_electrons"]) < 1e-9 * s["n_electrons"]
     plan.close()
+
+
+def test_not_spd_overlap_is_reported_and_plan_recovers():
+    """A cluster overlap with a non-positive Cholesky pivot (one atom's onsite S block set to
+    -I) is reported as LDC_ERR_NOT_SPD naming a cluster that contains that atom; the same
+    plan then builds the intact system to parity."""
+    import torch
+    import paper_1809_05637_amd as ldc
+    from gpu_util import to_dev
+    s = synth.small("sc27")
+    bad_atom = 5
+    S_bad = s["S"].copy()
+    rp, col, off, no = s["row_ptr"], s["col"], s["blk_off"], s["n_orb"]
+    for b in range(rp[bad_atom], rp[bad_atom + 1]):
+        if col[b] == bad_atom:
+            m = no[bad_atom]
+            S_bad[off[b]: off[b] + m * m] = (-np.eye(m)).ravel()
+    plan = ldc.Plan.from_system(s, stream=torch.cuda.current_stream())
+    H, Sb, S = to_dev(s["H"]), to_dev(S_bad), to_dev(s["S"])
+    D = torch.zeros_like(S)
+    plan.lno(Sb, None)
+    with pytest.raises(ldc.LdcError) as ei:
+        plan.solve(H, Sb)
+        plan.density(s["n_electrons"], s["kT"], D)
+    assert ei.value.name == "LDC_ERR_NOT_SPD"
+    mem_ptr, mem, _ = ldc.regions(s["pos"], s["cell"], s["periodic"], s["n_orb"], s["row_ptr"], s["col"],
+                                  s["r_L"], s["kappa"])
+    holders = {i for i in range(s["n_atoms"]) if bad_atom in mem[mem_ptr[i]:mem_ptr[i + 1]]}
+    assert ei.value.where in holders
+    ref = oracle.density_build(s, workers=1)
+    plan.lno(S, None)
+    plan.solve(H, S)
+    mu, eb, ne = plan.density(s["n_electrons"], s["kT"], D)
+    torch.cuda.synchronize()
+    assert np.abs(D.cpu().numpy() - ref["D"]).max() <= TOL_D
+    assert abs(eb - ref["e_band"]) / s["n_atoms"] <= TOL_E
+    plan.close()
