@@ -81,7 +81,7 @@ ldc_status check_status(Plan &p) {
 }
 
 const char *kStageNames[LDC_NUM_STAGES] = {"lambda", "lno_eig", "gather", "potrf", "sygst",
-                                           "sytrd", "stedc", "mu", "density"};
+                                           "sy2sb", "sb2st", "stedc", "mu", "density"};
 
 inline void stage_begin(Plan &p, int s) {
   if (p.profile) (void)hipEventRecord(p.ev_begin[s], p.stream);
@@ -223,10 +223,10 @@ ldc_status ldc_plan_create(ldc_plan_t *out, int n_atoms, const double *pos, cons
     delete h;
     return LDC_ERR_DEVICE;
   }
-  if ((size_t)p.max_dim * (2 + ldc::kWG / 64) * sizeof(double) + 20 * 1024 > 64 * 1024) {
+  if (p.max_dim > ldc::kMaxDimTri) {
     free_all(p);
     delete h;
-    return LDC_ERR_LIMIT;  // tridiagonalization keeps 6 length-n vectors in LDS
+    return LDC_ERR_LIMIT;  // the band reduction holds 8 panel columns in LDS
   }
   p.workgroups = opt->workgroups > 0 ? opt->workgroups : 2 * p.n_cu;
   p.workgroups = std::max(1, std::min(p.workgroups, n_atoms));
@@ -412,11 +412,14 @@ ldc_status ldc_solve(ldc_plan_t plan, const double *d_H, const double *d_S) {
   ldc::launch_sygst(p);
   stage_end(p, 4);
   stage_begin(p, 5);
-  ldc::launch_sytrd(p);
+  ldc::launch_sy2sb(p);
   stage_end(p, 5);
   stage_begin(p, 6);
-  ldc::launch_stedc(p);
+  ldc::launch_sb2st(p);
   stage_end(p, 6);
+  stage_begin(p, 7);
+  ldc::launch_stedc(p);
+  stage_end(p, 7);
   HIPCHK(hipGetLastError());
   p.last_H = d_H;
   p.last_S = d_S;
@@ -449,7 +452,7 @@ ldc_status ldc_density(ldc_plan_t plan, double n_electrons, double kT, double *d
   st[6] = kT;
   st[7] = g;
   HIPCHK(hipMemcpyAsync(p.d_mu, st, sizeof(st), hipMemcpyHostToDevice, p.stream));
-  stage_begin(p, 7);
+  stage_begin(p, 8);
   ldc::launch_mu_init(p, kT);
   int iters = 0;
   while (true) {
@@ -461,10 +464,10 @@ ldc_status ldc_density(ldc_plan_t plan, double n_electrons, double kT, double *d
     HIPCHK(hipStreamSynchronize(p.stream));
     if (chk[2] != 0.0 || iters >= 256) break;
   }
-  stage_end(p, 7);
-  stage_begin(p, 8);
-  ldc::launch_density(p, kT, d_D_out, p.last_H, p.last_S, g);
   stage_end(p, 8);
+  stage_begin(p, 9);
+  ldc::launch_density(p, kT, d_D_out, p.last_H, p.last_S, g);
+  stage_end(p, 9);
   HIPCHK(hipGetLastError());
   ldc_status s = finish_density(p, g, mu_out, e_band_out, n_e_out);
   if (p.profile) {

@@ -137,8 +137,10 @@ __global__ void __launch_bounds__(256) density_kernel(
     }
     __syncthreads();
     double *r = dc_apply(n, M, ws, ya, yb);
-    // r <- Q r (compact WY panels, T factors stored by the tridiagonalization)
-    wg_apply_q(A, ld, n, tt, cv + vl.u, false, r, kMaxOrb, M, false, qlds);
+    // r <- Q r = Q1 (Q2 r): the bulge-chasing reflectors, then the band reduction's compact-WY
+    // panels (T factors stored by the band reduction)
+    wg_apply_q2(A, ld, n, r, kMaxOrb, M, false);
+    wg_apply_q(A, ld, n, tt, cv + vl.u, false, r, kMaxOrb, M, false, qlds, kBand);
     // x_P = L_PP^{-T} r_P = ((L^{-1})_PP)^T r_P (P = the last p rows; the S slot holds L^{-1}):
     // x(g) = sum_{t >= g} Linv(t, g) r(t), written to the other buffer
     const int b0 = n - p;

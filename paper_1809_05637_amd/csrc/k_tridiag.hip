@@ -1,0 +1,485 @@
+// Two-stage Householder tridiagonalization of the standard-form cluster matrix
+// A = L^{-1} H^(i) L^{-T} (Sec. II.C (iii)): Q^T A Q = T with Q = Q1 Q2.
+//
+// Stage 1 (sy2sb_kernel), reduction to band form of width b = kBand.  For every panel of b
+// columns j0.. the block P = A(r:n, j0:j0+b), r = j0 + b, is QR-factorised (Householder,
+// compact WY: Q_p = I - V T V^T) and the trailing matrix is updated two-sidedly:
+//   X = A22 V T (symmetric product),  K = (V T)^T X,  W = X - V K / 2,
+//   A22 <- A22 - V W^T - W V^T.
+// All four products run on the FP64 matrix cores; only the QR of the tall-skinny panel is
+// vector code (leaves of 8 columns factored in LDS).  The reflectors stay below the band
+// (reflector k: unit at row k + b, the rest in A(k+b+1:, k)), tau in the tau vector and the
+// T factors in the compact-WY area, one b x b block per panel.  The tracked columns get
+// X <- Q1^T X at the end.
+//
+// Stage 2 (sb2st_kernel), band to tridiagonal by bulge chasing on a band array holding the
+// lower band and the bulge (2b + 1 diagonals).  Sweep s removes column s below its
+// subdiagonal: step j takes the reflector of rows [r0, r0 + b), r0 = s + 1 + j b, from
+// column s (j = 0) or from the first column of the bulge the previous step created
+// (j >= 1), applies it from the left to the bulge columns, two-sidedly to the diagonal block
+// and from the right to the band block below (which creates the next bulge).  Step j of
+// sweep s + 1 never touches what steps >= j + 3 of sweep s touch, so at time t every sweep s
+// with j = t - 3 s in range is advanced at once, one wavefront per step.  The reflectors are
+// kept in the strictly upper triangle of A (sweep s in column n - 1 - s, rows j b..:
+// tau first, then v(1:)); X <- Q2^T X follows, sweep by sweep.
+#include "wg_blas.h"
+#include "wg_qapply.h"
+
+namespace ldc {
+
+constexpr int LEAF = 8;                     // columns per LDS-resident leaf of the panel QR
+constexpr int kRowRegs = kMaxDimTri / 64;   // rows of a panel column held per lane
+
+// ---------------------------------------------------------------------------------------
+// QR of the panel P = A(r:n, j0:j0+kBand) (column-major, ld), r = j0 + kBand, m = n - r.
+// On return P holds R on and above its diagonal and the Householder vectors below it (unit
+// diagonal implicit); tau_k goes to tt[j0 + k] (0 where the reflector has length <= 1).
+// lf: LEAF * m doubles of LDS; sm: 2 * LEAF * LEAF + 4 * LEAF doubles; red: 4 * LEAF.
+__device__ void panel_qr(double *__restrict__ A, int ld, int n, int j0, double *__restrict__ tt, double *lf,
+                         double *sm, double *red) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nthr = blockDim.x, nw = nthr >> 6;
+  const int r = j0 + kBand;
+  double *Tl = sm;                  // [LEAF][LEAF] leaf T (row-major)
+  double *Gl = sm + LEAF * LEAF;    // [LEAF][LEAF] leaf V^T V
+  double *tl = Gl + LEAF * LEAF;    // [LEAF] leaf tau
+  for (int c0 = 0; c0 < kBand; c0 += LEAF) {
+    const int R0 = r + c0, mp = n - R0;
+    if (mp <= 0) {
+      if (tid < LEAF) tt[j0 + c0 + tid] = 0.0;
+      continue;
+    }
+    // leaf into LDS, column-major with stride mp
+    __syncthreads();
+    for (int e = tid; e < LEAF * mp; e += nthr) {
+      const int k = e / mp, i = e % mp;
+      lf[e] = A[(long long)(j0 + c0 + k) * ld + R0 + i];
+    }
+    __syncthreads();
+    for (int k = 0; k < LEAF; ++k) {
+      if (mp - k < 2) {
+        if (tid == 0) {
+          tt[j0 + c0 + k] = 0.0;
+          tl[k] = 0.0;
+        }
+        continue;
+      }
+      // sigma = |x(k+1:)|^2 and the raw dots of x(k+1:) with the later leaf columns
+      double part[LEAF];
+#pragma unroll
+      for (int q = 0; q < LEAF; ++q) part[q] = 0.0;
+      const double *xk = lf + k * mp;
+      for (int i = k + 1 + tid; i < mp; i += nthr) {
+        const double a = xk[i];
+        part[0] += a * a;
+#pragma unroll
+        for (int c = 1; c < LEAF; ++c)
+          if (k + c < LEAF) part[c] += a * lf[(k + c) * mp + i];
+      }
+#pragma unroll
+      for (int q = 0; q < LEAF; ++q) {
+        const double t = wave_sum(part[q]);
+        if (lane == 0) red[wave * LEAF + q] = t;
+      }
+      __syncthreads();
+      double tot[LEAF];
+#pragma unroll
+      for (int q = 0; q < LEAF; ++q) {
+        double a = 0.0;
+        for (int w = 0; w < nw; ++w) a += red[w * LEAF + q];
+        tot[q] = a;
+      }
+      const double sigma = tot[0];
+      const double alpha = xk[k];
+      double beta, tau, sc;
+      if (sigma == 0.0) {
+        tau = 0.0;
+        beta = alpha;
+        sc = 0.0;
+      } else {
+        beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+        tau = (beta - alpha) / beta;
+        sc = 1.0 / (alpha - beta);
+      }
+      double wc[LEAF];
+#pragma unroll
+      for (int c = 1; c < LEAF; ++c) wc[c] = (k + c < LEAF) ? lf[(k + c) * mp + k] + sc * tot[c] : 0.0;
+      __syncthreads();  // every thread has read red, alpha and the row-k entries
+      for (int i = k + tid; i < mp; i += nthr) {
+        const double v = (i == k) ? 1.0 : xk[i] * sc;
+#pragma unroll
+        for (int c = 1; c < LEAF; ++c)
+          if (k + c < LEAF) lf[(k + c) * mp + i] -= tau * v * wc[c];
+        lf[k * mp + i] = (i == k) ? beta : v;
+      }
+      if (tid == 0) {
+        tt[j0 + c0 + k] = tau;
+        tl[k] = tau;
+      }
+      __syncthreads();
+    }
+    // leaf back to A
+    for (int e = tid; e < LEAF * mp; e += nthr) {
+      const int k = e / mp, i = e % mp;
+      A[(long long)(j0 + c0 + k) * ld + R0 + i] = lf[e];
+    }
+    if (c0 + LEAF >= kBand) break;  // no later panel columns
+    // leaf Gram matrix G(a, b) = v_a . v_b (a < b): 8 lanes per pair, rows strided by 8
+    {
+      const int g = tid >> 3, sub = tid & 7;
+      double acc = 0.0;
+      int a = 0, b = 0;
+      if (g < LEAF * (LEAF - 1) / 2) {
+        int t = g;
+        a = 0;
+        while (t >= LEAF - 1 - a) {
+          t -= LEAF - 1 - a;
+          ++a;
+        }
+        b = a + 1 + t;
+        for (int i = b + 1 + sub; i < mp; i += 8) acc += lf[a * mp + i] * lf[b * mp + i];
+      }
+      acc += __shfl_xor(acc, 1, 64);
+      acc += __shfl_xor(acc, 2, 64);
+      acc += __shfl_xor(acc, 4, 64);
+      if (g < LEAF * (LEAF - 1) / 2 && sub == 0) Gl[a * LEAF + b] = acc + (b < mp ? lf[a * mp + b] : 0.0);
+    }
+    __syncthreads();
+    if (tid < LEAF) {
+      const int a = tid;
+      for (int i = 0; i < LEAF; ++i) {
+        double t;
+        if (i < a) t = 0.0;
+        else if (i == a) t = tl[i];
+        else {
+          double s = 0.0;
+          for (int q = a; q < i; ++q) s += Tl[a * LEAF + q] * Gl[q * LEAF + i];
+          t = -tl[i] * s;
+        }
+        Tl[a * LEAF + i] = t;
+      }
+    }
+    __syncthreads();
+    // later panel columns: P(:, c) <- (I - V T^T V^T) P(:, c), one column per wave at a time
+    // (the column is held in kRowRegs registers per lane; rows past mp are clamped)
+    for (int c = c0 + LEAF + wave; c < kBand; c += nw) {
+      double *pc = A + (long long)(j0 + c) * ld + R0;
+      double x[kRowRegs];
+#pragma unroll
+      for (int t = 0; t < kRowRegs; ++t) {
+        const int i = lane + 64 * t;
+        x[t] = pc[i < mp ? i : mp - 1];
+      }
+      double y[LEAF];
+#pragma unroll
+      for (int a = 0; a < LEAF; ++a) y[a] = 0.0;
+#pragma unroll
+      for (int t = 0; t < kRowRegs; ++t) {
+        const int i = lane + 64 * t;
+        if (i < mp) {
+#pragma unroll
+          for (int a = 0; a < LEAF; ++a) {
+            const double va = (i == a) ? 1.0 : (i > a ? lf[a * mp + i] : 0.0);
+            y[a] += va * x[t];
+          }
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < LEAF; ++a) y[a] = wave_sum(y[a]);
+      double z[LEAF];
+#pragma unroll
+      for (int a = 0; a < LEAF; ++a) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q <= a; ++q) s += Tl[q * LEAF + a] * y[q];
+        z[a] = s;
+      }
+#pragma unroll
+      for (int t = 0; t < kRowRegs; ++t) {
+        const int i = lane + 64 * t;
+        if (i < mp) {
+          double s = 0.0;
+#pragma unroll
+          for (int a = 0; a < LEAF; ++a) {
+            const double va = (i == a) ? 1.0 : (i > a ? lf[a * mp + i] : 0.0);
+            s += va * z[a];
+          }
+          pc[i] = x[t] - s;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+}
+
+// One panel of the reduction to band form: QR of A(r:n, j0:j0+b), its T factor (row-major
+// into Tp) and the two-sided update of A(r:n, r:n).  Kept out of line so that the products'
+// per-thread addressing is not held in registers across panels.
+__device__ __noinline__ void band_panel(double *__restrict__ A, int ld, int n, int j0, double *__restrict__ tt,
+                                        double *__restrict__ Tp, double *__restrict__ VW, double *__restrict__ VT,
+                                        double *__restrict__ Kst, double *__restrict__ Gst, double *sh, double *sm,
+                                        double *red) {
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  constexpr int b = kBand;
+  const int r = j0 + b, m = n - r;
+  panel_qr(A, ld, n, j0, tt, sh, sm, red);
+  // V (explicit, unit diagonal) into the first half of the rows of [V | W]
+  for (long long e = tid; e < (long long)m * b; e += nthr) {
+    const int i = (int)(e / b), k = (int)(e % b);
+    double v = 0.0;
+    if (i == k) v = 1.0;
+    else if (i > k) v = A[(long long)(j0 + k) * ld + r + i];
+    VW[(long long)i * 2 * b + k] = v;
+  }
+  __syncthreads();
+  // Gst = -V^T V
+  wg_gemm<G_B_RM | G_OVERWRITE>(Gst, b, VW, 2 * b, VW, 2 * b, b, b, m, sh);
+  // T (row-major): lane a forms row a
+  if (tid < b) {
+    const int a = tid;
+    for (int i = 0; i < b; ++i) {
+      double t;
+      if (i < a) t = 0.0;
+      else if (i == a) t = tt[j0 + i];
+      else {
+        double acc = 0.0;
+        for (int q = a; q < i; ++q) acc -= Tp[a * b + q] * Gst[i * b + q];  // G(q, i) = -Gst(q, i)
+        t = -tt[j0 + i] * acc;
+      }
+      Tp[a * b + i] = t;
+    }
+  }
+  __syncthreads();
+  // VT = -V T
+  wg_gemm<G_A_RM | G_B_RM | G_OVERWRITE | G_C_RM>(VT, b, VW, 2 * b, Tp, b, m, b, b, sh);
+  // X = A22 V T  (into the W half of [V | W])
+  double *A22 = A + (long long)r * ld + r;
+  wg_gemm<G_A_SYM | G_B_RM | G_OVERWRITE | G_C_RM>(VW + b, 2 * b, A22, ld, VT, b, m, b, m, sh);
+  // K = (V T)^T X, then K/2
+  wg_gemm<G_B_RM | G_OVERWRITE>(Kst, b, VT, b, VW + b, 2 * b, b, b, m, sh);
+  for (int e = tid; e < b * b; e += nthr) Kst[e] *= 0.5;
+  __syncthreads();
+  // W = X - V K/2
+  wg_gemm<G_A_RM | G_C_RM | G_LATE_C>(VW + b, 2 * b, VW, 2 * b, Kst, b, m, b, b, sh);
+  // A22 -= V W^T + W V^T (lower triangle)
+  wg_gemm<G_TRANS_B | G_LOWER | G_A_RM | G_B_RM | G_LATE_C>(A22, ld, VW, 2 * b, VW, 2 * b, m, m, 2 * b, sh, -1,
+                                                             b);
+}
+
+// ---------------------------------------------------------------------------------------
+// Stage 1: reduction to band form (see the top of the file).  Dynamic LDS: max(LEAF * nmax,
+// kGemmLds, kQapplyLds) doubles.
+__global__ void __launch_bounds__(256, 2) sy2sb_kernel(int n_clusters, const int *__restrict__ order,
+                                                       double *__restrict__ mat, const long long *__restrict__ mat_off,
+                                                       double *__restrict__ vec, const long long *__restrict__ vec_off,
+                                                       const int *__restrict__ dmax, const int *__restrict__ dim,
+                                                       const int *__restrict__ n_orb) {
+  extern __shared__ double sh[];
+  __shared__ double sm[2 * LEAF * LEAF + 4 * LEAF];
+  __shared__ double red[4 * LEAF];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  constexpr int b = kBand;
+  for (int s = blockIdx.x; s < n_clusters; s += gridDim.x) {
+    const int c = order[s];
+    const int n = dim[c], ld = n;
+    const int M = n_orb[c];
+    double *A = mat + mat_off[c];
+    const VecLayout vl = VecLayout::make(dmax[c]);
+    double *cv = vec + vec_off[c];
+    double *tt = cv + vl.tau, *Tq = cv + vl.u, *X = cv + vl.G0;
+    double *VW = cv + vl.vw, *VT = cv + vl.vt, *Kst = cv + vl.kg, *Gst = Kst + b * b;
+    int j0 = 0;
+    for (; j0 + b < n; j0 += b) {
+      const int r = j0 + b, m = n - r, p = j0 / b;
+      double *Tp = Tq + (long long)p * b * b;
+      if (m < 2) {
+        // a single reflector of length 1: identity
+        __syncthreads();
+        for (int e = tid; e < b * b; e += nthr) Tp[e] = 0.0;
+        if (tid == 0) tt[j0] = 0.0;
+        continue;
+      }
+      band_panel(A, ld, n, j0, tt, Tp, VW, VT, Kst, Gst, sh, sm, red);
+    }
+    // tracked columns: X <- Q1^T X
+    __syncthreads();
+    wg_apply_q(A, ld, n, tt, Tq, false, X, kTrack, 2 * M, true, sh, b);
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Stage 2: bulge chasing (see the top of the file).
+__device__ inline int sweep_steps(int n, int s) { return (s > n - 3) ? 0 : (n - 3 - s) / kBand + 1; }
+
+// One bulge step (sweep s, step j) by one wavefront.  The row lanes 0..len-1 hold rows
+// r0 + i of the step; every load and store below is consecutive in i for a fixed column
+// (coalesced).  Entry (r, c), r >= c, of the band array is Bd[c * LB + r - c].  Offsets are
+// unsigned 32-bit from the array base; indices past the end are clamped on load and never
+// stored (lanes outside the lower triangle of the diagonal block store to their own slot of
+// sink, which keeps those stores free of branches).
+//   (a) reflector from x = B(r0:r1, col);
+//   (b) bulge block B(r0:r1, col+1:r0) <- H B (its column dots through the LDS tile);
+//   (c) diagonal block B(r0:r1, r0:r1) <- H B H (upper half of its rows from the tile) and,
+//       on lanes 32.., the band block below B(r1:r1+b, r0:r1) <- B H.
+// vs, wsv: kBand doubles each and wt: kBand x (kBand + 1) doubles of the wave's LDS; sink:
+// 64 doubles.  Returns tau; the reflector is left in vs.
+__device__ double bulge_step(double *__restrict__ Bd, double *__restrict__ A, int ld, int n, int s, int j,
+                             double *vs, double *wsv, double *wt, double *__restrict__ sink) {
+  constexpr int b = kBand, TS = kBand + 1;
+  constexpr unsigned LB = kBandLd, LD1 = kBandLd - 1;
+  const int lane = threadIdx.x & 63;
+  const int r0 = s + 1 + j * b, col = (j == 0) ? s : r0 - b;
+  const int r1 = min(r0 + b, n), len = r1 - r0;
+  const int nl = r0 - col - 1;            // bulge columns right of x (0 or b - 1)
+  const bool lo = lane < 32;
+  const int i = lo ? lane : lane - 32;
+  const bool isRow = lo && i < len;
+  const unsigned ic = (unsigned)min(i, len - 1);
+  // (a)
+  const unsigned oXL = (unsigned)col * LB + (unsigned)(r0 - col) + ic;  // B(r0+i, col + c) at oXL + c LD1
+  const double x = isRow ? Bd[oXL] : 0.0;
+  const double sigma = wave_sum(isRow && i >= 1 ? x * x : 0.0);
+  const double alpha = __shfl(x, 0, 64);
+  double beta, tau, sc;
+  if (sigma == 0.0) {
+    tau = 0.0;
+    beta = alpha;
+    sc = 0.0;
+  } else {
+    beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+    tau = (beta - alpha) / beta;
+    sc = 1.0 / (alpha - beta);
+  }
+  const double v = isRow ? (i == 0 ? 1.0 : x * sc) : 0.0;
+  if (isRow) {
+    Bd[oXL] = (i == 0) ? beta : 0.0;
+    A[(long long)(n - 1 - s) * ld + j * b + i] = (i == 0) ? tau : v;
+  }
+  if (lo) vs[i] = v;
+  __builtin_amdgcn_wave_barrier();
+  if (tau == 0.0) return 0.0;
+  // (b)
+  if (nl > 0) {
+    double y[b];
+#pragma unroll
+    for (int c = 1; c < b; ++c) y[c] = Bd[oXL + (unsigned)min(c, nl) * LD1];
+    if (lo) {
+#pragma unroll
+      for (int c = 1; c < b; ++c) wt[i * TS + c] = isRow ? v * y[c] : 0.0;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lo && i >= 1) {
+      double d = 0.0;
+#pragma unroll
+      for (int q = 0; q < b; ++q) d += wt[q * TS + i];
+      wsv[i] = tau * d;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (isRow) {
+#pragma unroll
+      for (int c = 1; c < b; ++c) Bd[oXL + (unsigned)c * LD1] = y[c] - v * wsv[c];
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  // (c)
+  {
+    const int nr = min(b, n - r1);
+    const bool isR = !lo && i < nr;
+    const unsigned oW = (unsigned)r0 * LB + ic;  // B(r0+i, r0+k) at oW + k LD1 for k <= i
+    const unsigned oR = (unsigned)r0 * LB + (unsigned)len + (unsigned)min(i, max(nr - 1, 0));
+    const unsigned o = lo ? oW : oR;
+    double row[b];
+#pragma unroll
+    for (int k = 0; k < b; ++k) row[k] = Bd[o + (unsigned)min(k, len - 1) * LD1];
+    // the row lanes park their lower rows in the tile and read back full symmetric rows
+    if (lo) {
+#pragma unroll
+      for (int k = 0; k < b; ++k) wt[i * TS + k] = isRow ? row[k] : 0.0;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (isRow) {
+#pragma unroll
+      for (int k = 0; k < b; ++k) row[k] = wt[(k <= i) ? i * TS + k : k * TS + i];
+    }
+    double pdot = 0.0;
+#pragma unroll
+    for (int k = 0; k < b; ++k) pdot += row[k] * vs[k];
+    const double p = tau * pdot;
+    const double vp = wave_sum(isRow ? v * p : 0.0);
+    const double w = p - 0.5 * tau * vp * v;
+    if (lo) wsv[i] = isRow ? w : 0.0;
+    __builtin_amdgcn_wave_barrier();
+    if (isRow) {
+      double *own = sink + lane;
+#pragma unroll
+      for (int k = 0; k < b; ++k) {
+        const double val = row[k] - v * wsv[k] - w * vs[k];
+        *((k <= i) ? Bd + oW + (unsigned)k * LD1 : own) = val;
+      }
+    } else if (isR) {
+      const double ru = tau * pdot;
+#pragma unroll
+      for (int k = 0; k < b; ++k)
+        if (k < len) Bd[oR + (unsigned)k * LD1] = row[k] - ru * vs[k];
+    }
+  }
+  return tau;
+}
+
+__global__ void __launch_bounds__(256, 2) sb2st_kernel(int n_clusters, const int *__restrict__ order,
+                                                    double *__restrict__ mat, const long long *__restrict__ mat_off,
+                                                    double *__restrict__ vec, const long long *__restrict__ vec_off,
+                                                    const int *__restrict__ dmax, const int *__restrict__ dim,
+                                                    const int *__restrict__ n_orb) {
+  __shared__ double wv[4][2 * kBand];
+  __shared__ double wtile[4][kBand * (kBand + 1)];
+  const int tid = threadIdx.x, wave = tid >> 6, nthr = blockDim.x, nw = nthr >> 6;
+  constexpr int LB = kBandLd;
+  for (int sidx = blockIdx.x; sidx < n_clusters; sidx += gridDim.x) {
+    const int c = order[sidx];
+    const int n = dim[c], ld = n;
+    const int nt = 2 * n_orb[c];
+    double *A = mat + mat_off[c];
+    const VecLayout vl = VecLayout::make(dmax[c]);
+    double *cv = vec + vec_off[c];
+    double *dd = cv + vl.d, *ee = cv + vl.e, *X = cv + vl.G0;
+    double *Bd = cv + vl.vw;  // n x kBandLd (reuses the band-reduction workspace)
+    __syncthreads();
+    for (long long e = tid; e < (long long)n * LB; e += nthr) {
+      const int cc = (int)(e / LB), d = (int)(e % LB);
+      Bd[e] = (d <= kBand && cc + d < n) ? A[(long long)cc * ld + cc + d] : 0.0;
+    }
+    __syncthreads();
+    const int tend = 3 * (n - 3);
+    for (int t = 0; t <= tend; ++t) {
+      const int shi = min(t / 3, n - 3);
+      for (int s = shi - wave; s >= 0; s -= nw) {
+        const int j = t - 3 * s;
+        if (j >= sweep_steps(n, s)) break;
+        bulge_step(Bd, A, ld, n, s, j, wv[wave], wv[wave] + kBand, wtile[wave], cv + vl.kg);
+      }
+      __syncthreads();
+    }
+    for (int i = tid; i < n; i += nthr) {
+      dd[i] = Bd[(long long)i * LB];
+      ee[i] = (i < n - 1) ? Bd[(long long)i * LB + 1] : 0.0;
+    }
+    // tracked columns: X <- Q2^T X
+    wg_apply_q2(A, ld, n, X, kTrack, nt, true);
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+void launch_sy2sb(Plan &p) {
+  const size_t lds =
+      sizeof(double) * std::max({(size_t)LEAF * p.max_dim, (size_t)kGemmLds, (size_t)kQapplyLds});
+  hipLaunchKernelGGL(sy2sb_kernel, dim3(p.workgroups), dim3(kWG), lds, p.stream, p.n_atoms, p.d_order, p.d_mat,
+                     p.d_mat_off, p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb);
+}
+
+void launch_sb2st(Plan &p) {
+  hipLaunchKernelGGL(sb2st_kernel, dim3(p.workgroups), dim3(kWG), 0, p.stream, p.n_atoms, p.d_order, p.d_mat,
+                     p.d_mat_off, p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb);
+}
+
+}  // namespace ldc

@@ -98,8 +98,16 @@ struct Plan {
 };
 
 // vector workspace offsets inside a cluster's double region (n = dimension bound)
+// Band width of the reduction to band form and the row stride of the band array used by
+// the bulge chasing (lower band plus bulge: 2 kBand + 1 diagonals, padded to even).
+constexpr int kBand = 32;
+constexpr int kBandLd = 2 * kBand + 2;
+// Largest reduced cluster dimension (the panel QR holds 8 columns of the panel in LDS and a
+// column in 15 registers per lane).
+constexpr int kMaxDimTri = 960;
+
 struct VecLayout {
-  long long d, e, tau, lam, w, G0, G1, u, y0, y1, dc;
+  long long d, e, tau, lam, w, G0, G1, u, y0, y1, vw, vt, kg, dc;
   __host__ __device__ static VecLayout make(int n) {
     VecLayout v;
     long long o = 0;
@@ -113,6 +121,12 @@ struct VecLayout {
     v.u = o; o += (long long)(n + 32) * 32;  // compact-WY T factors, one 32 x 32 block per panel
     v.y0 = o; o += (long long)n * kMaxOrb;
     v.y1 = o; o += (long long)n * kMaxOrb;
+    // reduction to band form: [V | W] (n x 2 kBand, row-major), -V T (n x kBand, row-major),
+    // K and G (kBand x kBand each); the band array of the bulge chasing (n x kBandLd) reuses
+    // this space once the band form is complete
+    v.vw = o; o += (long long)n * 2 * kBand;
+    v.vt = o; o += (long long)n * kBand;
+    v.kg = o; o += 2LL * kBand * kBand;
     v.dc = o;
     return v;
   }
@@ -140,7 +154,8 @@ void launch_lno_eig(Plan &p, const double *d_S, double lambda_th, int k_min, int
 void launch_gather(Plan &p, const double *d_H, const double *d_S);
 void launch_potrf(Plan &p);
 void launch_sygst(Plan &p);
-void launch_sytrd(Plan &p);
+void launch_sy2sb(Plan &p);
+void launch_sb2st(Plan &p);
 void launch_stedc(Plan &p);
 void launch_mu_init(Plan &p, double kT);
 void launch_mu_step(Plan &p, double n_electrons, double kT, double g);

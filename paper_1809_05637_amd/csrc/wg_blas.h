@@ -10,20 +10,32 @@ constexpr int GT = 64;    // output tile edge
 constexpr int GK = 32;    // K chunk
 constexpr int GPAD = 1;   // LDS padding (doubles)
 
-// LDS needed by wg_gemm_sub: 2 * GK * (GT + GPAD) doubles.
+// LDS needed by wg_gemm: 2 * GK * (GT + GPAD) doubles.
 constexpr int kGemmLds = 2 * GK * (GT + GPAD);
 
 typedef double ldc_double4 __attribute__((ext_vector_type(4)));
 
-// C[m x n] -= A[m x k] * op(B), op(B) = B^T (B: n x k) if TRANS_B else B (B: k x n).
-// LOWER: only output tiles that touch the lower triangle (tile row >= tile column) are
-// computed (the strictly-upper part of diagonal tiles is computed too and must be unused).
-// A_RM / B_RM: A (resp. B) stored row-major with row stride lda (ldb) instead of
-// column-major with leading dimension lda (ldb).  OVERWRITE: C = -A op(B) (C is not read).
+// Operand layouts and options of wg_gemm (bit flags).
+enum : unsigned {
+  G_TRANS_B = 1u,     // op(B) = B^T (B: n x k); otherwise op(B) = B (B: k x n)
+  G_LOWER = 2u,       // only output tiles touching the lower triangle (tile row >= tile column)
+  G_A_RM = 4u,        // A row-major (row stride lda); otherwise column-major (leading dimension lda)
+  G_B_RM = 8u,        // B row-major (row stride ldb)
+  G_OVERWRITE = 16u,  // C = -A op(B) (C is not read)
+  G_LATE_C = 32u,     // read C at the store instead of prefetching it (fewer registers)
+  G_C_RM = 64u,       // C row-major (row stride ldc)
+  G_A_SYM = 128u,     // A is symmetric, held in the lower triangle of a column-major array
+};
+
+// C[m x n] -= A[m x k] * op(B)   (G_OVERWRITE: C = -A op(B)).
+// G_LOWER: the strictly-upper part of diagonal tiles is computed too and must be unused.
 // a_diag >= 0: A is zero above its a_diag-th superdiagonal (A[r][kk] = 0 for kk > r + a_diag),
 // so each tile row only runs over the K range that can be nonzero.
 // 0 < b_rot < k: the K index of op(B) is rotated, op(B)[kk][c] = op(B')[(kk + b_rot) mod k][c];
 // with A = [V | W] row-major and B = A this forms V W^T + W V^T in one pass.
+// G_A_SYM: A[r][kk] = A_lo[max(r,kk)][min(r,kk)]; a K chunk wholly right of the tile's rows
+// is read along rows of the stored lower triangle, the others down its columns (coalesced
+// except in the chunks that cross the diagonal).
 //
 // 64 x 64 output tiles; each of the 4 waves owns a 32 x 32 quarter as 2 x 2 blocks of
 // v_mfma_f64_16x16x4 (FP64 matrix cores).  Operands are swapped so that each output
@@ -31,10 +43,15 @@ typedef double ldc_double4 __attribute__((ext_vector_type(4)));
 // the instruction's A operand takes op(B) (lane l: op(B)[k0 + l/16][c0 + l%16]) and its B
 // operand takes A (lane l: A[r0 + l%16][k0 + l/16]); register r of lane l then holds
 // C[r0 + l%16][c0 + 4 r + l/16].  The next K chunk of A and op(B) is fetched into registers
-// while the current one is multiplied; after the last chunk the same registers fetch C.
-template <bool TRANS_B, bool LOWER, bool A_RM = false, bool B_RM = false, bool OVERWRITE = false>
-__device__ void wg_gemm_sub(double *C, int ldc, const double *A, int lda, const double *B, int ldb, int m, int n,
-                            int k, double *lds, int a_diag = -1, int b_rot = 0) {
+// while the current one is multiplied; after the last chunk the same registers fetch C
+// (unless G_LATE_C).
+template <unsigned F>
+__device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const double *B, int ldb, int m, int n, int k,
+                        double *lds, int a_diag = -1, int b_rot = 0) {
+  constexpr bool TRANS_B = F & G_TRANS_B, LOWER = F & G_LOWER, A_RM = F & G_A_RM, B_RM = F & G_B_RM;
+  constexpr bool OVERWRITE = F & G_OVERWRITE, PREFETCH_C = !(F & G_LATE_C), C_RM = F & G_C_RM;
+  constexpr bool A_SYM = F & G_A_SYM;
+  static_assert(!(A_SYM && A_RM), "a symmetric A is stored column-major");
   constexpr int LS = GT + GPAD;
   constexpr int PER = GT * GK / 256;  // staged elements per thread and operand (8)
   double *As = lds;                   // [GK][LS]
@@ -43,25 +60,48 @@ __device__ void wg_gemm_sub(double *C, int ldc, const double *A, int lda, const 
   const int wr = wave >> 1, wc = wave & 1;
   const int li = lane & 15, lk = lane >> 4;
   const int mt = (m + GT - 1) / GT, nt = (n + GT - 1) / GT;
-  // Staging: element q of this thread's share of a 64 x GK tile sits at (e0 + q STEP) along
-  // the 64 edge and ek along K, or at e0 along the edge and (ek + q STEP) along K; the
-  // faster-running index follows the operand's memory layout (coalesced loads).  Offsets
-  // are 32-bit (a cluster matrix has far fewer than 2^31 elements).
-  constexpr bool A_KFAST = A_RM;
+  // Staging: element q of this thread's share of a 64 x GK tile sits at (e + q STEP) along
+  // the 64 edge and kk along K (K-fast layout), or at e along the edge and (kk + q STEP)
+  // along K (edge-fast layout); the faster-running index follows the operand's memory
+  // layout (coalesced loads).  Offsets are 32-bit (a cluster matrix has far fewer than 2^31
+  // elements).
   constexpr bool B_KFAST = !((TRANS_B && !B_RM) || (!TRANS_B && B_RM));
-  const int a_e = A_KFAST ? tid / GK : tid % GT, a_k = A_KFAST ? tid % GK : tid / GT;
-  const int b_e = B_KFAST ? tid / GK : tid % GT, b_k = B_KFAST ? tid % GK : tid / GT;
-  constexpr int A_STEP = A_KFAST ? 256 / GK : 256 / GT;
-  constexpr int B_STEP = B_KFAST ? 256 / GK : 256 / GT;
-  // element (row, kk) of A and (col, kk) of op(B) in memory
+  const int ef = tid % GT, kf = tid / GT;   // edge-fast position
+  const int ek = tid / GK, kk0 = tid % GK;  // K-fast position
+  constexpr int STEP_E = 256 / GT, STEP_K = 256 / GK;
+  const int b_e = B_KFAST ? ek : ef, b_k = B_KFAST ? kk0 : kf;
+  constexpr int B_STEP = B_KFAST ? STEP_K : STEP_E;
   const int a_rs = A_RM ? lda : 1, a_ks = A_RM ? 1 : lda;
   const int b_cs = (TRANS_B != B_RM) ? 1 : ldb, b_ks = (TRANS_B != B_RM) ? ldb : 1;
-  auto fetch = [&](int r0, int c0, int k0, double *ra, double *rb) {
+  // layout of an A chunk: 1 = K-fast, 0 = edge-fast
+  auto a_mode_of = [&](int r0, int k0) -> int {
+    if (A_SYM) return (k0 >= r0 + GT) ? 1 : 0;
+    return A_RM ? 1 : 0;
+  };
+  auto fetchA = [&](int r0, int k0, int mode, double *ra) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int gr = r0 + a_e + (A_KFAST ? q * A_STEP : 0), gk = k0 + a_k + (A_KFAST ? 0 : q * A_STEP);
-      ra[q] = (gr < m && gk < k) ? A[gr * a_rs + gk * a_ks] : 0.0;
+      int gr, gk;
+      if (mode) {
+        gr = r0 + ek + q * STEP_K;
+        gk = k0 + kk0;
+      } else {
+        gr = r0 + ef;
+        gk = k0 + kf + q * STEP_E;
+      }
+      double val = 0.0;
+      if (gr < m && gk < k) {
+        if (A_SYM) {
+          const int hi = gr > gk ? gr : gk, lo = gr > gk ? gk : gr;
+          val = A[lo * lda + hi];
+        } else {
+          val = A[gr * a_rs + gk * a_ks];
+        }
+      }
+      ra[q] = val;
     }
+  };
+  auto fetchB = [&](int c0, int k0, double *rb) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int gc = c0 + b_e + (B_KFAST ? q * B_STEP : 0);
@@ -74,14 +114,19 @@ __device__ void wg_gemm_sub(double *C, int ldc, const double *A, int lda, const 
       rb[q] = in ? B[gc * b_cs + gk * b_ks] : 0.0;
     }
   };
-  auto stage = [&](const double *ra, const double *rb) {
+  auto stage = [&](int mode, const double *ra, const double *rb) {
+    if (mode) {
 #pragma unroll
-    for (int q = 0; q < PER; ++q)
-      As[(a_k + (A_KFAST ? 0 : q * A_STEP)) * LS + a_e + (A_KFAST ? q * A_STEP : 0)] = ra[q];
+      for (int q = 0; q < PER; ++q) As[kk0 * LS + ek + q * STEP_K] = ra[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) As[(kf + q * STEP_E) * LS + ef] = ra[q];
+    }
 #pragma unroll
     for (int q = 0; q < PER; ++q)
       Bs[(b_k + (B_KFAST ? 0 : q * B_STEP)) * LS + b_e + (B_KFAST ? q * B_STEP : 0)] = rb[q];
   };
+  auto cidx = [&](int gr, int gc) { return C_RM ? gr * ldc + gc : gc * ldc + gr; };
 
   for (int tile = 0; tile < mt * nt; ++tile) {
     const int ti = tile / nt, tj = tile % nt;
@@ -94,15 +139,21 @@ __device__ void wg_gemm_sub(double *C, int ldc, const double *A, int lda, const 
       for (int b = 0; b < 2; ++b) acc[a][b] = ldc_double4{0.0, 0.0, 0.0, 0.0};
     const int kend = (a_diag >= 0) ? min(k, r0 + GT + a_diag) : k;
     double ra[PER], rb[PER];
-    if (kend > 0) fetch(r0, c0, 0, ra, rb);
+    int amode = a_mode_of(r0, 0);
+    if (kend > 0) {
+      fetchA(r0, 0, amode, ra);
+      fetchB(c0, 0, rb);
+    }
     double cold[2][2][4];
     for (int k0 = 0; k0 < kend; k0 += GK) {
       __syncthreads();
-      stage(ra, rb);
+      stage(amode, ra, rb);
       __syncthreads();
       if (k0 + GK < kend) {
-        fetch(r0, c0, k0 + GK, ra, rb);
-      } else if (!OVERWRITE) {
+        amode = a_mode_of(r0, k0 + GK);
+        fetchA(r0, k0 + GK, amode, ra);
+        fetchB(c0, k0 + GK, rb);
+      } else if (!OVERWRITE && PREFETCH_C) {
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -110,7 +161,7 @@ __device__ void wg_gemm_sub(double *C, int ldc, const double *A, int lda, const 
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               const int gr = r0 + wr * 32 + a * 16 + li, gc = c0 + wc * 32 + b * 16 + 4 * r + lk;
-              cold[a][b][r] = (gr < m && gc < n) ? C[gc * ldc + gr] : 0.0;
+              cold[a][b][r] = (gr < m && gc < n) ? C[cidx(gr, gc)] : 0.0;
             }
       }
 #pragma unroll
@@ -137,8 +188,9 @@ __device__ void wg_gemm_sub(double *C, int ldc, const double *A, int lda, const 
         for (int r = 0; r < 4; ++r) {
           const int gc = c0 + wc * 32 + b * 16 + 4 * r + lk;
           if (gr < m && gc < n) {
-            if (OVERWRITE) C[gc * ldc + gr] = -acc[a][b][r];
-            else C[gc * ldc + gr] = cold[a][b][r] - acc[a][b][r];
+            if (OVERWRITE) C[cidx(gr, gc)] = -acc[a][b][r];
+            else if (PREFETCH_C) C[cidx(gr, gc)] = cold[a][b][r] - acc[a][b][r];
+            else C[cidx(gr, gc)] -= acc[a][b][r];
           }
         }
       }

@@ -1,8 +1,9 @@
-// Products with the orthogonal factor Q = H_0 H_1 ... H_{n-2} of the Householder
-// tridiagonalization, H_k = I - tau_k v_k v_k^T, v_k(0:k) = 0, v_k(k+1) = 1, v_k(k+2:) stored
-// in A(k+2:, k) (column-major, leading dimension ld).  Reflectors are grouped in panels of
-// QP columns; a panel's product is I - V T V^T with T upper triangular (compact WY form):
-// T(a,a) = tau_a, T(0:a, a) = -tau_a T(0:a, 0:a) (V(:, 0:a)^T v_a).
+// Products with an orthogonal factor Q = H_0 H_1 ... H_{n-1-sh} stored as Householder
+// reflectors below a band of width sh: H_k = I - tau_k v_k v_k^T, v_k(0:k+sh) = 0,
+// v_k(k+sh) = 1, v_k(k+sh+1:) stored in A(k+sh+1:, k) (column-major, leading dimension ld).
+// sh = 1 is the one-stage tridiagonalization, sh = b the reduction to band form.  Reflectors
+// are grouped in panels of QP columns; a panel's product is I - V T V^T with T upper
+// triangular (compact WY form): T(a,a) = tau_a, T(0:a, a) = -tau_a T(0:a, 0:a) (V(:, 0:a)^T v_a).
 #pragma once
 
 #include "dev_common.h"
@@ -18,10 +19,11 @@ constexpr int QS = QP + 1;  // LDS row stride
 constexpr int kQapplyLds = QCH * QS + 3 * QP * QS + QCH * (QXC + 1);
 
 // X (n rows, ncol <= QXC columns, row-major with row stride ldx) <- Q^T X (transpose) or
-// Q X.  With make_T the panels' T factors are formed and stored in Tq (QP*QP per panel);
-// otherwise the stored ones are used.  Whole workgroup (256 threads); lds: kQapplyLds.
+// Q X.  With make_T the panels' T factors are formed and stored in Tq (QP*QP per panel,
+// row-major); otherwise the stored ones are used.  Whole workgroup (256 threads); lds:
+// kQapplyLds.
 __device__ void wg_apply_q(const double *__restrict__ A, int ld, int n, const double *__restrict__ tau, double *Tq,
-                           bool make_T, double *X, int ldx, int ncol, bool transpose, double *lds) {
+                           bool make_T, double *X, int ldx, int ncol, bool transpose, double *lds, int sh = 1) {
   const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, wave = tid >> 6;
   double *Vc = lds;              // [QCH][QS]
   double *G = Vc + QCH * QS;     // [QP][QS]  V^T V
@@ -29,24 +31,25 @@ __device__ void wg_apply_q(const double *__restrict__ A, int ld, int n, const do
   double *Y = T + QP * QS;       // [QP][QS]  V^T X, then T' V^T X
   double *Xc = Y + QP * QS;      // [QCH][QXC+1] rows of X
   constexpr int NACC = (QP * QP + QP * QXC) / 256;  // entries per thread (8)
-  const int npan = (n - 1 + QP - 1) / QP;           // reflectors 0..n-2
+  const int nref = n - sh;                          // reflectors 0..n-1-sh
+  const int npan = nref > 0 ? (nref + QP - 1) / QP : 0;
   for (int pi = 0; pi < npan; ++pi) {
     const int p = transpose ? pi : (npan - 1 - pi);
-    const int p0 = p * QP, nbp = min(QP, n - 1 - p0);
+    const int p0 = p * QP, nbp = min(QP, nref - p0);
     const int nG = make_T ? QP * QP : 0;
     const int nE = nG + QP * ncol;
     double acc[NACC];
 #pragma unroll
     for (int q = 0; q < NACC; ++q) acc[q] = 0.0;
-    for (int r0 = p0 + 1; r0 < n; r0 += QCH) {
+    for (int r0 = p0 + sh; r0 < n; r0 += QCH) {
       __syncthreads();
       for (int e = tid; e < QCH * QP; e += nthr) {
         const int rr = e % QCH, t = e / QCH;
         const int r = r0 + rr, k = p0 + t;
         double val = 0.0;
         if (t < nbp && r < n) {
-          if (r == k + 1) val = 1.0;
-          else if (r > k + 1) val = A[(long long)k * ld + r];
+          if (r == k + sh) val = 1.0;
+          else if (r > k + sh) val = A[(long long)k * ld + r];
         }
         Vc[rr * QS + t] = val;
       }
@@ -128,15 +131,15 @@ __device__ void wg_apply_q(const double *__restrict__ A, int ld, int n, const do
     }
     __syncthreads();
     // X(r, :) -= V(r, :) Y, with V staged in LDS by chunks of QCH rows
-    for (int r0 = p0 + 1; r0 < n; r0 += QCH) {
+    for (int r0 = p0 + sh; r0 < n; r0 += QCH) {
       __syncthreads();
       for (int e = tid; e < QCH * QP; e += nthr) {
         const int rr = e % QCH, t = e / QCH;
         const int r = r0 + rr, k = p0 + t;
         double val = 0.0;
         if (t < nbp && r < n) {
-          if (r == k + 1) val = 1.0;
-          else if (r > k + 1) val = A[(long long)k * ld + r];
+          if (r == k + sh) val = 1.0;
+          else if (r > k + sh) val = A[(long long)k * ld + r];
         }
         Vc[rr * QS + t] = val;
       }
@@ -148,6 +151,51 @@ __device__ void wg_apply_q(const double *__restrict__ A, int ld, int n, const do
 #pragma unroll 8
         for (int t = 0; t < QP; ++t) s += Vc[rr * QS + t] * Y[t * QS + q];
         X[(long long)(r0 + rr) * ldx + q] -= s;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// X (n rows, ncol <= 32 columns, row-major, row stride ldx) <- Q2^T X (transpose) or Q2 X for
+// the bulge-chasing reflectors of the band-to-tridiagonal step: sweep s holds the reflectors
+// of rows [s + 1 + j b, s + 1 + j b + len), len = min(b, n - r0), b = kBand, stored in
+// column n - 1 - s of A above the diagonal at rows j b.. (tau first, then v(1:len)); the
+// steps of one sweep act on disjoint rows, so each sweep is one parallel step (16 or 32 lanes
+// per reflector, one column each), and Q2 = (sweep 0) (sweep 1) ... in that order.
+__device__ void wg_apply_q2(const double *__restrict__ A, int ld, int n, double *X, int ldx, int ncol,
+                            bool transpose) {
+  constexpr int b = kBand;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int gsh = ncol > 16 ? 5 : 4;
+  const int grp = tid >> gsh, q = tid & ((1 << gsh) - 1), ngrp = nthr >> gsh;
+  const int nsw = n - 2;  // sweeps 0 .. n-3
+  for (int it = 0; it < nsw; ++it) {
+    const int s = transpose ? it : nsw - 1 - it;
+    const int nst = (n - 3 - s) / b + 1;
+    for (int j = grp; j < nst; j += ngrp) {
+      const int r0 = s + 1 + j * b, len = min(b, n - r0);
+      const double *vp = A + (long long)(n - 1 - s) * ld + j * b;
+      const double *xp = X + (long long)r0 * ldx + (q < ncol ? q : ncol - 1);
+      double vv[b], xv[b];
+      // clamped unconditional loads (all in flight together); entries past len are masked
+#pragma unroll
+      for (int i = 0; i < b; ++i) {
+        const int ii = min(i, len - 1);
+        const double t = vp[ii];
+        vv[i] = (i < len) ? t : 0.0;
+        xv[i] = xp[(long long)ii * ldx];
+      }
+      const double tau = vv[0];
+      vv[0] = 1.0;
+      double d = 0.0;
+#pragma unroll
+      for (int i = 0; i < b; ++i) d += vv[i] * xv[i];
+      d *= tau;
+      if (q < ncol) {
+#pragma unroll
+        for (int i = 0; i < b; ++i)
+          if (i < len) X[(long long)(r0 + i) * ldx + q] = xv[i] - d * vv[i];
       }
     }
     __syncthreads();
