@@ -52,16 +52,17 @@ __device__ void secular_root(const double *__restrict__ d, const double *__restr
   double tau = 0.5 * (a + b);
   for (int it = 0; it < 100; ++it) {
     double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
-    for (int j = 0; j < k; ++j) {
-      const double diff = (d[j] - dorig) - tau;
-      const double term = z[j] * z[j] / diff;
-      if (j <= t) {
-        psi += term;
-        dpsi += term / diff;
-      } else {
-        phi += term;
-        dphi += term / diff;
-      }
+    for (int j = 0; j <= t; ++j) {
+      const double r = 1.0 / ((d[j] - dorig) - tau);
+      const double term = z[j] * z[j] * r;
+      psi += term;
+      dpsi += term * r;
+    }
+    for (int j = t + 1; j < k; ++j) {
+      const double r = 1.0 / ((d[j] - dorig) - tau);
+      const double term = z[j] * z[j] * r;
+      phi += term;
+      dphi += term * r;
     }
     const double g = rinv + psi + phi;
     const double err = 8.0 * (fabs(psi) + fabs(phi) + rinv) + fabs(tau) * (dpsi + dphi);
@@ -98,10 +99,43 @@ __device__ void secular_root(const double *__restrict__ d, const double *__restr
   *tau_out = tau;
 }
 
+// Total order on doubles (IEEE order for numbers; NaNs at the ends): sorting and ranking by
+// this key gives a permutation whatever the data.
+__device__ inline long long dc_key(double x) {
+  const long long b = __double_as_longlong(x);
+  return b >= 0 ? b : (b ^ 0x7fffffffffffffffLL);
+}
+
+// LDS copies of the current level's merge data (n entries each), read many times by the
+// secular solver, the Loewner formula, the norms, the output ranking and the row transform.
+struct DcLds {
+  double *d, *z, *zt, *tau, *nrm, *Ds, *g;
+  int *orig, *kpos, *jinv;
+  static constexpr int kBytesPerRow = 6 * sizeof(double) + 3 * sizeof(int);
+  static constexpr int kChunk = 32;  // rows of G1 staged per step of the row transform
+  static constexpr int kFixedBytes = kChunk * kTrack * sizeof(double);
+};
+
+__device__ inline DcLds dc_lds(void *base, int nmax) {
+  DcLds L;
+  double *b = static_cast<double *>(base);
+  L.d = b;
+  L.z = b + nmax;
+  L.zt = b + 2 * nmax;
+  L.tau = b + 3 * nmax;
+  L.nrm = b + 4 * nmax;
+  L.Ds = b + 5 * nmax;
+  L.g = b + 6 * nmax;  // kChunk x kTrack
+  L.orig = reinterpret_cast<int *>(b + 6 * nmax + DcLds::kChunk * kTrack);
+  L.kpos = L.orig + nmax;
+  L.jinv = L.kpos + nmax;
+  return L;
+}
+
 // Forward pass for one cluster (whole workgroup).  In: d, e (T), G0 rows = tracked X with
 // nx columns.  Out: lam ascending, G0 rows = Z^T X (columns 0..nx-1), records.
 __device__ void dc_forward(int n, const double *__restrict__ dd, const double *__restrict__ ee, int nx, DcWs ws,
-                           DevStatus *st, int cid) {
+                           DcLds S, DevStatus *st, int cid) {
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int Fc = nx, Lc = nx + 1, nt = nx + 2;
   double *lam = ws.lam, *G0 = ws.G0, *G1 = ws.G1;
@@ -120,7 +154,53 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
     const int size = 1 << l, span = 2 * size;
     const DcRec R = dc_rec(ws.dcd, ws.dci, n, l);
     const int nmerge = (n + span - 1) / span;
-    // Phase A: one thread per merge -- sort, normalise z, deflate
+    // Phase A0: stage the children's eigenvalues and z entries (z = last row of the left
+    // child's eigenvectors, sign(beta) x first row of the right child's: tracked columns Lc,
+    // Fc) in LDS and clear those columns.  S.tau, S.nrm and S.zt serve as scratch here; they
+    // are filled with their own data in the later phases.
+    for (int q = tid; q < n; q += nthr) {
+      const int lo = q - q % span, m = lo + size, hi = min(lo + span, n);
+      if (m >= hi) continue;
+      const double sg = ee[m - 1] >= 0.0 ? 1.0 : -1.0;
+      S.tau[q] = lam[q];
+      const int col = q < m ? Lc : Fc;
+      S.nrm[q] = (q < m ? 1.0 : sg) * G0[(long long)q * kTrack + col];
+      G0[(long long)q * kTrack + col] = 0.0;
+    }
+    __syncthreads();
+    // Phase A1: merge the two sorted children by rank (binary search in the other child;
+    // the left child's element first on equal keys).  Keys are a total order on the doubles,
+    // so the ranks form a permutation for any data.
+    for (int q = tid; q < n; q += nthr) {
+      const int lo = q - q % span, m = lo + size, hi = min(lo + span, n);
+      if (m >= hi) continue;
+      const long long key = dc_key(S.tau[q]);
+      int a, b2;
+      const bool left = q < m;
+      if (left) {  // right elements with key < key(x)
+        a = m;
+        b2 = hi;
+        while (a < b2) {
+          const int c = (a + b2) >> 1;
+          if (dc_key(S.tau[c]) < key) a = c + 1;
+          else b2 = c;
+        }
+      } else {  // left elements with key <= key(y)
+        a = lo;
+        b2 = m;
+        while (a < b2) {
+          const int c = (a + b2) >> 1;
+          if (dc_key(S.tau[c]) <= key) a = c + 1;
+          else b2 = c;
+        }
+      }
+      const int pos = left ? (q - lo) + (a - m) : (q - m) + (a - lo);
+      R.perm[lo + pos] = q - lo;
+      S.Ds[lo + pos] = S.tau[q];
+      S.zt[lo + pos] = S.nrm[q];
+    }
+    __syncthreads();
+    // Phase A2: one thread per merge -- normalise z, deflate (sequential chain on LDS data)
     for (int mi = tid; mi < nmerge; mi += nthr) {
       const int lo = mi * span, m = lo + size, hi = min(lo + span, n);
       if (m >= hi) {
@@ -128,38 +208,27 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
         continue;
       }
       const int k = hi - lo;
-      const double beta = ee[m - 1];
-      double rho = fabs(beta);
-      const double sg = beta >= 0.0 ? 1.0 : -1.0;
-      int i1 = lo, i2 = m;
+      double rho = fabs(ee[m - 1]);
+      double *Ds = S.Ds + lo, *zs = S.zt + lo;
       double zn2 = 0.0, dmaxabs = 0.0;
       for (int p = 0; p < k; ++p) {
-        int take;
-        if (i2 >= hi || (i1 < m && lam[i1] <= lam[i2])) take = i1++;
-        else take = i2++;
-        R.perm[lo + p] = take - lo;
-        const double dv = lam[take];
-        const double zv = take < m ? G0[(long long)take * kTrack + Lc] : sg * G0[(long long)take * kTrack + Fc];
-        ws.Ds[lo + p] = dv;
-        ws.zs[lo + p] = zv;
-        zn2 += zv * zv;
-        dmaxabs = fmax(dmaxabs, fabs(dv));
+        zn2 += zs[p] * zs[p];
+        dmaxabs = fmax(dmaxabs, fabs(Ds[p]));
       }
-      for (int r = lo; r < m; ++r) G0[(long long)r * kTrack + Lc] = 0.0;
-      for (int r = m; r < hi; ++r) G0[(long long)r * kTrack + Fc] = 0.0;
       const double zinv = 1.0 / sqrt(zn2);
       double zmax = 0.0;
       for (int p = 0; p < k; ++p) {
-        ws.zs[lo + p] *= zinv;
-        zmax = fmax(zmax, fabs(ws.zs[lo + p]));
+        zs[p] *= zinv;
+        zmax = fmax(zmax, fabs(zs[p]));
       }
       rho *= zn2;
       const double tol = 8.0 * kEps * fmax(dmaxabs, zmax);
       int kp = 0, nd = 0, nrot = 0, pj = -1;
       for (int j = 0; j < k; ++j) {
-        const double zj = ws.zs[lo + j];
+        const double zj = zs[j];
         if (rho * fabs(zj) <= tol) {
           R.kpos[hi - 1 - nd] = j;
+          S.kpos[hi - 1 - nd] = j;
           ++nd;
           continue;
         }
@@ -167,46 +236,52 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
           pj = j;
           continue;
         }
-        double s_ = ws.zs[lo + pj], c_ = zj;
+        double s_ = zs[pj], c_ = zj;
         const double tau = hypot(c_, s_);
-        const double tdiff = ws.Ds[lo + j] - ws.Ds[lo + pj];
+        const double tdiff = Ds[j] - Ds[pj];
         c_ /= tau;
         s_ = -s_ / tau;
         if (fabs(tdiff * c_ * s_) <= tol) {
-          ws.zs[lo + j] = tau;
-          ws.zs[lo + pj] = 0.0;
+          zs[j] = tau;
+          zs[pj] = 0.0;
           R.ra[lo + nrot] = pj;
           R.rb[lo + nrot] = j;
           R.rc[lo + nrot] = c_;
           R.rs[lo + nrot] = s_;
           ++nrot;
-          const double dp = ws.Ds[lo + pj], dj = ws.Ds[lo + j];
+          const double dp = Ds[pj], dj = Ds[j];
           const double t1 = dp * c_ * c_ + dj * s_ * s_;
-          ws.Ds[lo + j] = dp * s_ * s_ + dj * c_ * c_;
-          ws.Ds[lo + pj] = t1;
+          Ds[j] = dp * s_ * s_ + dj * c_ * c_;
+          Ds[pj] = t1;
           R.kpos[hi - 1 - nd] = pj;
+          S.kpos[hi - 1 - nd] = pj;
           ++nd;
         } else {
           R.kpos[lo + kp] = pj;
+          S.kpos[lo + kp] = pj;
           ++kp;
         }
         pj = j;
       }
       if (pj >= 0) {
         R.kpos[lo + kp] = pj;
+        S.kpos[lo + kp] = pj;
         ++kp;
       }
       R.cnt[lo] = kp;
       R.cnt[lo + 1] = nrot;
       ws.rhov[lo] = rho;
       for (int t = 0; t < kp; ++t) {
-        const int pos = R.kpos[lo + t];
-        R.dK[lo + t] = ws.Ds[lo + pos];
-        ws.zK[lo + t] = ws.zs[lo + pos];
+        const int pos = S.kpos[lo + t];
+        const double dv = Ds[pos], zv = zs[pos];
+        R.dK[lo + t] = dv;
+        S.d[lo + t] = dv;
+        S.z[lo + t] = zv;
       }
+      for (int t = 0; t < k; ++t) S.jinv[lo + S.kpos[lo + t]] = t;
     }
     __syncthreads();
-    // Phase A1: G1 = rows of G0 in sorted order
+    // Phase A3: G1 = rows of G0 in sorted order
     for (long long e = tid; e < (long long)n * nt; e += nthr) {
       const int q = (int)(e / nt), cc = (int)(e % nt);
       const int lo = q - q % span;
@@ -214,7 +289,7 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
       G1[(long long)q * kTrack + cc] = G0[(long long)(lo + R.perm[q]) * kTrack + cc];
     }
     __syncthreads();
-    // Phase A2: deflation rotations, one thread per (merge, column)
+    // Phase A4: deflation rotations, one thread per (merge, column)
     for (int e = tid; e < nmerge * nt; e += nthr) {
       const int mi = e / nt, cc = e % nt;
       const int lo = mi * span;
@@ -239,9 +314,11 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
       if (kp < 0 || t >= kp) continue;
       int o;
       double tau;
-      secular_root(R.dK + lo, ws.zK + lo, kp, ws.rhov[lo], t, &o, &tau);
+      secular_root(S.d + lo, S.z + lo, kp, ws.rhov[lo], t, &o, &tau);
       R.orig[lo + t] = o;
       R.tau[lo + t] = tau;
+      S.orig[lo + t] = o;
+      S.tau[lo + t] = tau;
     }
     __syncthreads();
     // Phase C: Loewner z
@@ -250,16 +327,20 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
       const int kp = R.cnt[lo];
       const int j = q - lo;
       if (kp < 0 || j >= kp) continue;
-      const double *dK = R.dK + lo;
+      const double *dK = S.d + lo;
+      const int *org = S.orig + lo;
+      const double *tu = S.tau + lo;
       const double dj = dK[j];
       const double rho = ws.rhov[lo];
-      double prod = -((dj - dK[R.orig[lo + j]]) - R.tau[lo + j]) / rho;
+      double prod = -((dj - dK[org[j]]) - tu[j]) / rho;
       for (int i = 0; i < kp; ++i) {
         if (i == j) continue;
-        const double num = (dj - dK[R.orig[lo + i]]) - R.tau[lo + i];
+        const double num = (dj - dK[org[i]]) - tu[i];
         prod *= num / (dj - dK[i]);
       }
-      R.zt[lo + j] = copysign(sqrt(fmax(prod, 0.0)), ws.zK[lo + j]);
+      const double ztj = copysign(sqrt(fmax(prod, 0.0)), S.z[lo + j]);
+      R.zt[lo + j] = ztj;
+      S.zt[lo + j] = ztj;
     }
     __syncthreads();
     // Phase D: eigenvector norms
@@ -268,14 +349,16 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
       const int kp = R.cnt[lo];
       const int t = q - lo;
       if (kp < 0 || t >= kp) continue;
-      const double *dK = R.dK + lo;
-      const double dorig = dK[R.orig[lo + t]], tau = R.tau[lo + t];
+      const double *dK = S.d + lo, *zt = S.zt + lo;
+      const double dorig = dK[S.orig[lo + t]], tau = S.tau[lo + t];
       double s2 = 0.0;
       for (int j = 0; j < kp; ++j) {
-        const double u = R.zt[lo + j] / ((dK[j] - dorig) - tau);
+        const double u = zt[j] / ((dK[j] - dorig) - tau);
         s2 += u * u;
       }
-      R.nrm[lo + t] = sqrt(s2);
+      const double nv = sqrt(s2);
+      R.nrm[lo + t] = nv;
+      S.nrm[lo + t] = nv;
     }
     __syncthreads();
     // Phase F: output order (ascending eigenvalue; ties by element index)
@@ -286,46 +369,80 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
       const int hi = min(lo + span, n), k = hi - lo;
       const int e = q - lo;
       auto val = [&](int x) -> double {
-        return x < kp ? R.dK[lo + R.orig[lo + x]] + R.tau[lo + x] : ws.Ds[lo + R.kpos[lo + x]];
+        return x < kp ? S.d[lo + S.orig[lo + x]] + S.tau[lo + x] : S.Ds[lo + S.kpos[lo + x]];
       };
       const double ve = val(e);
+      const long long ke = dc_key(ve);
       int rank = 0;
       for (int x = 0; x < k; ++x) {
-        const double vx = val(x);
-        rank += (vx < ve) || (vx == ve && x < e);
+        const long long kx = dc_key(val(x));
+        rank += (kx < ke) || (kx == ke && x < e);
       }
       R.oo[lo + rank] = e;
       lam[lo + rank] = ve;
     }
     __syncthreads();
-    // Phase E: transformed rows, written in output order
-    for (int q = tid; q < n; q += nthr) {
-      const int lo = q - q % span;
-      const int kp = R.cnt[lo];
-      if (kp < 0) continue;
-      const int e = R.oo[q];
+    // Phase E: transformed rows, written in output order.  Output row q (merge [lo, lo+k),
+    // element e = oo[q]) is sum_j u(e, j) G1(lo + kpos[j]) over the kept j (e < kp), or its own
+    // row G1(lo + kpos[e]) (deflated e).  One output row per thread and pass; G1 is staged
+    // through LDS kChunk rows at a time, and a staged row p belongs to j = jinv[p], so the
+    // threads of one merge read the same LDS row in step (broadcast).
+    for (int qb = 0; qb < n; qb += nthr) {
+      constexpr int CH = DcLds::kChunk;
+      const int q = qb + tid;
+      int lo = 0, hi = 0, kp = -1, e = 0;
+      double dorig = 0.0, tau = 0.0, ninv = 0.0;
+      if (q < n) {
+        lo = q - q % span;
+        hi = min(lo + span, n);
+        kp = R.cnt[lo];
+        if (kp >= 0) {
+          e = R.oo[q];
+          if (e < kp) {
+            dorig = S.d[lo + S.orig[lo + e]];
+            tau = S.tau[lo + e];
+            ninv = 1.0 / S.nrm[lo + e];
+          }
+        }
+      }
+      const bool kept = q < n && kp >= 0 && e < kp;
       double acc[kTrack];
-      if (e < kp) {
 #pragma unroll
-        for (int cc = 0; cc < kTrack; ++cc) acc[cc] = 0.0;
-        const double *dK = R.dK + lo;
-        const double dorig = dK[R.orig[lo + e]], tau = R.tau[lo + e];
-        const double ninv = 1.0 / R.nrm[lo + e];
-        for (int j = 0; j < kp; ++j) {
-          const double u = R.zt[lo + j] / ((dK[j] - dorig) - tau) * ninv;
-          const double *g = G1 + (long long)(lo + R.kpos[lo + j]) * kTrack;
+      for (int cc = 0; cc < kTrack; ++cc) acc[cc] = 0.0;
+      // the rows any thread of this pass needs: [first merge start, last merge end)
+      const int rlo = qb - qb % span, rhi = min(n, ((min(qb + nthr, n) - 1) / span + 1) * span);
+      for (int c0 = rlo; c0 < rhi; c0 += CH) {
+        __syncthreads();
+        for (int t = tid; t < CH * nt; t += nthr) {
+          const int r = t / nt, cc = t % nt;
+          S.g[r * kTrack + cc] = (c0 + r < n) ? G1[(long long)(c0 + r) * kTrack + cc] : 0.0;
+        }
+        __syncthreads();
+        if (kept) {
+          const int pa = max(c0, lo), pb = min(c0 + CH, hi);
+          const double *dK = S.d + lo, *zt = S.zt + lo;
+          for (int pp = pa; pp < pb; ++pp) {
+            const int j = S.jinv[pp];
+            if (j >= kp) continue;
+            const double w = zt[j] / ((dK[j] - dorig) - tau) * ninv;
+            const double *g = S.g + (pp - c0) * kTrack;
+#pragma unroll
+            for (int cc = 0; cc < kTrack; ++cc)
+              if (cc < nt) acc[cc] += w * g[cc];
+          }
+        }
+      }
+      if (q < n && kp >= 0) {
+        if (!kept) {
+          const double *g = G1 + (long long)(lo + S.kpos[lo + e]) * kTrack;
 #pragma unroll
           for (int cc = 0; cc < kTrack; ++cc)
-            if (cc < nt) acc[cc] += u * g[cc];
+            if (cc < nt) acc[cc] = g[cc];
         }
-      } else {
-        const double *g = G1 + (long long)(lo + R.kpos[lo + e]) * kTrack;
 #pragma unroll
-        for (int cc = 0; cc < kTrack; ++cc) acc[cc] = (cc < nt) ? g[cc] : 0.0;
+        for (int cc = 0; cc < kTrack; ++cc)
+          if (cc < nt) G0[(long long)q * kTrack + cc] = acc[cc];
       }
-#pragma unroll
-      for (int cc = 0; cc < kTrack; ++cc)
-        if (cc < nt) G0[(long long)q * kTrack + cc] = acc[cc];
     }
     __syncthreads();
   }
@@ -335,7 +452,9 @@ __global__ void __launch_bounds__(256) stedc_kernel(int n_clusters, const int *_
                                                     double *__restrict__ vec, const long long *__restrict__ vec_off,
                                                     int *__restrict__ ivec, const long long *__restrict__ ivec_off,
                                                     const int *__restrict__ dmax, const int *__restrict__ dim,
-                                                    const int *__restrict__ n_orb, DevStatus *st) {
+                                                    const int *__restrict__ n_orb, DevStatus *st, int nmax) {
+  extern __shared__ double dsh[];
+  const DcLds S = dc_lds(dsh, nmax);
   for (int s = blockIdx.x; s < n_clusters; s += gridDim.x) {
     const int c = order[s];
     const int n = dim[c];
@@ -344,7 +463,7 @@ __global__ void __launch_bounds__(256) stedc_kernel(int n_clusters, const int *_
     const VecLayout vl = VecLayout::make(dmax[c]);
     DcWs ws = dc_ws(cv, ivec + ivec_off[c], dmax[c]);
     __syncthreads();
-    dc_forward(n, cv + vl.d, cv + vl.e, 2 * M, ws, st, c);
+    dc_forward(n, cv + vl.d, cv + vl.e, 2 * M, ws, S, st, c);
     // weights w_mu = sum_alpha (C^T E_i)_{mu alpha} ((S C)^T E_i)_{mu alpha}
     double *w = cv + vl.w;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -358,8 +477,9 @@ __global__ void __launch_bounds__(256) stedc_kernel(int n_clusters, const int *_
 }
 
 void launch_stedc(Plan &p) {
-  hipLaunchKernelGGL(stedc_kernel, dim3(p.workgroups), dim3(kWG), 0, p.stream, p.n_atoms, p.d_order, p.d_vec,
-                     p.d_vec_off, p.d_ivec, p.d_ivec_off, p.d_dmax, p.d_dim, p.d_n_orb, p.d_status);
+  const size_t lds = (size_t)p.max_dim * DcLds::kBytesPerRow + DcLds::kFixedBytes;
+  hipLaunchKernelGGL(stedc_kernel, dim3(p.workgroups), dim3(kWG), lds, p.stream, p.n_atoms, p.d_order, p.d_vec,
+                     p.d_vec_off, p.d_ivec, p.d_ivec_off, p.d_dmax, p.d_dim, p.d_n_orb, p.d_status, p.max_dim);
 }
 
 }  // namespace ldc
