@@ -55,15 +55,23 @@ __device__ inline DcWs dc_ws(double *cv, int *ci, int nb) {
 
 // y (n rows, ny columns, row stride kMaxOrb) in final eigenvalue order -> Z y in the
 // tridiagonal index order.  ya/yb: ping-pong buffers; the result ends in the returned one.
-__device__ inline double *dc_apply(int n, int ny, DcWs ws, double *ya, double *yb) {
+// lds: at least 4.5 n + kApplyChunk * kMaxOrb doubles: a level's secular data (poles, z,
+// roots, norms, origins) and a chunk of y rows are staged there, so the row sums read LDS.
+constexpr int kApplyChunk = 32;
+__device__ inline int dc_apply_lds_doubles(int n) { return 4 * n + (n + 1) / 2 + kApplyChunk * kMaxOrb; }
+
+__device__ inline double *dc_apply(int n, int ny, DcWs ws, double *ya, double *yb, double *lds) {
   const int tid = threadIdx.x, nthr = blockDim.x;
+  double *sdK = lds, *szt = lds + n, *stau = lds + 2 * n, *snrm = lds + 3 * n;
+  int *sorig = reinterpret_cast<int *>(lds + 4 * n);
+  double *sy = lds + 4 * n + (n + 1) / 2;  // kApplyChunk x kMaxOrb
   int L = 0;
   while ((1 << L) < n) ++L;
   for (int l = L - 1; l >= 0; --l) {
     const int size = 1 << l, span = 2 * size;
     const DcRec R = dc_rec(ws.dcd, ws.dci, n, l);
     const int nmerge = (n + span - 1) / span;
-    // T1: output order -> element order
+    // T1: output order -> element order; stage the level's secular data
     for (long long e = tid; e < (long long)n * ny; e += nthr) {
       const int q = (int)(e / ny), cc = (int)(e % ny);
       const int lo = q - q % span;
@@ -73,38 +81,71 @@ __device__ inline double *dc_apply(int n, int ny, DcWs ws, double *ya, double *y
       }
       yb[(long long)(lo + R.oo[q]) * kMaxOrb + cc] = ya[(long long)q * kMaxOrb + cc];
     }
-    __syncthreads();
-    // T2: secular eigenvectors (and deflated identities) -> sorted-pole order
     for (int q = tid; q < n; q += nthr) {
       const int lo = q - q % span;
       const int kp = R.cnt[lo];
-      if (kp < 0) {
-        for (int cc = 0; cc < ny; ++cc) ya[(long long)q * kMaxOrb + cc] = yb[(long long)q * kMaxOrb + cc];
-        continue;
+      if (kp < 0 || q - lo >= kp) continue;
+      sdK[q] = R.dK[q];
+      szt[q] = R.zt[q];
+      stau[q] = R.tau[q];
+      snrm[q] = R.nrm[q];
+      sorig[q] = R.orig[q];
+    }
+    __syncthreads();
+    // T2: secular eigenvectors (and deflated identities) -> sorted-pole order.  Row j < kp of a
+    // merge is sum_t zt_j / ((d_j - d_orig(t) - tau_t) nrm_t) y_t; the y rows come through LDS
+    // kApplyChunk at a time (the threads of one merge read the same row: broadcast).
+    for (int qb = 0; qb < n; qb += nthr) {
+      const int q = qb + tid;
+      int lo = 0, kp = -1, j = 0;
+      double dj = 0.0, zj = 0.0;
+      if (q < n) {
+        lo = q - q % span;
+        kp = R.cnt[lo];
+        j = q - lo;
+        if (kp >= 0 && j < kp) {
+          dj = sdK[q];
+          zj = szt[q];
+        }
       }
-      const int j = q - lo;
+      const bool kept = q < n && kp >= 0 && j < kp;
       double acc[kMaxOrb];
-      if (j < kp) {
 #pragma unroll
-        for (int cc = 0; cc < kMaxOrb; ++cc) acc[cc] = 0.0;
-        const double *dK = R.dK + lo;
-        const double dj = dK[j], zj = R.zt[lo + j];
-        for (int t = 0; t < kp; ++t) {
-          const double u = zj / (((dj - dK[R.orig[lo + t]]) - R.tau[lo + t]) * R.nrm[lo + t]);
-          const double *y = yb + (long long)(lo + t) * kMaxOrb;
+      for (int cc = 0; cc < kMaxOrb; ++cc) acc[cc] = 0.0;
+      const int rlo = qb - qb % span, rhi = min(n, ((min(qb + nthr, n) - 1) / span + 1) * span);
+      for (int c0 = rlo; c0 < rhi; c0 += kApplyChunk) {
+        __syncthreads();
+        for (int e = tid; e < kApplyChunk * ny; e += nthr) {
+          const int r = e / ny, cc = e % ny;
+          sy[r * kMaxOrb + cc] = (c0 + r < n) ? yb[(long long)(c0 + r) * kMaxOrb + cc] : 0.0;
+        }
+        __syncthreads();
+        if (kept) {
+          const int ta = max(c0, lo), tb = min(c0 + kApplyChunk, lo + kp);
+          for (int t = ta; t < tb; ++t) {
+            const double u = zj / (((dj - sdK[lo + sorig[t]]) - stau[t]) * snrm[t]);
+            const double *y = sy + (t - c0) * kMaxOrb;
+#pragma unroll
+            for (int cc = 0; cc < kMaxOrb; ++cc)
+              if (cc < ny) acc[cc] += u * y[cc];
+          }
+        }
+      }
+      if (q < n) {
+        if (kp < 0) {
+          for (int cc = 0; cc < ny; ++cc) ya[(long long)q * kMaxOrb + cc] = yb[(long long)q * kMaxOrb + cc];
+        } else {
+          if (!kept) {
+            const double *y = yb + (long long)(lo + j) * kMaxOrb;
+#pragma unroll
+            for (int cc = 0; cc < kMaxOrb; ++cc) acc[cc] = (cc < ny) ? y[cc] : 0.0;
+          }
+          const int pos = R.kpos[lo + j];
 #pragma unroll
           for (int cc = 0; cc < kMaxOrb; ++cc)
-            if (cc < ny) acc[cc] += u * y[cc];
+            if (cc < ny) ya[(long long)(lo + pos) * kMaxOrb + cc] = acc[cc];
         }
-      } else {
-        const double *y = yb + (long long)(lo + j) * kMaxOrb;
-#pragma unroll
-        for (int cc = 0; cc < kMaxOrb; ++cc) acc[cc] = (cc < ny) ? y[cc] : 0.0;
       }
-      const int pos = R.kpos[lo + j];
-#pragma unroll
-      for (int cc = 0; cc < kMaxOrb; ++cc)
-        if (cc < ny) ya[(long long)(lo + pos) * kMaxOrb + cc] = acc[cc];
     }
     __syncthreads();
     // T3: deflation rotations, reverse order
@@ -140,6 +181,5 @@ __device__ inline double *dc_apply(int n, int ny, DcWs ws, double *ya, double *y
   }
   return ya;
 }
-
 
 }  // namespace ldc

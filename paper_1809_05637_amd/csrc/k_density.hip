@@ -12,6 +12,10 @@
 
 namespace ldc {
 
+// the product Z y stages its data in the compact-WY LDS area
+static_assert(4 * kMaxDimTri + (kMaxDimTri + 1) / 2 + kApplyChunk * kMaxOrb <= kQapplyLds,
+              "dc_apply staging must fit the compact-WY LDS area");
+
 // state layout of Plan::d_mu
 enum { MU_LO = 0, MU_HI, MU_DONE, MU_IT, MU_SUMW, MU_NE, MU_KT, MU_G, MU_MU, MU_BAD };
 
@@ -136,7 +140,7 @@ __global__ void __launch_bounds__(256) density_kernel(
       ya[(long long)i * kMaxOrb + a] = fermi((ws.lam[i] - mu) / kT) * ws.G0[(long long)i * kTrack + a];
     }
     __syncthreads();
-    double *r = dc_apply(n, M, ws, ya, yb);
+    double *r = dc_apply(n, M, ws, ya, yb, qlds);
     // r <- Q r = Q1 (Q2 r): the bulge-chasing reflectors, then the band reduction's compact-WY
     // panels (T factors stored by the band reduction)
     wg_apply_q2(A, ld, n, r, kMaxOrb, M, false);
@@ -149,7 +153,18 @@ __global__ void __launch_bounds__(256) density_kernel(
       const int g = b0 + e / M, a = e % M;
       const double *lc = L + (long long)g * ld;
       double acc = 0.0;
-      for (int t = g; t < n; ++t) acc += lc[t] * r[(long long)t * kMaxOrb + a];
+      // 8 rows per step, clamped past the end (their factor is zero): loads in flight together
+      for (int t0 = g; t0 < n; t0 += 8) {
+        double lv[8], rv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int t = min(t0 + u, n - 1);
+          lv[u] = lc[t];
+          rv[u] = r[(long long)t * kMaxOrb + a];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += (t0 + u < n) ? lv[u] * rv[u] : 0.0;
+      }
       xo[(long long)g * kMaxOrb + a] = acc;
     }
     __syncthreads();
