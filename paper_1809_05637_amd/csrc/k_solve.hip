@@ -258,7 +258,7 @@ __global__ void __launch_bounds__(256, 2) sygst_kernel(int n_clusters, const int
     const VecLayout vl = VecLayout::make(dmax[c]);
     double *cv = vec + vec_off[c];
     double *X = cv + vl.G0;
-    double *tmp = cv + vl.G1;  // n x NB scratch (column-major, ld n)
+    double *tmp = cv + vl.G1;  // n x GT scratch (spans the tracked-column partner and the T-factor area)
     const int b0 = n - M;
     __syncthreads();
     // tracked columns: X_v = L^T E_i (rows of L of the centre atom); X_u filled below
@@ -303,23 +303,25 @@ __global__ void __launch_bounds__(256, 2) sygst_kernel(int n_clusters, const int
       const int r = e % M, al = e / M;
       X[(long long)(b0 + r) * kTrack + al] = (r >= al) ? L[(long long)(b0 + al) * ld + b0 + r] : 0.0;
     }
-    // 2. W = L^{-1} H, block rows from the last (tmp holds -W_b, NB x n, ld NB)
-    for (int bj = nblk - 1; bj >= 0; --bj) {
-      const int r0 = bj * NB, jb = min(NB, n - r0), r1 = r0 + jb;
-      wg_gemm<G_OVERWRITE>(tmp, NB, L + r0, ld, H, ld, jb, n, r1, gl, r0);
+    // 2. W = L^{-1} H, block rows of GT from the last (tmp holds -W_b, GT x n, ld GT); full
+    //    MFMA tiles, K limited to the nonzero part of the block row of L^{-1}
+    const int nblk2 = (n + GT - 1) / GT;
+    for (int bj = nblk2 - 1; bj >= 0; --bj) {
+      const int r0 = bj * GT, jb = min(GT, n - r0), r1 = r0 + jb;
+      wg_gemm<G_OVERWRITE>(tmp, GT, L + r0, ld, H, ld, jb, n, r1, gl, r0);
       for (long long e = tid; e < (long long)jb * n; e += nthr) {
         const int rr = (int)(e % jb), q = (int)(e / jb);
-        H[(long long)q * ld + r0 + rr] = -tmp[(long long)q * NB + rr];
+        H[(long long)q * ld + r0 + rr] = -tmp[(long long)q * GT + rr];
       }
       __syncthreads();
     }
     // 3. A = L^{-1} W^T, lower part: block row b of A = L^{-1}(rows b, cols 0:r1) W(0:r1, 0:r1)^T
-    for (int bj = nblk - 1; bj >= 0; --bj) {
-      const int r0 = bj * NB, jb = min(NB, n - r0), r1 = r0 + jb;
-      wg_gemm<G_TRANS_B | G_OVERWRITE>(tmp, NB, L + r0, ld, H, ld, jb, r1, r1, gl, r0);
+    for (int bj = nblk2 - 1; bj >= 0; --bj) {
+      const int r0 = bj * GT, jb = min(GT, n - r0), r1 = r0 + jb;
+      wg_gemm<G_TRANS_B | G_OVERWRITE>(tmp, GT, L + r0, ld, H, ld, jb, r1, r1, gl, r0);
       for (long long e = tid; e < (long long)jb * r1; e += nthr) {
         const int rr = (int)(e % jb), q = (int)(e / jb);
-        H[(long long)q * ld + r0 + rr] = -tmp[(long long)q * NB + rr];
+        H[(long long)q * ld + r0 + rr] = -tmp[(long long)q * GT + rr];
       }
       __syncthreads();
     }
