@@ -31,21 +31,33 @@ FP64_PEAK_TFLOPS = 78.6     # MI355X dense FP64 (vector and matrix)
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
 
 
-def stage_work(dims, p_rows):
-    """Algorithmic FP64 flops per stage for clusters of dimension d (LAPACK counts)."""
+def stage_work(dims):
+    """Algorithmic FP64 flops of the matrix-core stages for clusters of dimension d (LAPACK
+    counts: Cholesky d^3/3, standard form d^3, reduction to band form 4 d^3 / 3)."""
     d = dims.astype(np.float64)
     return {
         "potrf": float(np.sum(d ** 3 / 3.0)),
         "sygst": float(np.sum(d ** 3)),
-        "sytrd": float(np.sum(4.0 * d ** 3 / 3.0)),
+        "sy2sb": float(np.sum(4.0 * d ** 3 / 3.0)),
     }
 
 
-def sytrd_bytes(dims):
-    """Bytes a one-stage Householder tridiagonalization must stream: the trailing lower
-    triangle (FP64) once per column, sum_k 8 (d-k)^2 / 2 ~ 8 d^3 / 6 per cluster."""
-    d = dims.astype(np.float64)
-    return float(np.sum(8.0 * d * (d + 1) * (2 * d + 1) / 12.0))
+def sb2st_bytes(dims, b=32):
+    """Bytes the band-to-tridiagonal chase must move: every step of every sweep reads and writes
+    its window once (the lower triangle of the len x len diagonal block and the nr x len block
+    below it) and writes its reflector (len doubles).  Sweep s, step j: r0 = s + 1 + j b,
+    len = min(b, d - r0), nr = min(b, d - r0 - len), steps while r0 <= d - 2."""
+    total = 0.0
+    for n in np.unique(dims):
+        cnt = int(np.sum(dims == n))
+        per = 0.0
+        for s in range(0, n - 2):
+            r0 = np.arange(s + 1, n - 1, b, dtype=np.float64)
+            ln = np.minimum(b, n - r0)
+            nr = np.clip(n - r0 - ln, 0, b)
+            per += float(np.sum(8.0 * (ln * (ln + 1) + 2.0 * nr * ln + ln)))
+        total += cnt * per
+    return total
 
 
 def copy_probe(mib):
@@ -61,16 +73,30 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes": n * 8, "copies": 3}), flush=True)
 
 
-def kernel_source_hash():
-    """Hash of the HIP sources the dominant kernel is built from (ties stored counters to code)."""
+def kernel_source_hash(source):
+    """Hash of a kernel's HIP source file and the local headers it includes (ties stored counters
+    to the code they were taken on)."""
     import hashlib
-    h = hashlib.sha256()
+    import re
     csrc = os.path.join(ROOT, "paper_1809_05637_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    seen, todo = [], [source]
+    while todo:
+        name = todo.pop()
+        if name in seen or not os.path.exists(os.path.join(csrc, name)):
+            continue
+        seen.append(name)
+        with open(os.path.join(csrc, name)) as f:
+            todo += re.findall(r'^#include "([^"]+)"', f.read(), re.M)
+    h = hashlib.sha256()
+    for name in sorted(seen):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
+
+
+# kernel -> source file (the dominant kernels whose counters can be stored)
+KERNEL_SOURCE = {"sb2st_kernel": "k_tridiag.hip", "sy2sb_kernel": "k_tridiag.hip",
+                 "sygst_kernel": "k_solve.hip", "potrf_kernel": "k_solve.hip", "stedc_kernel": "k_dc.hip"}
 
 
 def stored_traffic(kernel, workload):
@@ -79,13 +105,13 @@ def stored_traffic(kernel, workload):
     taken on other kernel sources."""
     import re
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
-    if not os.path.exists(path):
+    if not os.path.exists(path) or kernel not in KERNEL_SOURCE:
         return None
     with open(path) as f:
         text = f.read()
     h = re.search(r"^source_hash:\s*(\S+)", text, re.M)
     b = re.search(r"^hbm_bytes_per_launch:\s*([0-9.eE+]+)", text, re.M)
-    if not h or not b or h.group(1) != kernel_source_hash():
+    if not h or not b or h.group(1) != kernel_source_hash(KERNEL_SOURCE[kernel]):
         return None
     return float(b.group(1))
 
@@ -199,24 +225,28 @@ def main():
     log("[bench] stage ms/build: " + ", ".join(f"{k}={v:.2f}" for k, v in per_stage.items()))
     log(f"[bench] dims: min {dims.min()} mean {dims.mean():.1f} max {dims.max()}; wall {wall / args.steps * 1e3:.1f} "
         f"ms/step, events {ms_step:.1f} ms/step")
-    work = stage_work(dims, None)
+    work = stage_work(dims)
     dom = max(per_stage, key=per_stage.get)
-    if dom in ("sytrd",):
-        traffic_alg = sytrd_bytes(dims)
-        achieved = traffic_alg / (per_stage[dom] * 1e-3) / 1e9
-        roof = {"kernel": "sytrd_kernel", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": stored_traffic("sytrd_kernel", s["name"]),
-                "ms_per_launch": round(per_stage[dom], 3), "algorithmic_bytes": traffic_alg,
-                "flops_tflops": round(work["sytrd"] / (per_stage[dom] * 1e-3) / 1e12, 3)}
+    kern = dom + "_kernel"
+    if dom == "sb2st":
+        alg = sb2st_bytes(dims)
+        achieved = alg / (per_stage[dom] * 1e-3) / 1e9
+        roof = {"kernel": kern, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic(kern, s["name"]),
+                "ms_per_launch": round(per_stage[dom], 3), "algorithmic_bytes": alg}
     elif dom in work:
         achieved = work[dom] / (per_stage[dom] * 1e-3) / 1e12
-        roof = {"kernel": dom + "_kernel", "bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
-                "ms_per_launch": round(per_stage[dom], 3), "algorithmic_flops": work[dom]}
+        roof = {"kernel": kern, "bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                "traffic": stored_traffic(kern, s["name"]), "ms_per_launch": round(per_stage[dom], 3),
+                "algorithmic_flops": work[dom]}
     else:
-        roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+        roof = {"kernel": kern, "bound": "alu", "achieved": None, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": None, "traffic": None, "ms_per_launch": round(per_stage[dom], 3)}
+    # the eigensolve as a whole (Cholesky .. tridiagonal eigenvectors of the tracked columns)
+    # against the FP64 matrix-core peak, 7 d^3 flops per cluster
+    eig_ms = sum(per_stage.get(k, 0.0) for k in ("potrf", "sygst", "sy2sb", "sb2st", "q2x", "stedc"))
+    eig_tf = float(np.sum(7.0 * dims.astype(np.float64) ** 3)) / (eig_ms * 1e-3) / 1e12 if eig_ms > 0 else None
     value = s["n_atoms"] / (ms_step * 1e-3)
     out = {
         "metric": "atoms/s per density-matrix build (FP64 form)",
@@ -237,6 +267,9 @@ def main():
         "clusters_per_s": round(value, 2),
         "stage_ms": {k: round(v, 3) for k, v in per_stage.items()},
         "roofline": roof,
+        "eigensolve": {"flops_7d3": float(np.sum(7.0 * dims.astype(np.float64) ** 3)), "ms": round(eig_ms, 3),
+                       "tflops": round(eig_tf, 3) if eig_tf else None,
+                       "frac_fp64_peak": round(eig_tf / FP64_PEAK_TFLOPS, 4) if eig_tf else None},
         "accuracy": {"n_e_from_D": ne, "n_electrons": s["n_electrons"], "mu": mu},
     }
     plan.close()

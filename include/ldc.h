@@ -150,12 +150,12 @@ ldc_status ldc_cluster_dims(ldc_plan_t plan, int *dims);
 
 /* Stage timing with HIP events recorded on the plan's stream around each stage.
  * Stages: 0 Lambda, 1 LNO eigensolve, 2 gather, 3 Cholesky, 4 standard form,
- * 5 reduction to band form, 6 band to tridiagonal, 7 tridiagonal eigensolve,
- * 8 chemical potential, 9 density rows.
+ * 5 reduction to band form, 6 band to tridiagonal, 7 second-stage transform of the
+ * tracked columns, 8 tridiagonal eigensolve, 9 chemical potential, 10 density rows.
  * ldc_profile(plan, 1) enables timing and clears the accumulated times; 0 disables it.
  * ldc_stage_times fills ms (LDC_NUM_STAGES entries, summed over builds) and *builds (the
  * number of completed ldc_density calls while enabled).  Synchronizes. */
-#define LDC_NUM_STAGES 10
+#define LDC_NUM_STAGES 11
 ldc_status ldc_profile(ldc_plan_t plan, int enable);
 ldc_status ldc_stage_times(ldc_plan_t plan, double *ms, int *builds);
 const char *ldc_stage_name(int stage);

@@ -24,7 +24,7 @@ _LIB = None
 STATUS = {0: "LDC_OK", 1: "LDC_ERR_ARG", 2: "LDC_ERR_NOT_SPD", 3: "LDC_ERR_EIG_NOCONV", 4: "LDC_ERR_MU_BRACKET",
           5: "LDC_ERR_RANK", 6: "LDC_ERR_OOM", 7: "LDC_ERR_DEVICE", 8: "LDC_ERR_STATE", 9: "LDC_ERR_LIMIT"}
 
-NUM_STAGES = 10
+NUM_STAGES = 11
 
 c_int, c_double, c_void_p, c_size_t = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
 P_int = ctypes.POINTER(ctypes.c_int)

@@ -81,7 +81,7 @@ ldc_status check_status(Plan &p) {
 }
 
 const char *kStageNames[LDC_NUM_STAGES] = {"lambda", "lno_eig", "gather", "potrf", "sygst",
-                                           "sy2sb", "sb2st", "stedc", "mu", "density"};
+                                           "sy2sb", "sb2st", "q2x", "stedc", "mu", "density"};
 
 inline void stage_begin(Plan &p, int s) {
   if (p.profile) (void)hipEventRecord(p.ev_begin[s], p.stream);
@@ -418,8 +418,11 @@ ldc_status ldc_solve(ldc_plan_t plan, const double *d_H, const double *d_S) {
   ldc::launch_sb2st(p);
   stage_end(p, 6);
   stage_begin(p, 7);
-  ldc::launch_stedc(p);
+  ldc::launch_q2x(p);
   stage_end(p, 7);
+  stage_begin(p, 8);
+  ldc::launch_stedc(p);
+  stage_end(p, 8);
   HIPCHK(hipGetLastError());
   p.last_H = d_H;
   p.last_S = d_S;
@@ -452,7 +455,7 @@ ldc_status ldc_density(ldc_plan_t plan, double n_electrons, double kT, double *d
   st[6] = kT;
   st[7] = g;
   HIPCHK(hipMemcpyAsync(p.d_mu, st, sizeof(st), hipMemcpyHostToDevice, p.stream));
-  stage_begin(p, 8);
+  stage_begin(p, 9);
   ldc::launch_mu_init(p, kT);
   int iters = 0;
   while (true) {
@@ -464,10 +467,10 @@ ldc_status ldc_density(ldc_plan_t plan, double n_electrons, double kT, double *d
     HIPCHK(hipStreamSynchronize(p.stream));
     if (chk[2] != 0.0 || iters >= 256) break;
   }
-  stage_end(p, 8);
-  stage_begin(p, 9);
-  ldc::launch_density(p, kT, d_D_out, p.last_H, p.last_S, g);
   stage_end(p, 9);
+  stage_begin(p, 10);
+  ldc::launch_density(p, kT, d_D_out, p.last_H, p.last_S, g);
+  stage_end(p, 10);
   HIPCHK(hipGetLastError());
   ldc_status s = finish_density(p, g, mu_out, e_band_out, n_e_out);
   if (p.profile) {

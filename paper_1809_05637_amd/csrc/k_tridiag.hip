@@ -14,14 +14,15 @@
 //
 // Stage 2 (sb2st_kernel), band to tridiagonal by bulge chasing on a band array holding the
 // lower band and the bulge (2b + 1 diagonals).  Sweep s removes column s below its
-// subdiagonal: step j takes the reflector of rows [r0, r0 + b), r0 = s + 1 + j b, from
-// column s (j = 0) or from the first column of the bulge the previous step created
-// (j >= 1), applies it from the left to the bulge columns, two-sidedly to the diagonal block
-// and from the right to the band block below (which creates the next bulge).  Step j of
-// sweep s + 1 never touches what steps >= j + 3 of sweep s touch, so at time t every sweep s
-// with j = t - 3 s in range is advanced at once, one wavefront per step.  The reflectors are
-// kept in the strictly upper triangle of A (sweep s in column n - 1 - s, rows j b..:
-// tau first, then v(1:)); X <- Q2^T X follows, sweep by sweep.
+// subdiagonal: the reflector of rows [r0, r0 + b), r0 = s + 1 + j b, comes from column s
+// (j = 0) or from the first column of the bulge that step j - 1 created; step j applies it
+// two-sidedly to the diagonal block and from the right to the band block below (which
+// creates the next bulge), then forms the next reflector from that block and applies it from
+// the left to the rest of the block.  Step j of sweep s + 1 never touches what steps >= j + 3
+// of sweep s touch, so at time t every sweep s with j = t - 3 s in range is advanced at once,
+// one wavefront per step.  The reflectors are kept in the strictly upper triangle of A
+// (sweep s in column n - 1 - s, rows j b..: tau first, then v(1:)); q2x_lds_kernel then
+// forms X <- Q2^T X, sweep by sweep.
 #include "wg_blas.h"
 #include "wg_qapply.h"
 
@@ -311,138 +312,178 @@ __global__ void __launch_bounds__(256, 2) sy2sb_kernel(int n_clusters, const int
 // Stage 2: bulge chasing (see the top of the file).
 __device__ inline int sweep_steps(int n, int s) { return (s > n - 3) ? 0 : (n - 3 - s) / kBand + 1; }
 
-// One bulge step (sweep s, step j) by one wavefront.  The row lanes 0..len-1 hold rows
-// r0 + i of the step; every load and store below is consecutive in i for a fixed column
-// (coalesced).  Entry (r, c), r >= c, of the band array is Bd[c * LB + r - c].  Offsets are
-// unsigned 32-bit from the array base; indices past the end are clamped on load and never
-// stored (lanes outside the lower triangle of the diagonal block store to their own slot of
-// sink, which keeps those stores free of branches).
-//   (a) reflector from x = B(r0:r1, col);
-//   (b) bulge block B(r0:r1, col+1:r0) <- H B (its column dots through the LDS tile);
-//   (c) diagonal block B(r0:r1, r0:r1) <- H B H (upper half of its rows from the tile) and,
-//       on lanes 32.., the band block below B(r1:r1+b, r0:r1) <- B H.
-// vs, wsv: kBand doubles each and wt: kBand x (kBand + 1) doubles of the wave's LDS; sink:
-// 64 doubles.  Returns tau; the reflector is left in vs.
-__device__ double bulge_step(double *__restrict__ Bd, double *__restrict__ A, int ld, int n, int s, int j,
-                             double *vs, double *wsv, double *wt, double *__restrict__ sink) {
+// One bulge step (sweep s, step j) by one wavefront.  The reflector H_j = I - tau v v^T of the
+// rows [r0, r1), r0 = s + 1 + j b, r1 = min(r0 + b, n), is in the sweep's LDS slot (tau, then v
+// with v(0) = 1); step 0 first forms it from column s.  The step then
+//   (c) updates the diagonal block D = B(r0:r1, r0:r1) <- H_j D H_j and the block below it,
+//       R = B(r1:r2, r0:r1) <- R H_j, r2 = min(r1 + b, n) (this creates the bulge in R);
+//   (a) when r2 - r1 >= 2, forms H_{j+1} from the first column of R, which it reduces to
+//       beta e_0, stores it (A's upper triangle and the slot), and
+//   (b) applies H_{j+1} from the left to the other columns of R.
+// (a) and (b) belong to step j + 1 of the sweep; nothing else touches R between the two
+// steps, so they run here while R is still in registers and every step moves its window
+// through memory once.  Lanes 0..31 hold the rows of D, lanes 32..63 the rows of R; every
+// load and store is consecutive in the lane for a fixed column (coalesced).  Entry (r, c),
+// r >= c, of the band array is Bd[c * LB + r - c].  Offsets are unsigned 32-bit from the array
+// base; indices past the end are clamped on load and never stored (D lanes store the part of
+// their row above the diagonal to their own slot of sink, which keeps those stores free of
+// branches).  wsv: kBand doubles and wt: kBand x (kBand + 1) doubles of the wave's LDS; slot:
+// kBand + 1 doubles of the sweep; sink: 64 doubles.
+__device__ void bulge_step(double *__restrict__ Bd, double *__restrict__ A, int ld, int n, int s, int j,
+                           double *slot, double *wsv, double *wt, double *__restrict__ sink) {
   constexpr int b = kBand, TS = kBand + 1;
   constexpr unsigned LB = kBandLd, LD1 = kBandLd - 1;
-  const int lane = threadIdx.x & 63;
-  const int r0 = s + 1 + j * b, col = (j == 0) ? s : r0 - b;
-  const int r1 = min(r0 + b, n), len = r1 - r0;
-  const int nl = r0 - col - 1;            // bulge columns right of x (0 or b - 1)
+  // the lane index and (s, j) through opaque moves: keeps the compiler from hoisting the
+  // per-lane addresses of the fully unrolled loops below out of the time loop (they would
+  // not fit in registers at four waves per SIMD)
+  int tx;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(tx) : "v"((int)threadIdx.x));
+  s = __builtin_amdgcn_readfirstlane(s);
+  j = __builtin_amdgcn_readfirstlane(j);
+  asm volatile("" : "+s"(s), "+s"(j));
+  const int lane = tx & 63;
   const bool lo = lane < 32;
   const int i = lo ? lane : lane - 32;
-  const bool isRow = lo && i < len;
+  const int r0 = s + 1 + j * b, r1 = min(r0 + b, n), len = r1 - r0;
+  const int nr = min(b, n - r1);  // rows of R (0 on the last step of the sweep)
+  const bool isRow = lo && i < len, isR = !lo && i < nr;
   const unsigned ic = (unsigned)min(i, len - 1);
-  // (a)
-  const unsigned oXL = (unsigned)col * LB + (unsigned)(r0 - col) + ic;  // B(r0+i, col + c) at oXL + c LD1
-  const double x = isRow ? Bd[oXL] : 0.0;
-  const double sigma = wave_sum(isRow && i >= 1 ? x * x : 0.0);
-  const double alpha = __shfl(x, 0, 64);
-  double beta, tau, sc;
-  if (sigma == 0.0) {
-    tau = 0.0;
-    beta = alpha;
-    sc = 0.0;
+  const unsigned oW = (unsigned)r0 * LB + ic;  // D(i, k) at oW + k LD1 for k <= i
+  const unsigned oR = (unsigned)r0 * LB + (unsigned)len + (unsigned)min(i, max(nr - 1, 0));  // R(i, k) at oR + k LD1
+  const unsigned o = lo ? oW : oR;
+  const unsigned oX = (j == 0) ? (unsigned)s * LB + 1u + ic : o;  // column s below its diagonal (step 0)
+  const double x = Bd[oX];
+  double row[b];
+#pragma unroll
+  for (int k = 0; k < b; ++k) row[k] = Bd[o + (unsigned)min(k, len - 1) * LD1];
+  double *vs = slot + 1;
+  double tau, v;
+  if (j == 0) {
+    const double sigma = wave_sum(isRow && i >= 1 ? x * x : 0.0);
+    const double alpha = __shfl(x, 0, 64);
+    double beta, sc;
+    if (sigma == 0.0) {
+      tau = 0.0;
+      beta = alpha;
+      sc = 0.0;
+    } else {
+      beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+      tau = (beta - alpha) / beta;
+      sc = 1.0 / (alpha - beta);
+    }
+    v = isRow ? (i == 0 ? 1.0 : x * sc) : 0.0;
+    if (isRow) {
+      Bd[oX] = (i == 0) ? beta : 0.0;
+      A[(long long)(n - 1 - s) * ld + i] = (i == 0) ? tau : v;
+    }
+    if (lo) vs[i] = v;
   } else {
-    beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
-    tau = (beta - alpha) / beta;
-    sc = 1.0 / (alpha - beta);
+    tau = slot[0];
+    v = isRow ? vs[i] : 0.0;
   }
-  const double v = isRow ? (i == 0 ? 1.0 : x * sc) : 0.0;
-  if (isRow) {
-    Bd[oXL] = (i == 0) ? beta : 0.0;
-    A[(long long)(n - 1 - s) * ld + j * b + i] = (i == 0) ? tau : v;
-  }
-  if (lo) vs[i] = v;
   __builtin_amdgcn_wave_barrier();
-  if (tau == 0.0) return 0.0;
-  // (b)
-  if (nl > 0) {
-    double y[b];
+  // (c) the D lanes park their lower rows in the tile and read back full symmetric rows
+  if (lo) {
 #pragma unroll
-    for (int c = 1; c < b; ++c) y[c] = Bd[oXL + (unsigned)min(c, nl) * LD1];
-    if (lo) {
+    for (int k = 0; k < b; ++k) wt[i * TS + k] = isRow ? row[k] : 0.0;
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (isRow) {
+    // both candidates at fixed offsets from two bases (no per-column address registers)
 #pragma unroll
-      for (int c = 1; c < b; ++c) wt[i * TS + c] = isRow ? v * y[c] : 0.0;
+    for (int k = 0; k < b; ++k) {
+      const double lower = wt[i * TS + k], upper = wt[k * TS + i];
+      row[k] = (k <= i) ? lower : upper;
+    }
+  }
+  double pdot = 0.0;
+#pragma unroll
+  for (int k = 0; k < b; ++k) pdot += row[k] * vs[k];
+  const double p = tau * pdot;
+  const double vp = wave_sum(isRow ? v * p : 0.0);
+  const double w = p - 0.5 * tau * vp * v;
+  if (lo) wsv[i] = isRow ? w : 0.0;
+  __builtin_amdgcn_wave_barrier();
+  // v is read again from LDS below rather than held in 64 more registers
+  asm volatile("" ::: "memory");
+  if (isRow) {
+    double *own = sink + lane;
+#pragma unroll
+    for (int k = 0; k < b; ++k) {
+      const double val = row[k] - v * wsv[k] - w * vs[k];
+      *((k <= i) ? Bd + oW + (unsigned)k * LD1 : own) = val;
+    }
+  } else if (isR) {
+#pragma unroll
+    for (int k = 0; k < b; ++k) row[k] -= p * vs[k];
+  }
+  if (nr >= 2) {
+    // (a) H_{j+1} from x = R(:, 0)
+    const double x1 = isR ? row[0] : 0.0;
+    const double sigma = wave_sum(isR && i >= 1 ? x1 * x1 : 0.0);
+    const double alpha = __shfl(x1, 32, 64);
+    double beta, tau1, sc;
+    if (sigma == 0.0) {
+      tau1 = 0.0;
+      beta = alpha;
+      sc = 0.0;
+    } else {
+      beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+      tau1 = (beta - alpha) / beta;
+      sc = 1.0 / (alpha - beta);
+    }
+    const double v1 = isR ? (i == 0 ? 1.0 : x1 * sc) : 0.0;
+    row[0] = (i == 0) ? beta : 0.0;
+    if (isR) A[(long long)(n - 1 - s) * ld + (j + 1) * b + i] = (i == 0) ? tau1 : v1;
+    // the slot passes H_{j+1} to the next step (every read of H_j above comes first)
+    __builtin_amdgcn_wave_barrier();
+    if (!lo) vs[i] = v1;
+    if (lane == 32) slot[0] = tau1;
+    // (b) R(:, 1:) <- H_{j+1} R(:, 1:), column dots through the tile
+    if (!lo) {
+#pragma unroll
+      for (int c = 1; c < b; ++c) wt[i * TS + c] = isR ? v1 * row[c] : 0.0;
     }
     __builtin_amdgcn_wave_barrier();
     if (lo && i >= 1) {
       double d = 0.0;
 #pragma unroll
       for (int q = 0; q < b; ++q) d += wt[q * TS + i];
-      wsv[i] = tau * d;
+      wsv[i] = tau1 * d;
     }
     __builtin_amdgcn_wave_barrier();
-    if (isRow) {
+    if (isR) {
 #pragma unroll
-      for (int c = 1; c < b; ++c) Bd[oXL + (unsigned)c * LD1] = y[c] - v * wsv[c];
-    }
-    __builtin_amdgcn_wave_barrier();
-  }
-  // (c)
-  {
-    const int nr = min(b, n - r1);
-    const bool isR = !lo && i < nr;
-    const unsigned oW = (unsigned)r0 * LB + ic;  // B(r0+i, r0+k) at oW + k LD1 for k <= i
-    const unsigned oR = (unsigned)r0 * LB + (unsigned)len + (unsigned)min(i, max(nr - 1, 0));
-    const unsigned o = lo ? oW : oR;
-    double row[b];
-#pragma unroll
-    for (int k = 0; k < b; ++k) row[k] = Bd[o + (unsigned)min(k, len - 1) * LD1];
-    // the row lanes park their lower rows in the tile and read back full symmetric rows
-    if (lo) {
-#pragma unroll
-      for (int k = 0; k < b; ++k) wt[i * TS + k] = isRow ? row[k] : 0.0;
-    }
-    __builtin_amdgcn_wave_barrier();
-    if (isRow) {
-#pragma unroll
-      for (int k = 0; k < b; ++k) row[k] = wt[(k <= i) ? i * TS + k : k * TS + i];
-    }
-    double pdot = 0.0;
-#pragma unroll
-    for (int k = 0; k < b; ++k) pdot += row[k] * vs[k];
-    const double p = tau * pdot;
-    const double vp = wave_sum(isRow ? v * p : 0.0);
-    const double w = p - 0.5 * tau * vp * v;
-    if (lo) wsv[i] = isRow ? w : 0.0;
-    __builtin_amdgcn_wave_barrier();
-    if (isRow) {
-      double *own = sink + lane;
-#pragma unroll
-      for (int k = 0; k < b; ++k) {
-        const double val = row[k] - v * wsv[k] - w * vs[k];
-        *((k <= i) ? Bd + oW + (unsigned)k * LD1 : own) = val;
-      }
-    } else if (isR) {
-      const double ru = tau * pdot;
-#pragma unroll
-      for (int k = 0; k < b; ++k)
-        if (k < len) Bd[oR + (unsigned)k * LD1] = row[k] - ru * vs[k];
+      for (int c = 1; c < b; ++c) row[c] -= v1 * wsv[c];
     }
   }
-  return tau;
+  if (isR) {
+#pragma unroll
+    for (int k = 0; k < b; ++k) Bd[oR + (unsigned)k * LD1] = row[k];
+  }
 }
 
-__global__ void __launch_bounds__(256, 2) sb2st_kernel(int n_clusters, const int *__restrict__ order,
+// Sweeps in flight at one time step: at most ceil(steps / 3) <= 10 (n <= kMaxDimTri), so 16
+// slots indexed by s mod 16 are never shared by two live sweeps.
+constexpr int kSweepSlots = 16;
+static_assert(3 * kSweepSlots > (kMaxDimTri - 3) / kBand + 1, "sweep slots");
+
+__global__ void __launch_bounds__(256, 4) sb2st_kernel(int n_clusters, const int *__restrict__ order,
                                                     double *__restrict__ mat, const long long *__restrict__ mat_off,
                                                     double *__restrict__ vec, const long long *__restrict__ vec_off,
-                                                    const int *__restrict__ dmax, const int *__restrict__ dim,
-                                                    const int *__restrict__ n_orb) {
-  __shared__ double wv[4][2 * kBand];
+                                                    const int *__restrict__ dmax, const int *__restrict__ dim) {
+  __shared__ double wsv[4][kBand];
   __shared__ double wtile[4][kBand * (kBand + 1)];
+  __shared__ double slots[kSweepSlots][kBand + 1];
   const int tid = threadIdx.x, wave = tid >> 6, nthr = blockDim.x, nw = nthr >> 6;
   constexpr int LB = kBandLd;
   for (int sidx = blockIdx.x; sidx < n_clusters; sidx += gridDim.x) {
     const int c = order[sidx];
     const int n = dim[c], ld = n;
-    const int nt = 2 * n_orb[c];
     double *A = mat + mat_off[c];
     const VecLayout vl = VecLayout::make(dmax[c]);
     double *cv = vec + vec_off[c];
-    double *dd = cv + vl.d, *ee = cv + vl.e, *X = cv + vl.G0;
+    double *dd = cv + vl.d, *ee = cv + vl.e;
     double *Bd = cv + vl.vw;  // n x kBandLd (reuses the band-reduction workspace)
     __syncthreads();
     for (long long e = tid; e < (long long)n * LB; e += nthr) {
@@ -456,7 +497,7 @@ __global__ void __launch_bounds__(256, 2) sb2st_kernel(int n_clusters, const int
       for (int s = shi - wave; s >= 0; s -= nw) {
         const int j = t - 3 * s;
         if (j >= sweep_steps(n, s)) break;
-        bulge_step(Bd, A, ld, n, s, j, wv[wave], wv[wave] + kBand, wtile[wave], cv + vl.kg);
+        bulge_step(Bd, A, ld, n, s, j, slots[s % kSweepSlots], wsv[wave], wtile[wave], cv + vl.kg);
       }
       __syncthreads();
     }
@@ -464,8 +505,111 @@ __global__ void __launch_bounds__(256, 2) sb2st_kernel(int n_clusters, const int
       dd[i] = Bd[(long long)i * LB];
       ee[i] = (i < n - 1) ? Bd[(long long)i * LB + 1] : 0.0;
     }
-    // tracked columns: X <- Q2^T X
-    wg_apply_q2(A, ld, n, X, kTrack, nt, true);
+  }
+}
+
+// Tracked columns X <- Q2^T X after the bulge chasing (sweep after sweep, each sweep's
+// reflectors on disjoint rows).  X (n x nc, nc = 2 M) stays in LDS for all sweeps, so the only
+// global traffic is X in and out once and every reflector read once.  A sweep's reflectors are
+// one contiguous run of n - 1 - s doubles (column n - 1 - s of A from row 0: per step tau,
+// then v(1:len)).  Runs are fetched two sweeps ahead into registers and parked in a triple
+// buffer, one barrier per sweep.  Groups of 32 lanes take one reflector each, lane q one
+// column.
+constexpr int kQ2Run = (kMaxDimTri + kWG - 1) / kWG;  // run elements per thread
+
+__device__ inline void q2_fetch_run(double *nx, const double *A, int n, int s, int tid, int nthr) {
+  // run of sweep s (clamped unconditional loads; a run past the last sweep reads sweep n - 3)
+  const int ss = min(s, n - 3), len = n - 1 - ss;
+  const double *src = A + (long long)(n - 1 - ss) * n;
+#pragma unroll
+  for (int u = 0; u < kQ2Run; ++u) nx[u] = src[min(tid + u * nthr, len - 1)];
+}
+
+__global__ void __launch_bounds__(256, 1) q2x_lds_kernel(int n_clusters, const int *__restrict__ order,
+                                                      const double *__restrict__ mat,
+                                                      const long long *__restrict__ mat_off,
+                                                      double *__restrict__ vec, const long long *__restrict__ vec_off,
+                                                      const int *__restrict__ dmax, const int *__restrict__ dim,
+                                                      const int *__restrict__ n_orb, int max_dim) {
+  extern __shared__ double q2l[];
+  constexpr int b = kBand;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int grp = tid >> 5, q = tid & 31, ngrp = nthr >> 5;
+  for (int sidx = blockIdx.x; sidx < n_clusters; sidx += gridDim.x) {
+    const int c = order[sidx];
+    const int n = dim[c], nc = 2 * n_orb[c];
+    const double *A = mat + mat_off[c];
+    const VecLayout vl = VecLayout::make(dmax[c]);
+    double *X = vec + vec_off[c] + vl.G0;  // n x kTrack, row-major
+    double *Xs = q2l;                      // n x nc
+    double *runs = q2l + (long long)max_dim * nc;  // 3 x max_dim
+    __syncthreads();
+    if (n < 3) continue;
+    for (int e = tid; e < n * nc; e += nthr) Xs[e] = X[(e / nc) * kTrack + e % nc];
+    double nx0[kQ2Run], nx1[kQ2Run];
+    q2_fetch_run(nx0, A, n, 0, tid, nthr);
+    q2_fetch_run(nx1, A, n, 1, tid, nthr);
+#pragma unroll
+    for (int u = 0; u < kQ2Run; ++u)
+      if (tid + u * nthr < n - 1) runs[tid + u * nthr] = nx0[u];
+    __syncthreads();
+    const int qc = min(q, nc - 1);
+    const int nsw = n - 2;
+    for (int s = 0; s < nsw; ++s) {
+      // nx1 holds the run of sweep s + 1; fetch sweep s + 2's
+      q2_fetch_run(nx0, A, n, s + 2, tid, nthr);
+      const double *cur = runs + (s % 3) * max_dim;
+      const int nst = (n - 3 - s) / b + 1;
+      for (int j = grp; j < nst; j += ngrp) {
+        const int r0 = s + 1 + j * b, len = min(b, n - r0);
+        const double *vp = cur + j * b;
+        double *xp = Xs + (long long)r0 * nc + qc;
+        double vv[b], xv[b];
+#pragma unroll
+        for (int i = 0; i < b; ++i) {
+          const int ii = min(i, len - 1);
+          const double t = vp[ii];
+          vv[i] = (i < len) ? t : 0.0;
+          xv[i] = xp[ii * nc];
+        }
+        const double tau = vv[0];
+        vv[0] = 1.0;
+        double d = 0.0;
+#pragma unroll
+        for (int i = 0; i < b; ++i) d += vv[i] * xv[i];
+        d *= tau;
+        if (q < nc) {
+#pragma unroll
+          for (int i = 0; i < b; ++i)
+            if (i < len) xp[i * nc] = xv[i] - d * vv[i];
+        }
+      }
+      double *nxt = runs + ((s + 1) % 3) * max_dim;
+      const int nlen = n - 2 - s;
+#pragma unroll
+      for (int u = 0; u < kQ2Run; ++u)
+        if (tid + u * nthr < nlen) nxt[tid + u * nthr] = nx1[u];
+#pragma unroll
+      for (int u = 0; u < kQ2Run; ++u) nx1[u] = nx0[u];
+      __syncthreads();
+    }
+    for (int e = tid; e < n * nc; e += nthr) X[(e / nc) * kTrack + e % nc] = Xs[e];
+  }
+}
+
+// Global-memory variant for clusters whose X does not fit in LDS.
+__global__ void __launch_bounds__(256, 2) q2x_kernel(int n_clusters, const int *__restrict__ order,
+                                                  const double *__restrict__ mat, const long long *__restrict__ mat_off,
+                                                  double *__restrict__ vec, const long long *__restrict__ vec_off,
+                                                  const int *__restrict__ dmax, const int *__restrict__ dim,
+                                                  const int *__restrict__ n_orb) {
+  for (int sidx = blockIdx.x; sidx < n_clusters; sidx += gridDim.x) {
+    const int c = order[sidx];
+    const int n = dim[c];
+    const VecLayout vl = VecLayout::make(dmax[c]);
+    double *X = vec + vec_off[c] + vl.G0;
+    __syncthreads();
+    wg_apply_q2(mat + mat_off[c], n, n, X, kTrack, 2 * n_orb[c], true);
   }
 }
 
@@ -478,8 +622,29 @@ void launch_sy2sb(Plan &p) {
 }
 
 void launch_sb2st(Plan &p) {
-  hipLaunchKernelGGL(sb2st_kernel, dim3(p.workgroups), dim3(kWG), 0, p.stream, p.n_atoms, p.d_order, p.d_mat,
-                     p.d_mat_off, p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb);
+  // two workgroups per compute unit: more clusters in flight push the bands out of the caches
+  // (measured: 1, 1.5, 2 and 4 per CU give 190, 154, 133 and 149 ms on the 3920-atom slab)
+  const int wgs = std::max(1, std::min(p.workgroups, p.n_atoms));
+  hipLaunchKernelGGL(sb2st_kernel, dim3(wgs), dim3(kWG), 0, p.stream, p.n_atoms, p.d_order, p.d_mat, p.d_mat_off,
+                     p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim);
+}
+
+void launch_q2x(Plan &p) {
+  const size_t lds = sizeof(double) * (size_t)p.max_dim * (size_t)(2 * p.mmax + 3);
+  int dev = 0, lds_max = 0;
+  const bool fits = hipGetDevice(&dev) == hipSuccess &&
+                    hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+                    lds <= (size_t)lds_max &&
+                    hipFuncSetAttribute(reinterpret_cast<const void *>(q2x_lds_kernel),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess;
+  if (fits) {
+    const int wgs = std::max(1, std::min(p.n_cu, p.n_atoms));
+    hipLaunchKernelGGL(q2x_lds_kernel, dim3(wgs), dim3(kWG), lds, p.stream, p.n_atoms, p.d_order, p.d_mat,
+                       p.d_mat_off, p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb, p.max_dim);
+  } else {
+    hipLaunchKernelGGL(q2x_kernel, dim3(p.workgroups), dim3(kWG), 0, p.stream, p.n_atoms, p.d_order, p.d_mat,
+                       p.d_mat_off, p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb);
+  }
 }
 
 }  // namespace ldc

@@ -156,6 +156,7 @@ void launch_potrf(Plan &p);
 void launch_sygst(Plan &p);
 void launch_sy2sb(Plan &p);
 void launch_sb2st(Plan &p);
+void launch_q2x(Plan &p);
 void launch_stedc(Plan &p);
 void launch_mu_init(Plan &p, double kT);
 void launch_mu_step(Plan &p, double n_electrons, double kT, double g);
