@@ -235,22 +235,30 @@ __device__ __noinline__ void band_panel(double *__restrict__ A, int ld, int n, i
   __syncthreads();
   // Gst = -V^T V
   wg_gemm<G_B_RM | G_OVERWRITE>(Gst, b, VW, 2 * b, VW, 2 * b, b, b, m, sh);
-  // T (row-major): lane a forms row a
-  if (tid < b) {
-    const int a = tid;
-    for (int i = 0; i < b; ++i) {
-      double t;
-      if (i < a) t = 0.0;
-      else if (i == a) t = tt[j0 + i];
-      else {
+  // T (row-major), T(a, i) = -tau_i sum_{a <= q < i} T(a, q) G(q, i) for i > a, T(a, a) = tau_a:
+  // G = V^T V and tau in LDS, lane a keeps row a in registers (T(a, q) = 0 for q < a, so every
+  // lane runs the same fully unrolled recurrence)
+  {
+    double *Gs = sh, *taus = sh + b * b;
+    for (int e = tid; e < b * b; e += nthr) Gs[e] = -Gst[e];
+    if (tid < b) taus[tid] = tt[j0 + tid];
+    __syncthreads();
+    if (tid < b) {
+      const int a = tid;
+      double trow[b];
+#pragma unroll
+      for (int i = 0; i < b; ++i) {
         double acc = 0.0;
-        for (int q = a; q < i; ++q) acc -= Tp[a * b + q] * Gst[i * b + q];  // G(q, i) = -Gst(q, i)
-        t = -tt[j0 + i] * acc;
+#pragma unroll
+        for (int q = 0; q < i; ++q) acc += trow[q] * Gs[q * b + i];
+        const double ti = taus[i];
+        trow[i] = (i < a) ? 0.0 : ((i == a) ? ti : -ti * acc);
       }
-      Tp[a * b + i] = t;
+#pragma unroll
+      for (int i = 0; i < b; ++i) Tp[a * b + i] = trow[i];
     }
+    __syncthreads();
   }
-  __syncthreads();
   // VT = -V T
   wg_gemm<G_A_RM | G_B_RM | G_OVERWRITE | G_C_RM>(VT, b, VW, 2 * b, Tp, b, m, b, b, sh);
   // X = A22 V T  (into the W half of [V | W])

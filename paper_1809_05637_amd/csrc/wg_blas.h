@@ -42,9 +42,9 @@ enum : unsigned {
 // register covers 16 consecutive rows of one column (coalesced column-major stores):
 // the instruction's A operand takes op(B) (lane l: op(B)[k0 + l/16][c0 + l%16]) and its B
 // operand takes A (lane l: A[r0 + l%16][k0 + l/16]); register r of lane l then holds
-// C[r0 + l%16][c0 + 4 r + l/16].  The next K chunk of A and op(B) is fetched into registers
-// while the current one is multiplied; after the last chunk the same registers fetch C
-// (unless G_LATE_C).
+// C[r0 + l%16][c0 + 4 r + l/16].  The next K chunk of A and op(B) (after a tile's last
+// chunk: the next tile's first) is fetched into registers while the current one is multiplied;
+// with the last chunk C is fetched too (unless G_LATE_C).
 template <unsigned F>
 __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const double *B, int ldb, int m, int n, int k,
                         double *lds, int a_diag = -1, int b_rot = 0) {
@@ -127,23 +127,39 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
       Bs[(b_k + (B_KFAST ? 0 : q * B_STEP)) * LS + b_e + (B_KFAST ? q * B_STEP : 0)] = rb[q];
   };
   auto cidx = [&](int gr, int gc) { return C_RM ? gr * ldc + gc : gc * ldc + gr; };
+  // tiles in row-major order (G_LOWER: only tile row >= tile column)
+  auto next_tile = [&](int t) -> int {
+    for (; t < mt * nt; ++t)
+      if (!LOWER || t % nt <= t / nt) return t;
+    return -1;
+  };
+  auto k_end = [&](int r0) { return (a_diag >= 0) ? min(k, r0 + GT + a_diag) : k; };
 
-  for (int tile = 0; tile < mt * nt; ++tile) {
+  // Software pipeline over (tile, K chunk): the chunk after the one being multiplied is always
+  // in flight, including the first chunk of the next tile while the last chunk of this one runs.
+  double ra[PER], rb[PER];
+  int tile = next_tile(0);
+  int amode = 0;
+  if (tile >= 0) {
+    const int r0 = (tile / nt) * GT, c0 = (tile % nt) * GT;
+    amode = a_mode_of(r0, 0);
+    if (k_end(r0) > 0) {
+      fetchA(r0, 0, amode, ra);
+      fetchB(c0, 0, rb);
+    }
+  }
+  while (tile >= 0) {
     const int ti = tile / nt, tj = tile % nt;
-    if (LOWER && tj > ti) continue;
     const int r0 = ti * GT, c0 = tj * GT;
+    const int kend = k_end(r0);
+    const int nxt = next_tile(tile + 1);
+    const int r0n = (nxt >= 0) ? (nxt / nt) * GT : 0, c0n = (nxt >= 0) ? (nxt % nt) * GT : 0;
+    const bool fetch_next = nxt >= 0 && k_end(r0n) > 0;
     ldc_double4 acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b) acc[a][b] = ldc_double4{0.0, 0.0, 0.0, 0.0};
-    const int kend = (a_diag >= 0) ? min(k, r0 + GT + a_diag) : k;
-    double ra[PER], rb[PER];
-    int amode = a_mode_of(r0, 0);
-    if (kend > 0) {
-      fetchA(r0, 0, amode, ra);
-      fetchB(c0, 0, rb);
-    }
     double cold[2][2][4];
     for (int k0 = 0; k0 < kend; k0 += GK) {
       __syncthreads();
@@ -153,16 +169,23 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
         amode = a_mode_of(r0, k0 + GK);
         fetchA(r0, k0 + GK, amode, ra);
         fetchB(c0, k0 + GK, rb);
-      } else if (!OVERWRITE && PREFETCH_C) {
+      } else {
+        if (fetch_next) {
+          amode = a_mode_of(r0n, 0);
+          fetchA(r0n, 0, amode, ra);
+          fetchB(c0n, 0, rb);
+        }
+        if (!OVERWRITE && PREFETCH_C) {
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+          for (int a = 0; a < 2; ++a)
 #pragma unroll
-          for (int b = 0; b < 2; ++b)
+            for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int gr = r0 + wr * 32 + a * 16 + li, gc = c0 + wc * 32 + b * 16 + 4 * r + lk;
-              cold[a][b][r] = (gr < m && gc < n) ? C[cidx(gr, gc)] : 0.0;
-            }
+              for (int r = 0; r < 4; ++r) {
+                const int gr = r0 + wr * 32 + a * 16 + li, gc = c0 + wc * 32 + b * 16 + 4 * r + lk;
+                cold[a][b][r] = (gr < m && gc < n) ? C[cidx(gr, gc)] : 0.0;
+              }
+        }
       }
 #pragma unroll
       for (int s4 = 0; s4 < GK / 4; ++s4) {
@@ -178,6 +201,12 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
           for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[b], af[a], acc[a][b], 0, 0, 0);
       }
     }
+    if (kend <= 0 && fetch_next) {
+      amode = a_mode_of(r0n, 0);
+      fetchA(r0n, 0, amode, ra);
+      fetchB(c0n, 0, rb);
+    }
+    tile = nxt;
     if (kend <= 0 && !OVERWRITE) continue;  // nothing to subtract
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
