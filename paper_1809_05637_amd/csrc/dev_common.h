@@ -12,11 +12,47 @@ __device__ inline void report(DevStatus *st, int code, int where) {
   if (atomicCAS(&st->code, 0, code) == 0) atomicExch(&st->where, where);
 }
 
-// Sum over a 64-lane wavefront (every lane gets the total).
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+// Lane permutations of DPP moves within rows of 16 lanes: exchange with lane ^ 1 and lane ^ 2
+// inside each quad, mirror each 8-lane half row, mirror each row.
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
+template <int CTRL>
+__device__ inline double dpp_perm(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ inline double lane_value(double v, int l) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the 8 consecutive lanes of each group (every lane of the group gets its sum).
+__device__ inline double group8_sum(double v) {
+  v += dpp_perm<kDppXor1>(v);
+  v += dpp_perm<kDppXor2>(v);
+  v += dpp_perm<kDppHalfMirror>(v);
   return v;
+}
+
+// Sum over a 64-lane wavefront (every lane gets the total; all lanes must be active).
+// Row sums by DPP moves, then the four rows through scalar reads.
+__device__ inline double wave_sum(double v) {
+  v = group8_sum(v);
+  v += dpp_perm<kDppMirror>(v);
+  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+}
+
+__device__ inline double wave_max(double v) {
+  v = fmax(v, dpp_perm<kDppXor1>(v));
+  v = fmax(v, dpp_perm<kDppXor2>(v));
+  v = fmax(v, dpp_perm<kDppHalfMirror>(v));
+  v = fmax(v, dpp_perm<kDppMirror>(v));
+  return fmax(fmax(lane_value(v, 0), lane_value(v, 16)), fmax(lane_value(v, 32), lane_value(v, 48)));
 }
 
 // Workgroup sum of one value per thread; scratch: >= blockDim.x/64 doubles of LDS.
@@ -34,8 +70,7 @@ __device__ inline double block_sum(double v, double *scratch) {
 
 __device__ inline double block_max(double v, double *scratch) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  v = wave_max(v);
   __syncthreads();
   if (lane == 0) scratch[wid] = v;
   __syncthreads();

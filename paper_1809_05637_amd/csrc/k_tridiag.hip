@@ -35,7 +35,7 @@ constexpr int kRowRegs = kMaxDimTri / 64;   // rows of a panel column held per l
 // QR of the panel P = A(r:n, j0:j0+kBand) (column-major, ld), r = j0 + kBand, m = n - r.
 // On return P holds R on and above its diagonal and the Householder vectors below it (unit
 // diagonal implicit); tau_k goes to tt[j0 + k] (0 where the reflector has length <= 1).
-// lf: LEAF * m doubles of LDS; sm: 2 * LEAF * LEAF + 4 * LEAF doubles; red: 4 * LEAF.
+// lf: LEAF * m doubles of LDS; sm: 2 * LEAF * LEAF + 4 * LEAF doubles; red: 10 * LEAF.
 __device__ void panel_qr(double *__restrict__ A, int ld, int n, int j0, double *__restrict__ tt, double *lf,
                          double *sm, double *red) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nthr = blockDim.x, nw = nthr >> 6;
@@ -43,6 +43,7 @@ __device__ void panel_qr(double *__restrict__ A, int ld, int n, int j0, double *
   double *Tl = sm;                  // [LEAF][LEAF] leaf T (row-major)
   double *Gl = sm + LEAF * LEAF;    // [LEAF][LEAF] leaf V^T V
   double *tl = Gl + LEAF * LEAF;    // [LEAF] leaf tau
+  double *rk = red + 8 * LEAF;      // [2][LEAF] published row k
   for (int c0 = 0; c0 < kBand; c0 += LEAF) {
     const int R0 = r + c0, mp = n - R0;
     if (mp <= 0) {
@@ -56,21 +57,38 @@ __device__ void panel_qr(double *__restrict__ A, int ld, int n, int j0, double *
       lf[e] = A[(long long)(j0 + c0 + k) * ld + R0 + i];
     }
     __syncthreads();
-    for (int k = 0; k < LEAF; ++k) {
-      if (mp - k < 2) {
-        if (tid == 0) {
-          tt[j0 + c0 + k] = 0.0;
-          tl[k] = 0.0;
+    // Column k of the leaf: every thread owns rows i = tid + t nthr.  One pass over its rows
+    // applies reflector k - 1 and accumulates the sums for reflector k (|x(k+1:)|^2 and the dots
+    // of x(k+1:) with the later leaf columns); the owner of row k publishes that row, so a
+    // single barrier per column suffices (red and rk are double-buffered by k).
+    double tau_p = 0.0, beta_p = 0.0, sc_p = 0.0, wc_p[LEAF];
+#pragma unroll
+    for (int c = 0; c < LEAF; ++c) wc_p[c] = 0.0;
+    for (int k = 0; k <= LEAF; ++k) {
+      if (k >= 1) {
+        const int kp = k - 1;
+        for (int i = tid; i < mp; i += nthr) {
+          if (i < kp) continue;
+          const double v = (i == kp) ? 1.0 : lf[kp * mp + i] * sc_p;
+#pragma unroll
+          for (int c = 1; c < LEAF; ++c)
+            if (kp + c < LEAF) lf[(kp + c) * mp + i] -= tau_p * v * wc_p[c];
+          lf[kp * mp + i] = (i == kp) ? beta_p : v;
         }
-        continue;
       }
-      // sigma = |x(k+1:)|^2 and the raw dots of x(k+1:) with the later leaf columns
+      if (k == LEAF) break;
+      double *rkk = rk + (k & 1) * LEAF, *redk = red + (k & 1) * 4 * LEAF;
+      if (k < mp && k % nthr == tid) {
+#pragma unroll
+        for (int c = 0; c < LEAF; ++c)
+          if (k + c < LEAF) rkk[c] = lf[(k + c) * mp + k];
+      }
       double part[LEAF];
 #pragma unroll
       for (int q = 0; q < LEAF; ++q) part[q] = 0.0;
-      const double *xk = lf + k * mp;
-      for (int i = k + 1 + tid; i < mp; i += nthr) {
-        const double a = xk[i];
+      for (int i = tid; i < mp; i += nthr) {
+        if (i <= k) continue;
+        const double a = lf[k * mp + i];
         part[0] += a * a;
 #pragma unroll
         for (int c = 1; c < LEAF; ++c)
@@ -79,45 +97,35 @@ __device__ void panel_qr(double *__restrict__ A, int ld, int n, int j0, double *
 #pragma unroll
       for (int q = 0; q < LEAF; ++q) {
         const double t = wave_sum(part[q]);
-        if (lane == 0) red[wave * LEAF + q] = t;
+        if (lane == 0) redk[wave * LEAF + q] = t;
       }
       __syncthreads();
       double tot[LEAF];
 #pragma unroll
       for (int q = 0; q < LEAF; ++q) {
         double a = 0.0;
-        for (int w = 0; w < nw; ++w) a += red[w * LEAF + q];
+        for (int w = 0; w < nw; ++w) a += redk[w * LEAF + q];
         tot[q] = a;
       }
       const double sigma = tot[0];
-      const double alpha = xk[k];
-      double beta, tau, sc;
-      if (sigma == 0.0) {
-        tau = 0.0;
-        beta = alpha;
-        sc = 0.0;
+      const double alpha = (k < mp) ? rkk[0] : 0.0;
+      if (mp - k < 2 || sigma == 0.0) {
+        tau_p = 0.0;
+        beta_p = alpha;
+        sc_p = 0.0;
       } else {
-        beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
-        tau = (beta - alpha) / beta;
-        sc = 1.0 / (alpha - beta);
+        beta_p = -copysign(sqrt(alpha * alpha + sigma), alpha);
+        tau_p = (beta_p - alpha) / beta_p;
+        sc_p = 1.0 / (alpha - beta_p);
       }
-      double wc[LEAF];
 #pragma unroll
-      for (int c = 1; c < LEAF; ++c) wc[c] = (k + c < LEAF) ? lf[(k + c) * mp + k] + sc * tot[c] : 0.0;
-      __syncthreads();  // every thread has read red, alpha and the row-k entries
-      for (int i = k + tid; i < mp; i += nthr) {
-        const double v = (i == k) ? 1.0 : xk[i] * sc;
-#pragma unroll
-        for (int c = 1; c < LEAF; ++c)
-          if (k + c < LEAF) lf[(k + c) * mp + i] -= tau * v * wc[c];
-        lf[k * mp + i] = (i == k) ? beta : v;
-      }
+      for (int c = 1; c < LEAF; ++c) wc_p[c] = (k + c < LEAF && k < mp) ? rkk[c] + sc_p * tot[c] : 0.0;
       if (tid == 0) {
-        tt[j0 + c0 + k] = tau;
-        tl[k] = tau;
+        tt[j0 + c0 + k] = tau_p;
+        tl[k] = tau_p;
       }
-      __syncthreads();
     }
+    __syncthreads();
     // leaf back to A
     for (int e = tid; e < LEAF * mp; e += nthr) {
       const int k = e / mp, i = e % mp;
@@ -139,9 +147,7 @@ __device__ void panel_qr(double *__restrict__ A, int ld, int n, int j0, double *
         b = a + 1 + t;
         for (int i = b + 1 + sub; i < mp; i += 8) acc += lf[a * mp + i] * lf[b * mp + i];
       }
-      acc += __shfl_xor(acc, 1, 64);
-      acc += __shfl_xor(acc, 2, 64);
-      acc += __shfl_xor(acc, 4, 64);
+      acc = group8_sum(acc);
       if (g < LEAF * (LEAF - 1) / 2 && sub == 0) Gl[a * LEAF + b] = acc + (b < mp ? lf[a * mp + b] : 0.0);
     }
     __syncthreads();
@@ -269,9 +275,9 @@ __device__ __noinline__ void band_panel(double *__restrict__ A, int ld, int n, i
   for (int e = tid; e < b * b; e += nthr) Kst[e] *= 0.5;
   __syncthreads();
   // W = X - V K/2
-  wg_gemm<G_A_RM | G_C_RM | G_LATE_C>(VW + b, 2 * b, VW, 2 * b, Kst, b, m, b, b, sh);
+  wg_gemm<G_A_RM | G_C_RM>(VW + b, 2 * b, VW, 2 * b, Kst, b, m, b, b, sh);
   // A22 -= V W^T + W V^T (lower triangle)
-  wg_gemm<G_TRANS_B | G_LOWER | G_A_RM | G_B_RM | G_LATE_C>(A22, ld, VW, 2 * b, VW, 2 * b, m, m, 2 * b, sh, -1,
+  wg_gemm<G_TRANS_B | G_LOWER | G_A_RM | G_B_RM>(A22, ld, VW, 2 * b, VW, 2 * b, m, m, 2 * b, sh, -1,
                                                              b);
 }
 
@@ -285,7 +291,7 @@ __global__ void __launch_bounds__(256, 2) sy2sb_kernel(int n_clusters, const int
                                                        const int *__restrict__ n_orb) {
   extern __shared__ double sh[];
   __shared__ double sm[2 * LEAF * LEAF + 4 * LEAF];
-  __shared__ double red[4 * LEAF];
+  __shared__ double red[10 * LEAF];
   const int tid = threadIdx.x, nthr = blockDim.x;
   constexpr int b = kBand;
   for (int s = blockIdx.x; s < n_clusters; s += gridDim.x) {
