@@ -1,4 +1,5 @@
-"""Common chemical potential and density rows (Sec. II.C steps (iv)-(v); Eq. 13, 16, 24, 27).
+"""Common chemical potential, density rows and energy density rows (Sec. II.C steps
+(iv)-(v); Eq. 13, 16, 24, 25, 27).
 
 Readings where the text is open (the paper defers the mu search to earlier work):
 * Fermi-Dirac occupation f(x) = 1/(1+exp(x)) with x = (eps - mu)/kT, evaluated as
@@ -54,6 +55,14 @@ def density_rows(rows_center, rows, eps, mu, kT):
     """Eq. 24 with Eq. 27: D_{ij} = C_i diag(f) C_j^T for every j in ``rows``."""
     f = fermi((eps - mu) / kT)
     ci = rows_center * f[None, :]
+    return {j: ci @ cj.T for j, cj in rows.items()}
+
+
+def energy_density_rows(rows_center, rows, eps, mu, kT):
+    """Eq. 25 with Eq. 27: the energy-weighted integral of the spectral Green function of
+    cluster i gives e_{ij} = C_i diag(f eps) C_j^T for every j in ``rows``."""
+    fe = fermi((eps - mu) / kT) * eps
+    ci = rows_center * fe[None, :]
     return {j: ci @ cj.T for j, cj in rows.items()}
 
 

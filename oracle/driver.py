@@ -19,7 +19,7 @@ import numpy as np
 from .regions import plan_regions
 from .lno import all_lnos
 from .cluster import solve_cluster
-from .density import bisect_mu, density_rows, band_energy_and_count
+from .density import bisect_mu, density_rows, energy_density_rows, band_energy_and_count
 
 _G = {}
 
@@ -38,7 +38,10 @@ def _solve(i):
         mu, kT = _G["mu"], _G["kT"]
         if "rows" not in out:
             out = solve_cluster(_G["sys"], _G["regions"][i], _G["us"], _G["ranks"], keep_rows=True)
-        out["D"] = density_rows(out["rows"][int(_G["regions"][i].center)], out["rows"], out["eps"], mu, kT)
+        ci = out["rows"][int(_G["regions"][i].center)]
+        out["D"] = density_rows(ci, out["rows"], out["eps"], mu, kT)
+        if _G.get("energy"):
+            out["E"] = energy_density_rows(ci, out["rows"], out["eps"], mu, kT)
         del out["rows"]
     return i, out
 
@@ -56,7 +59,7 @@ def default_workers():
 
 
 def density_build(sysd, dprev=None, fixed_rank=None, mu=None, clusters=None, workers=None,
-                  lno=None, regions=None, verbose=False):
+                  lno=None, regions=None, verbose=False, energy=False):
     """One density build.
 
     dprev: previous density matrix (BSR values) for the LNOs; None or lno=False gives plain
@@ -64,7 +67,8 @@ def density_build(sysd, dprev=None, fixed_rank=None, mu=None, clusters=None, wor
     given, no bisection; density rows at this chemical potential.  clusters: restrict to
     these atoms (needs mu for density rows).  Returns a dict with D (BSR values, rows of
     the computed clusters), mu, e_band, n_e, spectra {i: (eps, w)}, ranks, us, regions,
-    dims, iters and timings.
+    dims, iters and timings.  energy: also the energy density rows (Eq. 25) as E and
+    tr_es = g Tr(E S).
     """
     t0 = time.time()
     kT = sysd["kT"]
@@ -88,7 +92,7 @@ def density_build(sysd, dprev=None, fixed_rank=None, mu=None, clusters=None, wor
     est = est / max(1, min(len(idx), 8)) * len(idx)
     keep_rows = est < 3e9
     _G.update(sys=sysd, regions=regions, us=us, ranks=ranks, keep_rows=keep_rows and mu is None,
-              mu=mu, kT=kT)
+              mu=mu, kT=kT, energy=energy)
     res = dict(_map(_solve, idx, workers))
     t_solve = time.time()
     spectra = {i: (res[i]["eps"], res[i]["w"]) for i in idx}
@@ -101,25 +105,37 @@ def density_build(sysd, dprev=None, fixed_rank=None, mu=None, clusters=None, wor
             for i in idx:
                 r = res[i]
                 res[i]["D"] = density_rows(r["rows"][i], r["rows"], r["eps"], mu, kT)
+                if energy:
+                    res[i]["E"] = energy_density_rows(r["rows"][i], r["rows"], r["eps"], mu, kT)
         else:
             _G.update(mu=mu)
             res2 = dict(_map(_solve, idx, workers))
             for i in idx:
                 res[i]["D"] = res2[i]["D"]
+                if energy:
+                    res[i]["E"] = res2[i]["E"]
     t_mu = time.time()
-    dvals = np.zeros_like(sysd["S"])
     row_ptr, col, blk_off, n_orb = sysd["row_ptr"], sysd["col"], sysd["blk_off"], sysd["n_orb"]
-    for i in idx:
-        dblk = res[i]["D"]
-        for b in range(row_ptr[i], row_ptr[i + 1]):
-            j = int(col[b])
-            dvals[blk_off[b]: blk_off[b] + n_orb[i] * n_orb[j]] = dblk[j].ravel()
+
+    def assemble(key):
+        vals = np.zeros_like(sysd["S"])
+        for i in idx:
+            blk = res[i][key]
+            for b in range(row_ptr[i], row_ptr[i + 1]):
+                j = int(col[b])
+                vals[blk_off[b]: blk_off[b] + n_orb[i] * n_orb[j]] = blk[j].ravel()
+        return vals
+
+    dvals = assemble("D")
     e_band, n_e = band_energy_and_count(sysd, dvals, g)
     e_spec = g * sum(float(np.sum(0.5 * (1 - np.tanh(0.5 * (spectra[i][0] - mu) / kT)) * spectra[i][0] * spectra[i][1]))
                      for i in idx)
     out = dict(D=dvals, mu=mu, e_band=e_band, n_e=n_e, e_band_spectral=e_spec, spectra=spectra,
                ranks=ranks, us=us, regions=regions, dims={i: res[i]["dim"] for i in idx}, iters=iters,
                times=dict(lno=t_lno - t0, solve=t_solve - t_lno, mu_rows=t_mu - t_solve, total=time.time() - t0))
+    if energy:
+        out["E"] = assemble("E")
+        out["tr_es"] = g * float(np.dot(out["E"], sysd["S"]))
     if verbose:
         print(f"[oracle] {sysd.get('name')} clusters={len(idx)} mu={mu:.12f} e_band={e_band:.10f} "
               f"times={out['times']}", flush=True)
