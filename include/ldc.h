@@ -141,6 +141,16 @@ ldc_status ldc_density(ldc_plan_t plan, double n_electrons, double kT, double *d
 ldc_status ldc_density_at(ldc_plan_t plan, double mu, double kT, double *d_D_out, double *e_band_out,
                           double *n_e_out);
 
+/* Energy density matrix rows (Eq. 25 with Eq. 27, the energy-weighted integral of the
+ * cluster's spectral Green function): e_{i alpha, j beta} = sum_mu f eps c_{i alpha,mu}
+ * c_{j beta,mu} for every j in the pattern row of i, written to d_E_out (same layout as S),
+ * at the chemical potential and kT of the last ldc_density / ldc_density_at call, from the
+ * spectra and tracked projections the plan keeps (no new eigensolve).  tr_es_out (host, may
+ * be NULL): g Tr(E S), which equals g sum_i sum_mu f eps w = E_band since F_i lies in the
+ * short region; when given, the call synchronizes.  LDC_ERR_STATE if no density was built
+ * since the last ldc_solve. */
+ldc_status ldc_energy_density(ldc_plan_t plan, double *d_E_out, double *tr_es_out);
+
 /* Copy one cluster's spectrum (eps ascending, weights) to host arrays of capacity
  * >= max_dim_pao; *dim receives its dimension.  Synchronizes. */
 ldc_status ldc_cluster_spectrum(ldc_plan_t plan, int atom, double *eps, double *w, int *dim);

@@ -7,7 +7,8 @@ raw device pointers (torch tensors supply device memory and the stream).  It fai
 loudly when the library is missing -- there is no CPU fallback.
 
 Entry points mirror include/ldc.h: Plan.lno (ldc_lno), Plan.solve (ldc_solve),
-Plan.density (ldc_density), Plan.density_at (ldc_density_at).
+Plan.density (ldc_density), Plan.density_at (ldc_density_at), Plan.energy_density
+(ldc_energy_density).
 """
 from __future__ import annotations
 
@@ -79,6 +80,7 @@ def load():
         "ldc_solve": (c_int, [c_void_p, c_void_p, c_void_p]),
         "ldc_density": (c_int, [c_void_p, c_double, c_double, c_void_p, P_double, P_double, P_double]),
         "ldc_density_at": (c_int, [c_void_p, c_double, c_double, c_void_p, P_double, P_double]),
+        "ldc_energy_density": (c_int, [c_void_p, c_void_p, P_double]),
         "ldc_cluster_spectrum": (c_int, [c_void_p, c_int, P_double, P_double, P_int]),
         "ldc_last_error": (ctypes.c_char_p, [c_void_p, P_int]),
         "ldc_cluster_dims": (c_int, [c_void_p, P_int]),
@@ -209,6 +211,13 @@ class Plan:
         self._check(self._lib.ldc_density_at(self._h, float(mu), float(kT), _ptr(D_out), ctypes.byref(eb),
                                              ctypes.byref(ne)))
         return eb.value, ne.value
+
+    def energy_density(self, E_out):
+        """ldc_energy_density: energy density rows (Eq. 25) at the last density's mu into E_out.
+        Returns g Tr(E S)."""
+        tr = c_double()
+        self._check(self._lib.ldc_energy_density(self._h, _ptr(E_out), ctypes.byref(tr)))
+        return tr.value
 
     def cluster_dims(self):
         """Reduced dimension of every cluster after the last solve."""

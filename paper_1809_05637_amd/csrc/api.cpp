@@ -370,6 +370,7 @@ ldc_status ldc_lno(ldc_plan_t plan, const double *d_S, const double *d_Dprev, co
   if (!plan) return LDC_ERR_ARG;
   Plan &p = plan->p;
   p.solved = 0;
+  p.has_density = 0;
   if (!d_Dprev) {
     p.lno_mode = 0;
     if (ranks_out)
@@ -438,6 +439,7 @@ static ldc_status finish_density(Plan &p, double g, double *mu_out, double *e_ba
   if (mu_out) *mu_out = st[8];
   if (e_band_out) *e_band_out = g * st[16];
   if (n_e_out) *n_e_out = g * st[17];
+  p.has_density = 1;
   return LDC_OK;
 }
 
@@ -469,7 +471,7 @@ ldc_status ldc_density(ldc_plan_t plan, double n_electrons, double kT, double *d
   }
   stage_end(p, 9);
   stage_begin(p, 10);
-  ldc::launch_density(p, kT, d_D_out, p.last_H, p.last_S, g);
+  ldc::launch_density(p, 0, d_D_out, p.last_H, p.last_S);
   stage_end(p, 10);
   HIPCHK(hipGetLastError());
   ldc_status s = finish_density(p, g, mu_out, e_band_out, n_e_out);
@@ -495,9 +497,28 @@ ldc_status ldc_density_at(ldc_plan_t plan, double mu, double kT, double *d_D_out
   st[7] = g;
   st[8] = mu;
   HIPCHK(hipMemcpyAsync(p.d_mu, st, sizeof(st), hipMemcpyHostToDevice, p.stream));
-  ldc::launch_density(p, kT, d_D_out, p.last_H, p.last_S, g);
+  ldc::launch_density(p, 0, d_D_out, p.last_H, p.last_S);
   HIPCHK(hipGetLastError());
   return finish_density(p, g, nullptr, e_band_out, n_e_out);
+}
+
+ldc_status ldc_energy_density(ldc_plan_t plan, double *d_E_out, double *tr_es_out) {
+  if (!plan || !d_E_out) return LDC_ERR_ARG;
+  Plan &p = plan->p;
+  if (!p.solved || !p.has_density) {
+    p.msg = "ldc_energy_density called before a density build on the current solve";
+    return LDC_ERR_STATE;
+  }
+  const double g = p.opt.spin_g > 0 ? p.opt.spin_g : 2;
+  ldc::launch_density(p, 1, d_E_out, p.last_H, p.last_S);
+  HIPCHK(hipGetLastError());
+  if (!tr_es_out) return LDC_OK;
+  ldc_status s = check_status(p);
+  if (s != LDC_OK) return s;
+  double st[32];
+  HIPCHK(hipMemcpy(st, p.d_mu, sizeof(st), hipMemcpyDeviceToHost));
+  *tr_es_out = g * st[19];
+  return LDC_OK;
 }
 
 ldc_status ldc_cluster_spectrum(ldc_plan_t plan, int atom, double *eps, double *w, int *dim) {

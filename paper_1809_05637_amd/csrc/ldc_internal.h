@@ -92,6 +92,7 @@ struct Plan {
 
   const double *last_H = nullptr, *last_S = nullptr;
   int solved = 0;
+  int has_density = 0;              // a density was built since the last ldc_solve
   size_t device_bytes = 0;
   std::string msg;
   int err_where = -1;
@@ -161,7 +162,9 @@ void launch_stedc(Plan &p);
 void launch_mu_init(Plan &p, double kT);
 void launch_mu_step(Plan &p, double n_electrons, double kT, double g);
 void launch_mu_fixed(Plan &p, double mu);
-void launch_density(Plan &p, double kT, double *d_D, const double *d_H, const double *d_S, double g);
+// energy = 0: density rows (sums of D.H and D.S to state[16..17]); 1: energy density rows
+// (sums of E.H and E.S to state[18..19]); at mu = state[MU_MU], kT = state[MU_KT].
+void launch_density(Plan &p, int energy, double *d_D, const double *d_H, const double *d_S);
 
 }  // namespace ldc
 

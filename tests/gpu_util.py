@@ -12,8 +12,9 @@ def to_dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to(device())
 
 
-def gpu_build(s, dprev=None, fixed_rank=None, mu=None, plan=None, keep_plan=False):
-    """One build (ldc_lno, ldc_solve, ldc_density or ldc_density_at).  Returns a dict."""
+def gpu_build(s, dprev=None, fixed_rank=None, mu=None, plan=None, keep_plan=False, energy=False):
+    """One build (ldc_lno, ldc_solve, ldc_density or ldc_density_at, and with energy=True
+    ldc_energy_density).  Returns a dict."""
     import torch
     import paper_1809_05637_amd as ldc
     print(f"[gpu] build {s.get('name')} atoms={s['n_atoms']} lno={dprev is not None}", flush=True)
@@ -32,6 +33,11 @@ def gpu_build(s, dprev=None, fixed_rank=None, mu=None, plan=None, keep_plan=Fals
         eb, ne = plan.density_at(mu, s["kT"], D)
     torch.cuda.synchronize()
     out = dict(D=D.cpu().numpy(), mu=mu, e_band=eb, n_e=ne, ranks=ranks)
+    if energy:
+        E = torch.zeros_like(S)
+        out["tr_es"] = plan.energy_density(E)
+        torch.cuda.synchronize()
+        out["E"] = E.cpu().numpy()
     if keep_plan:
         out["plan"] = plan
         out["dev"] = (H, S, D)
