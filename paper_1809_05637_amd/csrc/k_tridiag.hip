@@ -480,14 +480,17 @@ __device__ void bulge_step(double *__restrict__ Bd, double *__restrict__ A, int 
 // Sweeps in flight at one time step: at most ceil(steps / 3) <= 10 (n <= kMaxDimTri), so 16
 // slots indexed by s mod 16 are never shared by two live sweeps.
 constexpr int kSweepSlots = 16;
+// Wavefronts per chase workgroup: at most about ten sweeps are in flight at a time step, and
+// more waves per cluster hide the latency of each step without adding clusters in flight.
+constexpr int kChaseWaves = 8;
 static_assert(3 * kSweepSlots > (kMaxDimTri - 3) / kBand + 1, "sweep slots");
 
-__global__ void __launch_bounds__(256, 4) sb2st_kernel(int n_clusters, const int *__restrict__ order,
+__global__ void __launch_bounds__(64 * kChaseWaves, 4) sb2st_kernel(int n_clusters, const int *__restrict__ order,
                                                     double *__restrict__ mat, const long long *__restrict__ mat_off,
                                                     double *__restrict__ vec, const long long *__restrict__ vec_off,
                                                     const int *__restrict__ dmax, const int *__restrict__ dim) {
-  __shared__ double wsv[4][kBand];
-  __shared__ double wtile[4][kBand * (kBand + 1)];
+  __shared__ double wsv[kChaseWaves][kBand];
+  __shared__ double wtile[kChaseWaves][kBand * (kBand + 1)];
   __shared__ double slots[kSweepSlots][kBand + 1];
   const int tid = threadIdx.x, wave = tid >> 6, nthr = blockDim.x, nw = nthr >> 6;
   constexpr int LB = kBandLd;
@@ -637,9 +640,10 @@ void launch_sy2sb(Plan &p) {
 
 void launch_sb2st(Plan &p) {
   // two workgroups per compute unit: more clusters in flight push the bands out of the caches
-  // (measured: 1, 1.5, 2 and 4 per CU give 190, 154, 133 and 149 ms on the 3920-atom slab)
+  // (measured with four waves per workgroup: 1, 1.5, 2 and 4 per CU give 190, 154, 133 and
+  // 149 ms on the 3920-atom slab; eight waves at 2 per CU: 122 ms)
   const int wgs = std::max(1, std::min(p.workgroups, p.n_atoms));
-  hipLaunchKernelGGL(sb2st_kernel, dim3(wgs), dim3(kWG), 0, p.stream, p.n_atoms, p.d_order, p.d_mat, p.d_mat_off,
+  hipLaunchKernelGGL(sb2st_kernel, dim3(wgs), dim3(64 * kChaseWaves), 0, p.stream, p.n_atoms, p.d_order, p.d_mat, p.d_mat_off,
                      p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim);
 }
 
