@@ -526,12 +526,13 @@ __global__ void __launch_bounds__(64 * kChaseWaves, 4) sb2st_kernel(int n_cluste
 }
 
 // Tracked columns X <- Q2^T X after the bulge chasing (sweep after sweep, each sweep's
-// reflectors on disjoint rows).  X (n x nc, nc = 2 M) stays in LDS for all sweeps, so the only
-// global traffic is X in and out once and every reflector read once.  A sweep's reflectors are
-// one contiguous run of n - 1 - s doubles (column n - 1 - s of A from row 0: per step tau,
-// then v(1:len)).  Runs are fetched two sweeps ahead into registers and parked in a triple
-// buffer, one barrier per sweep.  Groups of 32 lanes take one reflector each, lane q one
-// column.
+// reflectors on disjoint rows).  Each workgroup takes one half of a cluster's 2M tracked
+// columns (the [L^{-1} E_i] or the [L^T E_i] half), so two workgroups fit a CU.  That half
+// (n x M) stays in LDS for all sweeps: the only global traffic is X in and out once and every
+// reflector read once per half.  A sweep's reflectors are one contiguous run of n - 1 - s
+// doubles (column n - 1 - s of A from row 0: per step tau, then v(1:len)).  Runs are fetched
+// two sweeps ahead into registers and parked in a triple buffer, one barrier per sweep.
+// Groups of 16 lanes take one reflector each, lane q one column (M <= 16).
 constexpr int kQ2Run = (kMaxDimTri + kWG - 1) / kWG;  // run elements per thread
 
 __device__ inline void q2_fetch_run(double *nx, const double *A, int n, int s, int tid, int nthr) {
@@ -542,7 +543,7 @@ __device__ inline void q2_fetch_run(double *nx, const double *A, int n, int s, i
   for (int u = 0; u < kQ2Run; ++u) nx[u] = src[min(tid + u * nthr, len - 1)];
 }
 
-__global__ void __launch_bounds__(256, 1) q2x_lds_kernel(int n_clusters, const int *__restrict__ order,
+__global__ void __launch_bounds__(256, 2) q2x_lds_kernel(int n_clusters, const int *__restrict__ order,
                                                       const double *__restrict__ mat,
                                                       const long long *__restrict__ mat_off,
                                                       double *__restrict__ vec, const long long *__restrict__ vec_off,
@@ -551,15 +552,15 @@ __global__ void __launch_bounds__(256, 1) q2x_lds_kernel(int n_clusters, const i
   extern __shared__ double q2l[];
   constexpr int b = kBand;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int grp = tid >> 5, q = tid & 31, ngrp = nthr >> 5;
-  for (int sidx = blockIdx.x; sidx < n_clusters; sidx += gridDim.x) {
-    const int c = order[sidx];
-    const int n = dim[c], nc = 2 * n_orb[c];
+  const int grp = tid >> 4, q = tid & 15, ngrp = nthr >> 4;
+  for (int item = blockIdx.x; item < 2 * n_clusters; item += gridDim.x) {
+    const int c = order[item >> 1], half = item & 1;
+    const int n = dim[c], nc = n_orb[c];
     const double *A = mat + mat_off[c];
     const VecLayout vl = VecLayout::make(dmax[c]);
-    double *X = vec + vec_off[c] + vl.G0;  // n x kTrack, row-major
-    double *Xs = q2l;                      // n x nc
-    double *runs = q2l + (long long)max_dim * nc;  // 3 x max_dim
+    double *X = vec + vec_off[c] + vl.G0 + half * nc;  // n x nc of the n x kTrack row-major block
+    double *Xs = q2l;                                  // n x nc
+    double *runs = q2l + (long long)max_dim * nc;      // 3 x max_dim
     __syncthreads();
     if (n < 3) continue;
     for (int e = tid; e < n * nc; e += nthr) Xs[e] = X[(e / nc) * kTrack + e % nc];
@@ -648,7 +649,7 @@ void launch_sb2st(Plan &p) {
 }
 
 void launch_q2x(Plan &p) {
-  const size_t lds = sizeof(double) * (size_t)p.max_dim * (size_t)(2 * p.mmax + 3);
+  const size_t lds = sizeof(double) * (size_t)p.max_dim * (size_t)(p.mmax + 3);
   int dev = 0, lds_max = 0;
   const bool fits = hipGetDevice(&dev) == hipSuccess &&
                     hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
@@ -656,7 +657,7 @@ void launch_q2x(Plan &p) {
                     hipFuncSetAttribute(reinterpret_cast<const void *>(q2x_lds_kernel),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess;
   if (fits) {
-    const int wgs = std::max(1, std::min(p.n_cu, p.n_atoms));
+    const int wgs = std::max(1, std::min(2 * p.n_cu, 2 * p.n_atoms));
     hipLaunchKernelGGL(q2x_lds_kernel, dim3(wgs), dim3(kWG), lds, p.stream, p.n_atoms, p.d_order, p.d_mat,
                        p.d_mat_off, p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb, p.max_dim);
   } else {
