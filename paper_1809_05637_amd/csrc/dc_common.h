@@ -123,11 +123,12 @@ __device__ inline double *dc_apply(int n, int ny, DcWs ws, double *ya, double *y
         if (kept) {
           const int ta = max(c0, lo), tb = min(c0 + kApplyChunk, lo + kp);
           for (int t = ta; t < tb; ++t) {
-            const double u = zj / (((dj - sdK[lo + sorig[t]]) - stau[t]) * snrm[t]);
+            const double u = zj * rcp_nr(((dj - sdK[lo + sorig[t]]) - stau[t]) * snrm[t]);
             const double *y = sy + (t - c0) * kMaxOrb;
+            // all kMaxOrb columns, unguarded (a guard per column would serialize the LDS
+            // reads); the entries past ny are never stored
 #pragma unroll
-            for (int cc = 0; cc < kMaxOrb; ++cc)
-              if (cc < ny) acc[cc] += u * y[cc];
+            for (int cc = 0; cc < kMaxOrb; ++cc) acc[cc] += u * y[cc];
           }
         }
       }

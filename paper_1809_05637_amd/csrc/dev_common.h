@@ -79,6 +79,16 @@ __device__ inline double block_max(double v, double *scratch) {
   return t;
 }
 
+// 1/x by the hardware reciprocal and two Newton steps (a few ulp; x finite, nonzero and of
+// normal magnitude -- the D&C denominators d_j - lambda are never zero for kept poles).
+__device__ inline double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 // Fermi-Dirac occupation f(x) = 1/(1+e^x), evaluated as (1 - tanh(x/2))/2.
 __device__ inline double fermi(double x) { return 0.5 * (1.0 - tanh(0.5 * x)); }
 

@@ -16,6 +16,8 @@
 // permutation, the rotations, the secular-equation data and the output order.
 #include "dc_common.h"
 
+#include <type_traits>
+
 namespace ldc {
 
 constexpr double kEps = 2.220446049250313e-16;
@@ -31,7 +33,7 @@ __device__ void secular_root(const double *__restrict__ d, const double *__restr
     const double delta = d[t + 1] - d[t];
     const double dt = d[t];
     double g = rinv;
-    for (int j = 0; j < k; ++j) g += z[j] * z[j] / ((d[j] - dt) - 0.5 * delta);
+    for (int j = 0; j < k; ++j) g += z[j] * z[j] * rcp_nr((d[j] - dt) - 0.5 * delta);
     if (g >= 0.0) {
       o = t;
       a = 0.0;
@@ -50,20 +52,33 @@ __device__ void secular_root(const double *__restrict__ d, const double *__restr
   }
   const double dorig = d[o];
   double tau = 0.5 * (a + b);
+  // sum of z_j^2 / (d_j - lambda) and of its derivative over [j0, j1), four independent
+  // partial sums (the terms' latency chains overlap)
+  auto sums = [&](int j0, int j1, double &sv, double &dv) {
+    double s4[4] = {0.0, 0.0, 0.0, 0.0}, d4[4] = {0.0, 0.0, 0.0, 0.0};
+    int j = j0;
+    for (; j + 4 <= j1; j += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double r = rcp_nr((d[j + u] - dorig) - tau);
+        const double term = z[j + u] * z[j + u] * r;
+        s4[u] += term;
+        d4[u] += term * r;
+      }
+    }
+    for (; j < j1; ++j) {
+      const double r = rcp_nr((d[j] - dorig) - tau);
+      const double term = z[j] * z[j] * r;
+      s4[0] += term;
+      d4[0] += term * r;
+    }
+    sv = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+    dv = (d4[0] + d4[1]) + (d4[2] + d4[3]);
+  };
   for (int it = 0; it < 100; ++it) {
-    double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
-    for (int j = 0; j <= t; ++j) {
-      const double r = 1.0 / ((d[j] - dorig) - tau);
-      const double term = z[j] * z[j] * r;
-      psi += term;
-      dpsi += term * r;
-    }
-    for (int j = t + 1; j < k; ++j) {
-      const double r = 1.0 / ((d[j] - dorig) - tau);
-      const double term = z[j] * z[j] * r;
-      phi += term;
-      dphi += term * r;
-    }
+    double psi, dpsi, phi, dphi;
+    sums(0, t + 1, psi, dpsi);
+    sums(t + 1, k, phi, dphi);
     const double g = rinv + psi + phi;
     const double err = 8.0 * (fabs(psi) + fabs(phi) + rinv) + fabs(tau) * (dpsi + dphi);
     if (g < 0.0) a = tau;
@@ -336,7 +351,7 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
       for (int i = 0; i < kp; ++i) {
         if (i == j) continue;
         const double num = (dj - dK[org[i]]) - tu[i];
-        prod *= num / (dj - dK[i]);
+        prod *= num * rcp_nr(dj - dK[i]);
       }
       const double ztj = copysign(sqrt(fmax(prod, 0.0)), S.z[lo + j]);
       R.zt[lo + j] = ztj;
@@ -353,7 +368,7 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
       const double dorig = dK[S.orig[lo + t]], tau = S.tau[lo + t];
       double s2 = 0.0;
       for (int j = 0; j < kp; ++j) {
-        const double u = zt[j] / ((dK[j] - dorig) - tau);
+        const double u = zt[j] * rcp_nr((dK[j] - dorig) - tau);
         s2 += u * u;
       }
       const double nv = sqrt(s2);
@@ -361,22 +376,29 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
       S.nrm[lo + t] = nv;
     }
     __syncthreads();
-    // Phase F: output order (ascending eigenvalue; ties by element index)
+    // Phase F: output order (ascending eigenvalue; ties by element index).  The values go to
+    // S.z first (free after phase C), then every element counts the smaller ones of its merge
+    // (the threads of a merge read the same entry in step).
     for (int q = tid; q < n; q += nthr) {
       const int lo = q - q % span;
       const int kp = R.cnt[lo];
       if (kp < 0) continue;
-      const int hi = min(lo + span, n), k = hi - lo;
+      const int x = q - lo;
+      S.z[q] = x < kp ? S.d[lo + S.orig[lo + x]] + S.tau[lo + x] : S.Ds[lo + S.kpos[lo + x]];
+    }
+    __syncthreads();
+    for (int q = tid; q < n; q += nthr) {
+      const int lo = q - q % span;
+      const int kp = R.cnt[lo];
+      if (kp < 0) continue;
+      const int hi = min(lo + span, n);
       const int e = q - lo;
-      auto val = [&](int x) -> double {
-        return x < kp ? S.d[lo + S.orig[lo + x]] + S.tau[lo + x] : S.Ds[lo + S.kpos[lo + x]];
-      };
-      const double ve = val(e);
+      const double ve = S.z[q];
       const long long ke = dc_key(ve);
       int rank = 0;
-      for (int x = 0; x < k; ++x) {
-        const long long kx = dc_key(val(x));
-        rank += (kx < ke) || (kx == ke && x < e);
+      for (int x = lo; x < hi; ++x) {
+        const long long kx = dc_key(S.z[x]);
+        rank += (kx < ke) || (kx == ke && x < q);
       }
       R.oo[lo + rank] = e;
       lam[lo + rank] = ve;
@@ -385,65 +407,92 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
     // Phase E: transformed rows, written in output order.  Output row q (merge [lo, lo+k),
     // element e = oo[q]) is sum_j u(e, j) G1(lo + kpos[j]) over the kept j (e < kp), or its own
     // row G1(lo + kpos[e]) (deflated e).  One output row per thread and pass; G1 is staged
-    // through LDS kChunk rows at a time, and a staged row p belongs to j = jinv[p], so the
-    // threads of one merge read the same LDS row in step (broadcast).
-    for (int qb = 0; qb < n; qb += nthr) {
-      constexpr int CH = DcLds::kChunk;
-      const int q = qb + tid;
-      int lo = 0, hi = 0, kp = -1, e = 0;
-      double dorig = 0.0, tau = 0.0, ninv = 0.0;
-      if (q < n) {
-        lo = q - q % span;
-        hi = min(lo + span, n);
-        kp = R.cnt[lo];
-        if (kp >= 0) {
-          e = R.oo[q];
-          if (e < kp) {
-            dorig = S.d[lo + S.orig[lo + e]];
-            tau = S.tau[lo + e];
-            ninv = 1.0 / S.nrm[lo + e];
-          }
-        }
-      }
-      const bool kept = q < n && kp >= 0 && e < kp;
-      double acc[kTrack];
-#pragma unroll
-      for (int cc = 0; cc < kTrack; ++cc) acc[cc] = 0.0;
-      // the rows any thread of this pass needs: [first merge start, last merge end)
-      const int rlo = qb - qb % span, rhi = min(n, ((min(qb + nthr, n) - 1) / span + 1) * span);
-      for (int c0 = rlo; c0 < rhi; c0 += CH) {
-        __syncthreads();
-        for (int t = tid; t < CH * nt; t += nthr) {
-          const int r = t / nt, cc = t % nt;
-          S.g[r * kTrack + cc] = (c0 + r < n) ? G1[(long long)(c0 + r) * kTrack + cc] : 0.0;
-        }
-        __syncthreads();
-        if (kept) {
-          const int pa = max(c0, lo), pb = min(c0 + CH, hi);
-          const double *dK = S.d + lo, *zt = S.zt + lo;
-          for (int pp = pa; pp < pb; ++pp) {
-            const int j = S.jinv[pp];
-            if (j >= kp) continue;
-            const double w = zt[j] / ((dK[j] - dorig) - tau) * ninv;
-            const double *g = S.g + (pp - c0) * kTrack;
-#pragma unroll
-            for (int cc = 0; cc < kTrack; ++cc)
-              if (cc < nt) acc[cc] += w * g[cc];
-          }
-        }
-      }
-      if (q < n && kp >= 0) {
-        if (!kept) {
-          const double *g = G1 + (long long)(lo + S.kpos[lo + e]) * kTrack;
-#pragma unroll
-          for (int cc = 0; cc < kTrack; ++cc)
-            if (cc < nt) acc[cc] = g[cc];
-        }
-#pragma unroll
-        for (int cc = 0; cc < kTrack; ++cc)
-          if (cc < nt) G0[(long long)q * kTrack + cc] = acc[cc];
-      }
+    // through LDS kChunk rows at a time.  A staged row p carries its pole and Loewner z in
+    // S.Ds[p] and S.z[p] (the merge data of row p's j = jinv[p]; a deflated row has z = 0 and a
+    // far pole, so its weight is exactly zero), so the threads of one merge read the same LDS
+    // entries in step (broadcast) and, when merges span whole chunks, run a fixed 32-row loop.
+    for (int pp = tid; pp < n; pp += nthr) {
+      const int lo = pp - pp % span;
+      const int kp = R.cnt[lo];
+      if (kp < 0) continue;
+      const int j = S.jinv[pp];
+      const bool kj = j < kp;
+      S.Ds[pp] = kj ? S.d[lo + j] : 1e300;
+      S.z[pp] = kj ? S.zt[lo + j] : 0.0;
     }
+    // the columns are summed unguarded up to a compile-time count NT >= nt (entries past nt are
+    // never stored): a guard per column would serialize the LDS reads
+    auto transform = [&](auto ntc) {
+      constexpr int NT = decltype(ntc)::value;
+      for (int qb = 0; qb < n; qb += nthr) {
+        constexpr int CH = DcLds::kChunk;
+        const int q = qb + tid;
+        int lo = 0, hi = 0, kp = -1, e = 0;
+        double dorig = 0.0, tau = 0.0, ninv = 0.0;
+        if (q < n) {
+          lo = q - q % span;
+          hi = min(lo + span, n);
+          kp = R.cnt[lo];
+          if (kp >= 0) {
+            e = R.oo[q];
+            if (e < kp) {
+              dorig = S.d[lo + S.orig[lo + e]];
+              tau = S.tau[lo + e];
+              ninv = 1.0 / S.nrm[lo + e];
+            }
+          }
+        }
+        const bool kept = q < n && kp >= 0 && e < kp;
+        double acc[NT];
+#pragma unroll
+        for (int cc = 0; cc < NT; ++cc) acc[cc] = 0.0;
+        // the rows any thread of this pass needs: [first merge start, last merge end)
+        const int rlo = qb - qb % span, rhi = min(n, ((min(qb + nthr, n) - 1) / span + 1) * span);
+        for (int c0 = rlo; c0 < rhi; c0 += CH) {
+          __syncthreads();
+          for (int t = tid; t < CH * nt; t += nthr) {
+            const int r = t / nt, cc = t % nt;
+            S.g[r * kTrack + cc] = (c0 + r < n) ? G1[(long long)(c0 + r) * kTrack + cc] : 0.0;
+          }
+          __syncthreads();
+          if (!kept || c0 + CH <= lo || c0 >= hi) continue;
+          if (span >= CH) {
+            // the chunk lies inside this merge (merges start at multiples of span >= CH); rows
+            // past the end of the matrix are masked
+#pragma unroll 4
+            for (int r = 0; r < CH; ++r) {
+              const int pp = min(c0 + r, n - 1);
+              const double w0 = S.z[pp] * rcp_nr((S.Ds[pp] - dorig) - tau) * ninv;
+              const double w = (c0 + r < hi) ? w0 : 0.0;
+              const double *g = S.g + r * kTrack;
+#pragma unroll
+              for (int cc = 0; cc < NT; ++cc) acc[cc] += w * g[cc];
+            }
+          } else {
+            const int pa = max(c0, lo), pb = min(c0 + CH, hi);
+            for (int pp = pa; pp < pb; ++pp) {
+              const double w = S.z[pp] * rcp_nr((S.Ds[pp] - dorig) - tau) * ninv;
+              const double *g = S.g + (pp - c0) * kTrack;
+#pragma unroll
+              for (int cc = 0; cc < NT; ++cc) acc[cc] += w * g[cc];
+            }
+          }
+        }
+        if (q < n && kp >= 0) {
+          if (!kept) {
+            const double *g = G1 + (long long)(lo + S.kpos[lo + e]) * kTrack;
+#pragma unroll
+            for (int cc = 0; cc < NT; ++cc)
+              if (cc < nt) acc[cc] = g[cc];
+          }
+#pragma unroll
+          for (int cc = 0; cc < NT; ++cc)
+            if (cc < nt) G0[(long long)q * kTrack + cc] = acc[cc];
+        }
+      }
+    };
+    if (nt <= 20) transform(std::integral_constant<int, 20>{});
+    else transform(std::integral_constant<int, kTrack>{});
     __syncthreads();
   }
 }

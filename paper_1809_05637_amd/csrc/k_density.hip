@@ -102,7 +102,7 @@ __global__ void mu_finalize_kernel(int mode, int nparts, double *__restrict__ st
 
 // Density rows (Eq. 24 with Eq. 27, weights f) or energy density rows (Eq. 25 with Eq. 27,
 // weights f eps; energy != 0) of every cluster at mu = state[MU_MU].
-__global__ void __launch_bounds__(256) density_kernel(
+__global__ void __launch_bounds__(256, 2) density_kernel(
     int energy, int n_clusters, const int *__restrict__ order, double *__restrict__ mat, const long long *__restrict__ mat_off,
     double *__restrict__ vec, const long long *__restrict__ vec_off, int *__restrict__ ivec,
     const long long *__restrict__ ivec_off, const int *__restrict__ dmax, const int *__restrict__ dim,

@@ -27,14 +27,20 @@ __global__ void __launch_bounds__(256) gather_kernel(int n_clusters, const int *
                                                      int *__restrict__ dim) {
   __shared__ int off[kMaxMembers + 1];
   __shared__ int dm[kMaxMembers];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ int matom[kMaxMembers];
+  __shared__ int morb[kMaxMembers];  // M_j, negated for a long member (LNO contraction)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   for (int s = blockIdx.x; s < n_clusters; s += gridDim.x) {
     const int c = order[s];
     const int mb = mem_ptr[c], nm = mem_ptr[c + 1] - mb;
     __syncthreads();
     for (int a = tid; a < nm; a += blockDim.x) {
       const int atom = mem_atom[mb + a];
-      dm[a] = (lno_mode && mem_long[mb + a]) ? rank[atom] : n_orb[atom];
+      const int m = n_orb[atom];
+      const bool lg = lno_mode && mem_long[mb + a];
+      dm[a] = lg ? rank[atom] : m;
+      matom[a] = atom;
+      morb[a] = lg ? -m : m;
     }
     __syncthreads();
     if (tid == 0) {
@@ -51,53 +57,87 @@ __global__ void __launch_bounds__(256) gather_kernel(int n_clusters, const int *
       Sc[e] = 0.0;
     }
     __syncthreads();
-    for (int pp = pair_ptr[c] + wave; pp < pair_ptr[c + 1]; pp += (blockDim.x >> 6)) {
-      const int ab = pair_ab[pp];
-      const int a = ab & 0xffff, b = ab >> 16;
-      const int blk = pair_blk[pp];
-      const int ja = mem_atom[mb + a], jb = mem_atom[mb + b];
-      const int ma = n_orb[ja], mbb = n_orb[jb];
-      const bool la = lno_mode && mem_long[mb + a];
-      const bool lb = lno_mode && mem_long[mb + b];
-      const int da = dm[a], db = dm[b];
-      const double *hb = H + blk_off[blk];
-      const double *sb = S + blk_off[blk];
-      const double *Ua = U + (long long)ja * kMaxOrb * kMaxOrb;
-      const double *Ub = U + (long long)jb * kMaxOrb * kMaxOrb;
-      for (int e = lane; e < da * db; e += 64) {
-        const int r = e % da, q = e / da;
-        double h = 0.0, sv = 0.0;
+    // Pairs in batches of 64 per wave: the lanes first load the batch's pair records and block
+    // offsets together, then each half-wave takes one pair at a time (records by shuffle), so
+    // a pair costs one round trip to its block instead of a chain of dependent loads.
+    const int p_end = pair_ptr[c + 1];
+    const int half = lane >> 5, hl = lane & 31;
+    for (int pb = pair_ptr[c] + wave * 64; pb < p_end; pb += nw * 64) {
+      const int pl = min(pb + lane, p_end - 1);
+      const int ab_l = pair_ab[pl];
+      const long long bo_l = blk_off[pair_blk[pl]];
+      const int bo_lo = (int)(unsigned long long)bo_l, bo_hi = (int)((unsigned long long)bo_l >> 32);
+      const int np = min(64, p_end - pb);
+      for (int i = 0; i < np; i += 2) {
+        const int src = min(i + half, np - 1);
+        const int ab = __shfl(ab_l, src, 64);
+        const long long bo = (long long)(((unsigned long long)(unsigned)__shfl(bo_hi, src, 64) << 32) |
+                                         (unsigned)__shfl(bo_lo, src, 64));
+        const int a = ab & 0xffff, b = ab >> 16;
+        const int da = dm[a], db = dm[b];
+        const int ma_s = morb[a], mb_s = morb[b];
+        const bool la = ma_s < 0, lb = mb_s < 0;
+        const int ma = la ? -ma_s : ma_s, mbb = lb ? -mb_s : mb_s;
+        const int ne = (i + half < np) ? da * db : 0;
+        const double *hb = H + bo;
+        const double *sb = S + bo;
+        const long long ob = (long long)off[b] * n + off[a];
         if (!la && !lb) {
-          h = hb[r * mbb + q];
-          sv = sb[r * mbb + q];
-        } else if (la && !lb) {
-          for (int al = 0; al < ma; ++al) {
-            const double u = Ua[al + r * ma];
-            h += u * hb[al * mbb + q];
-            sv += u * sb[al * mbb + q];
-          }
-        } else if (!la && lb) {
-          for (int be = 0; be < mbb; ++be) {
-            const double u = Ub[be + q * mbb];
-            h += hb[r * mbb + be] * u;
-            sv += sb[r * mbb + be] * u;
+          // plain block copy: four elements per lane in flight (clamped loads, masked stores)
+          for (int e0 = hl; e0 < ne; e0 += 128) {
+            double hv[4], sv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int e = min(e0 + 32 * u, ne - 1), r = e % da, q = e / da;
+              hv[u] = hb[r * mbb + q];
+              sv[u] = sb[r * mbb + q];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int e = e0 + 32 * u;
+              if (e < ne) {
+                const long long o = ob + (long long)(e / da) * n + e % da;
+                Hc[o] = hv[u];
+                Sc[o] = sv[u];
+              }
+            }
           }
         } else {
-          for (int al = 0; al < ma; ++al) {
-            double th = 0.0, ts = 0.0;
-            for (int be = 0; be < mbb; ++be) {
-              const double u = Ub[be + q * mbb];
-              th += hb[al * mbb + be] * u;
-              ts += sb[al * mbb + be] * u;
+          const double *Ua = U + (long long)matom[a] * kMaxOrb * kMaxOrb;
+          const double *Ub = U + (long long)matom[b] * kMaxOrb * kMaxOrb;
+          for (int e = hl; e < ne; e += 32) {
+            const int r = e % da, q = e / da;
+            double h = 0.0, sv = 0.0;
+            if (la && !lb) {
+              for (int al = 0; al < ma; ++al) {
+                const double u = Ua[al + r * ma];
+                h += u * hb[al * mbb + q];
+                sv += u * sb[al * mbb + q];
+              }
+            } else if (!la && lb) {
+              for (int be = 0; be < mbb; ++be) {
+                const double u = Ub[be + q * mbb];
+                h += hb[r * mbb + be] * u;
+                sv += sb[r * mbb + be] * u;
+              }
+            } else {
+              for (int al = 0; al < ma; ++al) {
+                double th = 0.0, ts = 0.0;
+                for (int be = 0; be < mbb; ++be) {
+                  const double u = Ub[be + q * mbb];
+                  th += hb[al * mbb + be] * u;
+                  ts += sb[al * mbb + be] * u;
+                }
+                const double u = Ua[al + r * ma];
+                h += u * th;
+                sv += u * ts;
+              }
             }
-            const double u = Ua[al + r * ma];
-            h += u * th;
-            sv += u * ts;
+            const long long o = ob + (long long)q * n + r;
+            Hc[o] = h;
+            Sc[o] = sv;
           }
         }
-        const long long o = (long long)(off[b] + q) * n + off[a] + r;
-        Hc[o] = h;
-        Sc[o] = sv;
       }
     }
   }
@@ -151,16 +191,21 @@ __device__ void wg_rows_times_small(const double *src, int lds_, double *dst, in
 __device__ inline void lds_tri_inverse(double (*L11)[NB + 1], double (*Li)[NB + 1], int jb) {
   const int tid = threadIdx.x;
   if (tid < NB) {
+    // lane c keeps column c in registers; the rows of L11 are read by every lane in step
+    // (broadcast), and x(t) = 0 for t < c makes the full sums equal to the sums from t = c
     const int c = tid;
+    double x[NB];
+#pragma unroll
     for (int r = 0; r < NB; ++r) {
-      double val = 0.0;
-      if (c < jb && r < jb && r >= c) {
-        double acc = (r == c) ? 1.0 : 0.0;
-        for (int t = c; t < r; ++t) acc -= L11[r][t] * Li[t][c];
-        val = acc / L11[r][r];
-      }
-      Li[r][c] = val;
+      double acc = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+      for (int t = 0; t < r; ++t) acc -= L11[r][t] * x[t];
+      const bool on = c < jb && r < jb && r >= c;
+      const double q = acc / L11[r][r];
+      x[r] = on ? q : 0.0;
     }
+#pragma unroll
+    for (int r = 0; r < NB; ++r) Li[r][c] = x[r];
   }
   __syncthreads();
 }
@@ -193,24 +238,40 @@ __global__ void __launch_bounds__(256, 2) potrf_kernel(int n_clusters, const int
         L11[r][q] = (r < jb && q < jb && r >= q) ? S[(long long)(j0 + q) * ld + j0 + r] : 0.0;
       }
       __syncthreads();
-      for (int q = 0; q < jb; ++q) {
-        if (tid == 0) {
-          double piv = L11[q][q];
-          if (!(piv > 0.0)) {
-            bad = 1;
-            piv = 1.0;
+      // unblocked factor of the diagonal block by wave 0 alone: lane r keeps row r in
+      // registers, the pivot comes by a lane read and column q through LDS (no workgroup
+      // barriers inside the block)
+      if (tid < 64) {
+        const int r = tid;
+        double row[NB];
+#pragma unroll
+        for (int t = 0; t < NB; ++t) row[t] = (r < jb) ? L11[min(r, NB - 1)][t] : 0.0;
+        int badl = 0;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          if (q < jb) {
+            const double pv = lane_value(row[q], q);
+            const bool ok = pv > 0.0;
+            badl |= ok ? 0 : 1;
+            const double sp = sqrt(ok ? pv : 1.0);
+            row[q] = (r == q) ? sp : ((r > q) ? row[q] / sp : row[q]);
+            if (r < NB) Li[r][0] = row[q];  // column q of L, staged for the update
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int t = q + 1; t < NB; ++t) {
+              const double ltq = Li[t][0];
+              if (r >= t) row[t] -= row[q] * ltq;
+            }
+            __builtin_amdgcn_wave_barrier();
           }
-          L11[q][q] = sqrt(piv);
         }
-        __syncthreads();
-        if (tid > q && tid < jb) L11[tid][q] /= L11[q][q];
-        __syncthreads();
-        for (int e = tid; e < NB * NB; e += blockDim.x) {
-          const int r = e % NB, t = e / NB;
-          if (t > q && r >= t && r < jb) L11[r][t] -= L11[r][q] * L11[t][q];
+        if (r < jb) {
+#pragma unroll
+          for (int t = 0; t < NB; ++t) L11[r][t] = (t <= r) ? row[t] : 0.0;
         }
-        __syncthreads();
+        if (r == 0 && badl) bad = 1;
       }
+      __syncthreads();
       for (int e = tid; e < NB * NB; e += blockDim.x) {
         const int r = e % NB, q = e / NB;
         if (r < jb && q < jb && r >= q) S[(long long)(j0 + q) * ld + j0 + r] = L11[r][q];

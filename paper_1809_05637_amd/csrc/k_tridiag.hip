@@ -266,16 +266,16 @@ __device__ __noinline__ void band_panel(double *__restrict__ A, int ld, int n, i
     __syncthreads();
   }
   // VT = -V T
-  wg_gemm<G_A_RM | G_B_RM | G_OVERWRITE | G_C_RM>(VT, b, VW, 2 * b, Tp, b, m, b, b, sh);
+  wg_gemm<G_A_RM | G_B_RM | G_OVERWRITE | G_C_RM, 128, 32>(VT, b, VW, 2 * b, Tp, b, m, b, b, sh);
   // X = A22 V T  (into the W half of [V | W])
   double *A22 = A + (long long)r * ld + r;
-  wg_gemm<G_A_SYM | G_B_RM | G_OVERWRITE | G_C_RM>(VW + b, 2 * b, A22, ld, VT, b, m, b, m, sh);
+  wg_gemm<G_A_SYM | G_B_RM | G_OVERWRITE | G_C_RM, 128, 32>(VW + b, 2 * b, A22, ld, VT, b, m, b, m, sh);
   // K = (V T)^T X, then K/2
   wg_gemm<G_B_RM | G_OVERWRITE>(Kst, b, VT, b, VW + b, 2 * b, b, b, m, sh);
   for (int e = tid; e < b * b; e += nthr) Kst[e] *= 0.5;
   __syncthreads();
   // W = X - V K/2
-  wg_gemm<G_A_RM | G_C_RM>(VW + b, 2 * b, VW, 2 * b, Kst, b, m, b, b, sh);
+  wg_gemm<G_A_RM | G_C_RM, 128, 32>(VW + b, 2 * b, VW, 2 * b, Kst, b, m, b, b, sh);
   // A22 -= V W^T + W V^T (lower triangle)
   wg_gemm<G_TRANS_B | G_LOWER | G_A_RM | G_B_RM>(A22, ld, VW, 2 * b, VW, 2 * b, m, m, 2 * b, sh, -1,
                                                              b);
@@ -283,7 +283,7 @@ __device__ __noinline__ void band_panel(double *__restrict__ A, int ld, int n, i
 
 // ---------------------------------------------------------------------------------------
 // Stage 1: reduction to band form (see the top of the file).  Dynamic LDS: max(LEAF * nmax,
-// kGemmLds, kQapplyLds) doubles.
+// kGemmLds, kGemmLdsTall, kQapplyLds) doubles.
 __global__ void __launch_bounds__(256, 2) sy2sb_kernel(int n_clusters, const int *__restrict__ order,
                                                        double *__restrict__ mat, const long long *__restrict__ mat_off,
                                                        double *__restrict__ vec, const long long *__restrict__ vec_off,
@@ -634,7 +634,7 @@ __global__ void __launch_bounds__(256, 2) q2x_kernel(int n_clusters, const int *
 // ---------------------------------------------------------------------------------------
 void launch_sy2sb(Plan &p) {
   const size_t lds =
-      sizeof(double) * std::max({(size_t)LEAF * p.max_dim, (size_t)kGemmLds, (size_t)kQapplyLds});
+      sizeof(double) * std::max({(size_t)LEAF * p.max_dim, (size_t)kGemmLds, (size_t)kGemmLdsTall, (size_t)kQapplyLds});
   hipLaunchKernelGGL(sy2sb_kernel, dim3(p.workgroups), dim3(kWG), lds, p.stream, p.n_atoms, p.d_order, p.d_mat,
                      p.d_mat_off, p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb);
 }

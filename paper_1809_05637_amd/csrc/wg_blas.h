@@ -10,8 +10,10 @@ constexpr int GT = 64;    // output tile edge
 constexpr int GK = 32;    // K chunk
 constexpr int GPAD = 1;   // LDS padding (doubles)
 
-// LDS needed by wg_gemm: 2 * GK * (GT + GPAD) doubles.
+// LDS needed by wg_gemm: 2 * GK * (GT + GPAD) doubles; by the tall 128 x 32 tiles
+// (wg_gemm<F, 128, 32>): GK * (128 + 32 + 2 GPAD).
 constexpr int kGemmLds = 2 * GK * (GT + GPAD);
+constexpr int kGemmLdsTall = GK * (128 + 32 + 2 * GPAD);
 
 typedef double ldc_double4 __attribute__((ext_vector_type(4)));
 
@@ -37,50 +39,53 @@ enum : unsigned {
 // is read along rows of the stored lower triangle, the others down its columns (coalesced
 // except in the chunks that cross the diagonal).
 //
-// 64 x 64 output tiles; each of the 4 waves owns a 32 x 32 quarter as 2 x 2 blocks of
-// v_mfma_f64_16x16x4 (FP64 matrix cores).  Operands are swapped so that each output
+// TM x TN output tiles (64 x 64, or 128 x 32 for outputs 32 columns wide); each of the 4
+// waves owns a 32 x 32 part as 2 x 2 blocks of v_mfma_f64_16x16x4 (FP64 matrix cores).  Operands are swapped so that each output
 // register covers 16 consecutive rows of one column (coalesced column-major stores):
 // the instruction's A operand takes op(B) (lane l: op(B)[k0 + l/16][c0 + l%16]) and its B
 // operand takes A (lane l: A[r0 + l%16][k0 + l/16]); register r of lane l then holds
 // C[r0 + l%16][c0 + 4 r + l/16].  The next K chunk of A and op(B) (after a tile's last
 // chunk: the next tile's first) is fetched into registers while the current one is multiplied;
 // with the last chunk C is fetched too (unless G_LATE_C).
-template <unsigned F>
+template <unsigned F, int TM = GT, int TN = GT>
 __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const double *B, int ldb, int m, int n, int k,
                         double *lds, int a_diag = -1, int b_rot = 0) {
   constexpr bool TRANS_B = F & G_TRANS_B, LOWER = F & G_LOWER, A_RM = F & G_A_RM, B_RM = F & G_B_RM;
   constexpr bool OVERWRITE = F & G_OVERWRITE, PREFETCH_C = !(F & G_LATE_C), C_RM = F & G_C_RM;
   constexpr bool A_SYM = F & G_A_SYM;
   static_assert(!(A_SYM && A_RM), "a symmetric A is stored column-major");
-  constexpr int LS = GT + GPAD;
-  constexpr int PER = GT * GK / 256;  // staged elements per thread and operand (8)
-  double *As = lds;                   // [GK][LS]
-  double *Bs = lds + GK * LS;         // [GK][LS]
+  static_assert(TM * TN == 4 * 32 * 32 && TM % 32 == 0 && TN % 32 == 0, "four 32 x 32 wave parts");
+  static_assert(!LOWER || TM == TN, "lower-triangle tiling needs square tiles");
+  constexpr int LSA = TM + GPAD, LSB = TN + GPAD;
+  constexpr int PERA = TM * GK / 256, PERB = TN * GK / 256;  // staged elements per thread
+  double *As = lds;                   // [GK][LSA]
+  double *Bs = lds + GK * LSA;        // [GK][LSB]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave / (TN / 32), wc = wave % (TN / 32);
   const int li = lane & 15, lk = lane >> 4;
-  const int mt = (m + GT - 1) / GT, nt = (n + GT - 1) / GT;
+  const int mt = (m + TM - 1) / TM, nt = (n + TN - 1) / TN;
   // Staging: element q of this thread's share of a 64 x GK tile sits at (e + q STEP) along
   // the 64 edge and kk along K (K-fast layout), or at e along the edge and (kk + q STEP)
   // along K (edge-fast layout); the faster-running index follows the operand's memory
   // layout (coalesced loads).  Offsets are 32-bit (a cluster matrix has far fewer than 2^31
   // elements).
   constexpr bool B_KFAST = !((TRANS_B && !B_RM) || (!TRANS_B && B_RM));
-  const int ef = tid % GT, kf = tid / GT;   // edge-fast position
-  const int ek = tid / GK, kk0 = tid % GK;  // K-fast position
-  constexpr int STEP_E = 256 / GT, STEP_K = 256 / GK;
-  const int b_e = B_KFAST ? ek : ef, b_k = B_KFAST ? kk0 : kf;
-  constexpr int B_STEP = B_KFAST ? STEP_K : STEP_E;
+  const int ef = tid % TM, kf = tid / TM;      // edge-fast position (A)
+  const int efb = tid % TN, kfb = tid / TN;    // edge-fast position (B)
+  const int ek = tid / GK, kk0 = tid % GK;     // K-fast position
+  constexpr int STEP_E = 256 / TM, STEP_EB = 256 / TN, STEP_K = 256 / GK;
+  const int b_e = B_KFAST ? ek : efb, b_k = B_KFAST ? kk0 : kfb;
+  constexpr int B_STEP = B_KFAST ? STEP_K : STEP_EB;
   const int a_rs = A_RM ? lda : 1, a_ks = A_RM ? 1 : lda;
   const int b_cs = (TRANS_B != B_RM) ? 1 : ldb, b_ks = (TRANS_B != B_RM) ? ldb : 1;
   // layout of an A chunk: 1 = K-fast, 0 = edge-fast
   auto a_mode_of = [&](int r0, int k0) -> int {
-    if (A_SYM) return (k0 >= r0 + GT) ? 1 : 0;
+    if (A_SYM) return (k0 >= r0 + TM) ? 1 : 0;
     return A_RM ? 1 : 0;
   };
   auto fetchA = [&](int r0, int k0, int mode, double *ra) {
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
+    for (int q = 0; q < PERA; ++q) {
       int gr, gk;
       if (mode) {
         gr = r0 + ek + q * STEP_K;
@@ -103,7 +108,7 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
   };
   auto fetchB = [&](int c0, int k0, double *rb) {
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
+    for (int q = 0; q < PERB; ++q) {
       const int gc = c0 + b_e + (B_KFAST ? q * B_STEP : 0);
       int gk = k0 + b_k + (B_KFAST ? 0 : q * B_STEP);
       const bool in = gc < n && gk < k;
@@ -117,14 +122,14 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
   auto stage = [&](int mode, const double *ra, const double *rb) {
     if (mode) {
 #pragma unroll
-      for (int q = 0; q < PER; ++q) As[kk0 * LS + ek + q * STEP_K] = ra[q];
+      for (int q = 0; q < PERA; ++q) As[kk0 * LSA + ek + q * STEP_K] = ra[q];
     } else {
 #pragma unroll
-      for (int q = 0; q < PER; ++q) As[(kf + q * STEP_E) * LS + ef] = ra[q];
+      for (int q = 0; q < PERA; ++q) As[(kf + q * STEP_E) * LSA + ef] = ra[q];
     }
 #pragma unroll
-    for (int q = 0; q < PER; ++q)
-      Bs[(b_k + (B_KFAST ? 0 : q * B_STEP)) * LS + b_e + (B_KFAST ? q * B_STEP : 0)] = rb[q];
+    for (int q = 0; q < PERB; ++q)
+      Bs[(b_k + (B_KFAST ? 0 : q * B_STEP)) * LSB + b_e + (B_KFAST ? q * B_STEP : 0)] = rb[q];
   };
   auto cidx = [&](int gr, int gc) { return C_RM ? gr * ldc + gc : gc * ldc + gr; };
   // tiles in row-major order (G_LOWER: only tile row >= tile column)
@@ -133,15 +138,15 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
       if (!LOWER || t % nt <= t / nt) return t;
     return -1;
   };
-  auto k_end = [&](int r0) { return (a_diag >= 0) ? min(k, r0 + GT + a_diag) : k; };
+  auto k_end = [&](int r0) { return (a_diag >= 0) ? min(k, r0 + TM + a_diag) : k; };
 
   // Software pipeline over (tile, K chunk): the chunk after the one being multiplied is always
   // in flight, including the first chunk of the next tile while the last chunk of this one runs.
-  double ra[PER], rb[PER];
+  double ra[PERA], rb[PERB];
   int tile = next_tile(0);
   int amode = 0;
   if (tile >= 0) {
-    const int r0 = (tile / nt) * GT, c0 = (tile % nt) * GT;
+    const int r0 = (tile / nt) * TM, c0 = (tile % nt) * TN;
     amode = a_mode_of(r0, 0);
     if (k_end(r0) > 0) {
       fetchA(r0, 0, amode, ra);
@@ -150,10 +155,10 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
   }
   while (tile >= 0) {
     const int ti = tile / nt, tj = tile % nt;
-    const int r0 = ti * GT, c0 = tj * GT;
+    const int r0 = ti * TM, c0 = tj * TN;
     const int kend = k_end(r0);
     const int nxt = next_tile(tile + 1);
-    const int r0n = (nxt >= 0) ? (nxt / nt) * GT : 0, c0n = (nxt >= 0) ? (nxt % nt) * GT : 0;
+    const int r0n = (nxt >= 0) ? (nxt / nt) * TM : 0, c0n = (nxt >= 0) ? (nxt % nt) * TN : 0;
     const bool fetch_next = nxt >= 0 && k_end(r0n) > 0;
     ldc_double4 acc[2][2];
 #pragma unroll
@@ -189,12 +194,12 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
       }
 #pragma unroll
       for (int s4 = 0; s4 < GK / 4; ++s4) {
-        const int kr = (4 * s4 + lk) * LS;
+        const int kra = (4 * s4 + lk) * LSA, krb = (4 * s4 + lk) * LSB;
         double af[2], bf[2];
 #pragma unroll
-        for (int a = 0; a < 2; ++a) af[a] = As[kr + wr * 32 + a * 16 + li];
+        for (int a = 0; a < 2; ++a) af[a] = As[kra + wr * 32 + a * 16 + li];
 #pragma unroll
-        for (int b = 0; b < 2; ++b) bf[b] = Bs[kr + wc * 32 + b * 16 + li];
+        for (int b = 0; b < 2; ++b) bf[b] = Bs[krb + wc * 32 + b * 16 + li];
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll

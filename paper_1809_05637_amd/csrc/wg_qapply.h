@@ -31,6 +31,8 @@ __device__ void wg_apply_q(const double *__restrict__ A, int ld, int n, const do
   double *Y = T + QP * QS;       // [QP][QS]  V^T X, then T' V^T X
   double *Xc = Y + QP * QS;      // [QCH][QXC+1] rows of X
   constexpr int NACC = (QP * QP + QP * QXC) / 256;  // entries per thread (8)
+  constexpr int NST = QCH * QP / 256;               // staged V (and X) entries per thread (4)
+  static_assert(QCH * QXC <= NST * 256, "X staging");
   const int nref = n - sh;                          // reflectors 0..n-1-sh
   const int npan = nref > 0 ? (nref + QP - 1) / QP : 0;
   for (int pi = 0; pi < npan; ++pi) {
@@ -38,27 +40,43 @@ __device__ void wg_apply_q(const double *__restrict__ A, int ld, int n, const do
     const int p0 = p * QP, nbp = min(QP, nref - p0);
     const int nG = make_T ? QP * QP : 0;
     const int nE = nG + QP * ncol;
+    // Staging of QCH rows from r0: V entry e = tid + 256 u at (row e % QCH, reflector e / QCH),
+    // X entry e at (row e / ncol, column e % ncol).  Loads are clamped into range and
+    // unconditional (the next chunk is fetched while the current one is used); values outside
+    // the reflectors or past row n are masked.
+    auto fetch = [&](int r0, double *rv, double *rx) {
+#pragma unroll
+      for (int u = 0; u < NST; ++u) {
+        const int e = tid + u * nthr, rr = e % QCH, t = e / QCH;
+        const int r = r0 + rr, k = p0 + t;
+        const double a = A[(long long)min(k, p0 + nbp - 1) * ld + min(r, n - 1)];
+        const bool in = t < nbp && r < n;
+        rv[u] = (in && r > k + sh) ? a : ((in && r == k + sh) ? 1.0 : 0.0);
+        const int xr = r0 + e / ncol, xq = e % ncol;
+        const double x = X[(long long)min(xr, n - 1) * ldx + xq];
+        rx[u] = (e < QCH * ncol && xr < n) ? x : 0.0;
+      }
+    };
+    auto stage = [&](const double *rv, const double *rx) {
+#pragma unroll
+      for (int u = 0; u < NST; ++u) {
+        const int e = tid + u * nthr;
+        Vc[(e % QCH) * QS + e / QCH] = rv[u];
+        if (e < QCH * ncol) Xc[(e / ncol) * (QXC + 1) + e % ncol] = rx[u];
+      }
+    };
+    double rv[NST], rx[NST];
     double acc[NACC];
 #pragma unroll
     for (int q = 0; q < NACC; ++q) acc[q] = 0.0;
+    fetch(p0 + sh, rv, rx);
     for (int r0 = p0 + sh; r0 < n; r0 += QCH) {
       __syncthreads();
-      for (int e = tid; e < QCH * QP; e += nthr) {
-        const int rr = e % QCH, t = e / QCH;
-        const int r = r0 + rr, k = p0 + t;
-        double val = 0.0;
-        if (t < nbp && r < n) {
-          if (r == k + sh) val = 1.0;
-          else if (r > k + sh) val = A[(long long)k * ld + r];
-        }
-        Vc[rr * QS + t] = val;
-      }
-      for (int e = tid; e < QCH * ncol; e += nthr) {
-        const int rr = e / ncol, qq = e % ncol;
-        Xc[rr * (QXC + 1) + qq] = (r0 + rr < n) ? X[(long long)(r0 + rr) * ldx + qq] : 0.0;
-      }
+      stage(rv, rx);
       __syncthreads();
-      const int rmax = min(QCH, n - r0);
+      if (r0 + QCH < n) fetch(r0 + QCH, rv, rx);
+      // whole chunks (rows past n are staged as zeros): fixed trip counts keep the LDS reads
+      // in flight together
 #pragma unroll
       for (int q = 0; q < NACC; ++q) {
         const int e = tid + q * 256;
@@ -66,11 +84,14 @@ __device__ void wg_apply_q(const double *__restrict__ A, int ld, int n, const do
           double s = 0.0;
           if (e < nG) {
             const int a = e / QP, b = e % QP;
-            if (a < b)
-              for (int rr = 0; rr < rmax; ++rr) s += Vc[rr * QS + a] * Vc[rr * QS + b];
+            if (a < b) {
+#pragma unroll 8
+              for (int rr = 0; rr < QCH; ++rr) s += Vc[rr * QS + a] * Vc[rr * QS + b];
+            }
           } else {
             const int a = (e - nG) / ncol, qq = (e - nG) % ncol;
-            for (int rr = 0; rr < rmax; ++rr) s += Vc[rr * QS + a] * Xc[rr * (QXC + 1) + qq];
+#pragma unroll 8
+            for (int rr = 0; rr < QCH; ++rr) s += Vc[rr * QS + a] * Xc[rr * (QXC + 1) + qq];
           }
           acc[q] += s;
         }
@@ -84,6 +105,8 @@ __device__ void wg_apply_q(const double *__restrict__ A, int ld, int n, const do
         else Y[((e - nG) / ncol) * QS + (e - nG) % ncol] = acc[q];
       }
     }
+    // the first chunk of the second pass is fetched while T and T'Y are formed
+    fetch(p0 + sh, rv, rx);
     __syncthreads();
     double *Tp = Tq + (long long)p * QP * QP;
     if (make_T) {
@@ -129,28 +152,19 @@ __device__ void wg_apply_q(const double *__restrict__ A, int ld, int n, const do
       const int e = tid + q * 256;
       if (e < QP * ncol) Y[(e / ncol) * QS + e % ncol] = z[q];
     }
-    __syncthreads();
-    // X(r, :) -= V(r, :) Y, with V staged in LDS by chunks of QCH rows
+    // X(r, :) <- X(r, :) - V(r, :) Y, V and X staged in LDS by chunks of QCH rows
     for (int r0 = p0 + sh; r0 < n; r0 += QCH) {
       __syncthreads();
-      for (int e = tid; e < QCH * QP; e += nthr) {
-        const int rr = e % QCH, t = e / QCH;
-        const int r = r0 + rr, k = p0 + t;
-        double val = 0.0;
-        if (t < nbp && r < n) {
-          if (r == k + sh) val = 1.0;
-          else if (r > k + sh) val = A[(long long)k * ld + r];
-        }
-        Vc[rr * QS + t] = val;
-      }
+      stage(rv, rx);
       __syncthreads();
+      if (r0 + QCH < n) fetch(r0 + QCH, rv, rx);
       const int rmax = min(QCH, n - r0);
       for (int e = tid; e < rmax * ncol; e += nthr) {
         const int rr = e / ncol, q = e % ncol;
         double s = 0.0;
 #pragma unroll 8
         for (int t = 0; t < QP; ++t) s += Vc[rr * QS + t] * Y[t * QS + q];
-        X[(long long)(r0 + rr) * ldx + q] -= s;
+        X[(long long)(r0 + rr) * ldx + q] = Xc[rr * (QXC + 1) + q] - s;
       }
     }
     __syncthreads();
