@@ -211,9 +211,12 @@ __device__ inline void lds_tri_inverse(double (*L11)[NB + 1], double (*Li)[NB + 
 }
 
 // ---------------------------------------------------------------------------------------
-// Blocked right-looking Cholesky S^(i) = L L^T (lower; the strictly-upper part is left as
-// it was).  Per panel: unblocked factor of the diagonal block in LDS, its inverse, the
-// panel below as L21 = A21 L11^{-T}, and the trailing update A22 -= L21 L21^T (MFMA GEMM).
+// Blocked right-looking Cholesky S^(i) = L L^T (lower; parts of the strictly-upper triangle
+// of the diagonal blocks are overwritten -- the standard-form step clears it).  Per panel:
+// unblocked factor of the diagonal block, its inverse, the panel below as
+// L21 = A21 L11^{-T}; panels go in pairs: the first updates only the second's columns, the
+// second updates the rest of the trailing matrix with both (A22 -= L21 L21^T with K = 2 NB on
+// MFMA), so the trailing matrix is streamed once per pair.
 // A non-positive pivot reports LDC_ERR_NOT_SPD for the cluster.
 __global__ void __launch_bounds__(256, 2) potrf_kernel(int n_clusters, const int *__restrict__ order,
                                                        double *__restrict__ mat, const long long *__restrict__ mat_off,
@@ -283,7 +286,17 @@ __global__ void __launch_bounds__(256, 2) potrf_kernel(int n_clusters, const int
         lds_tri_inverse(L11, Li, jb);
         double *P = S + (long long)j0 * ld + j0 + jb;
         wg_rows_times_small<true>(P, ld, P, ld, m, jb, Li, gl);
-        wg_gemm<G_TRANS_B | G_LOWER>(S + (long long)(j0 + jb) * ld + j0 + jb, ld, P, ld, P, ld, m, m, jb, gl);
+        double *C = S + (long long)(j0 + jb) * ld + j0 + jb;
+        if (((j0 / NB) & 1) == 0) {
+          // first panel of a pair: update only the next panel's columns now; the rest of the
+          // trailing matrix takes both panels at once (K = 2 NB) after the next panel
+          wg_gemm<G_TRANS_B>(C, ld, P, ld, P, ld, m, min(NB, m), jb, gl);
+        } else {
+          // second panel: A22 -= [L21 of both panels] [L21 of both panels]^T (the first
+          // panel's L21 rows below this panel sit in the NB columns to the left)
+          const double *P2 = S + (long long)(j0 - NB) * ld + j0 + jb;
+          wg_gemm<G_TRANS_B | G_LOWER>(C, ld, P2, ld, P2, ld, m, m, NB + jb, gl);
+        }
       }
     }
     __syncthreads();
