@@ -309,7 +309,7 @@ __global__ void __launch_bounds__(256, 2) potrf_kernel(int n_clusters, const int
 // 1. L^{-1} in place of L (block columns from the last: B21 <- -L22^{-1} L21 L11^{-1},
 //    L11 <- L11^{-1}); the strictly-upper part of the S slot is cleared first.
 // 2. W = L^{-1} H in place of H, block rows from the last (each block row only needs rows
-//    of H above it, which are still intact).
+//    of H above it and its own, which are still intact), each tile written in place.
 // 3. A = L^{-1} W^T (lower part) in place of W, block rows from the last.
 // All products are MFMA GEMMs that skip the structurally zero part of L^{-1}.  The tracked
 // columns of the tridiagonal solver are set up here: X_u = L^{-1} E_i (the last M columns of
@@ -332,7 +332,7 @@ __global__ void __launch_bounds__(256, 2) sygst_kernel(int n_clusters, const int
     const VecLayout vl = VecLayout::make(dmax[c]);
     double *cv = vec + vec_off[c];
     double *X = cv + vl.G0;
-    double *tmp = cv + vl.G1;  // n x GT scratch (spans the tracked-column partner and the T-factor area)
+    double *tmp = cv + vl.G1;  // n x NB scratch of the inversion
     const int b0 = n - M;
     __syncthreads();
     // tracked columns: X_v = L^T E_i (rows of L of the centre atom); X_u filled below
@@ -377,27 +377,20 @@ __global__ void __launch_bounds__(256, 2) sygst_kernel(int n_clusters, const int
       const int r = e % M, al = e / M;
       X[(long long)(b0 + r) * kTrack + al] = (r >= al) ? L[(long long)(b0 + al) * ld + b0 + r] : 0.0;
     }
-    // 2. W = L^{-1} H, block rows of GT from the last (tmp holds -W_b, GT x n, ld GT); full
-    //    MFMA tiles, K limited to the nonzero part of the block row of L^{-1}
+    // 2. W = L^{-1} H in place, block rows of GT from the last; full MFMA tiles, K limited to
+    //    the nonzero part of the block row of L^{-1}.  A tile of block row b reads only its own
+    //    columns of H (rows 0..r1, its own rows included) and is written after its last read.
     const int nblk2 = (n + GT - 1) / GT;
     for (int bj = nblk2 - 1; bj >= 0; --bj) {
       const int r0 = bj * GT, jb = min(GT, n - r0), r1 = r0 + jb;
-      wg_gemm<G_OVERWRITE>(tmp, GT, L + r0, ld, H, ld, jb, n, r1, gl, r0);
-      for (long long e = tid; e < (long long)jb * n; e += nthr) {
-        const int rr = (int)(e % jb), q = (int)(e / jb);
-        H[(long long)q * ld + r0 + rr] = -tmp[(long long)q * GT + rr];
-      }
-      __syncthreads();
+      wg_gemm<G_OVERWRITE | G_PLUS>(H + r0, ld, L + r0, ld, H, ld, jb, n, r1, gl, r0);
     }
-    // 3. A = L^{-1} W^T, lower part: block row b of A = L^{-1}(rows b, cols 0:r1) W(0:r1, 0:r1)^T
+    // 3. A = L^{-1} W^T in place, lower part: block row b of A = L^{-1}(rows b, cols 0:r1)
+    //    W(0:r1, 0:r1)^T.  Only the diagonal tile reads W's rows b, so the tiles run from the
+    //    last (diagonal) one.
     for (int bj = nblk2 - 1; bj >= 0; --bj) {
       const int r0 = bj * GT, jb = min(GT, n - r0), r1 = r0 + jb;
-      wg_gemm<G_TRANS_B | G_OVERWRITE>(tmp, GT, L + r0, ld, H, ld, jb, r1, r1, gl, r0);
-      for (long long e = tid; e < (long long)jb * r1; e += nthr) {
-        const int rr = (int)(e % jb), q = (int)(e / jb);
-        H[(long long)q * ld + r0 + rr] = -tmp[(long long)q * GT + rr];
-      }
-      __syncthreads();
+      wg_gemm<G_TRANS_B | G_OVERWRITE | G_PLUS | G_REV>(H + r0, ld, L + r0, ld, H, ld, jb, r1, r1, gl, r0);
     }
   }
 }

@@ -27,9 +27,11 @@ enum : unsigned {
   G_LATE_C = 32u,     // read C at the store instead of prefetching it (fewer registers)
   G_C_RM = 64u,       // C row-major (row stride ldc)
   G_A_SYM = 128u,     // A is symmetric, held in the lower triangle of a column-major array
+  G_PLUS = 256u,      // add instead of subtract: C += A op(B) (G_OVERWRITE: C = A op(B))
+  G_REV = 512u,       // tiles from the last to the first
 };
 
-// C[m x n] -= A[m x k] * op(B)   (G_OVERWRITE: C = -A op(B)).
+// C[m x n] -= A[m x k] * op(B)   (G_OVERWRITE: C = -A op(B); G_PLUS: + instead of -).
 // G_LOWER: the strictly-upper part of diagonal tiles is computed too and must be unused.
 // a_diag >= 0: A is zero above its a_diag-th superdiagonal (A[r][kk] = 0 for kk > r + a_diag),
 // so each tile row only runs over the K range that can be nonzero.
@@ -52,7 +54,7 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
                         double *lds, int a_diag = -1, int b_rot = 0) {
   constexpr bool TRANS_B = F & G_TRANS_B, LOWER = F & G_LOWER, A_RM = F & G_A_RM, B_RM = F & G_B_RM;
   constexpr bool OVERWRITE = F & G_OVERWRITE, PREFETCH_C = !(F & G_LATE_C), C_RM = F & G_C_RM;
-  constexpr bool A_SYM = F & G_A_SYM;
+  constexpr bool A_SYM = F & G_A_SYM, PLUS = F & G_PLUS, REV = F & G_REV;
   static_assert(!(A_SYM && A_RM), "a symmetric A is stored column-major");
   static_assert(TM * TN == 4 * 32 * 32 && TM % 32 == 0 && TN % 32 == 0, "four 32 x 32 wave parts");
   static_assert(!LOWER || TM == TN, "lower-triangle tiling needs square tiles");
@@ -132,10 +134,14 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
       Bs[(b_k + (B_KFAST ? 0 : q * B_STEP)) * LSB + b_e + (B_KFAST ? q * B_STEP : 0)] = rb[q];
   };
   auto cidx = [&](int gr, int gc) { return C_RM ? gr * ldc + gc : gc * ldc + gr; };
-  // tiles in row-major order (G_LOWER: only tile row >= tile column)
-  auto next_tile = [&](int t) -> int {
-    for (; t < mt * nt; ++t)
-      if (!LOWER || t % nt <= t / nt) return t;
+  // tiles in row-major order (G_REV: reversed; G_LOWER: only tile row >= tile column); a
+  // tile sequence index i maps to the tile index tile_of(i)
+  auto tile_of = [&](int i) { return REV ? mt * nt - 1 - i : i; };
+  auto next_tile = [&](int i) -> int {
+    for (; i < mt * nt; ++i) {
+      const int t = tile_of(i);
+      if (!LOWER || t % nt <= t / nt) return i;
+    }
     return -1;
   };
   auto k_end = [&](int r0) { return (a_diag >= 0) ? min(k, r0 + TM + a_diag) : k; };
@@ -146,7 +152,7 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
   int tile = next_tile(0);
   int amode = 0;
   if (tile >= 0) {
-    const int r0 = (tile / nt) * TM, c0 = (tile % nt) * TN;
+    const int r0 = (tile_of(tile) / nt) * TM, c0 = (tile_of(tile) % nt) * TN;
     amode = a_mode_of(r0, 0);
     if (k_end(r0) > 0) {
       fetchA(r0, 0, amode, ra);
@@ -154,11 +160,11 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
     }
   }
   while (tile >= 0) {
-    const int ti = tile / nt, tj = tile % nt;
+    const int ti = tile_of(tile) / nt, tj = tile_of(tile) % nt;
     const int r0 = ti * TM, c0 = tj * TN;
     const int kend = k_end(r0);
     const int nxt = next_tile(tile + 1);
-    const int r0n = (nxt >= 0) ? (nxt / nt) * TM : 0, c0n = (nxt >= 0) ? (nxt % nt) * TN : 0;
+    const int r0n = (nxt >= 0) ? (tile_of(nxt) / nt) * TM : 0, c0n = (nxt >= 0) ? (tile_of(nxt) % nt) * TN : 0;
     const bool fetch_next = nxt >= 0 && k_end(r0n) > 0;
     ldc_double4 acc[2][2];
 #pragma unroll
@@ -222,9 +228,10 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
         for (int r = 0; r < 4; ++r) {
           const int gc = c0 + wc * 32 + b * 16 + 4 * r + lk;
           if (gr < m && gc < n) {
-            if (OVERWRITE) C[cidx(gr, gc)] = -acc[a][b][r];
-            else if (PREFETCH_C) C[cidx(gr, gc)] = cold[a][b][r] - acc[a][b][r];
-            else C[cidx(gr, gc)] -= acc[a][b][r];
+            const double v = PLUS ? acc[a][b][r] : -acc[a][b][r];
+            if (OVERWRITE) C[cidx(gr, gc)] = v;
+            else if (PREFETCH_C) C[cidx(gr, gc)] = cold[a][b][r] + v;
+            else C[cidx(gr, gc)] += v;
           }
         }
       }
