@@ -306,7 +306,7 @@ __global__ void __launch_bounds__(256, 2) potrf_kernel(int n_clusters, const int
 
 // Standard form (Sec. II.C (iii) via Cholesky): with S = L L^T,
 //   A = L^{-1} H L^{-T}.
-// 1. L^{-1} in place of L (block columns from the last: B21 <- -L22^{-1} L21 L11^{-1},
+// 1. L^{-1} in place of L (block columns of 2 NB from the last: B21 <- -L22^{-1} L21 L11^{-1},
 //    L11 <- L11^{-1}); the strictly-upper part of the S slot is cleared first.
 // 2. W = L^{-1} H in place of H, block rows from the last (each block row only needs rows
 //    of H above it and its own, which are still intact), each tile written in place.
@@ -321,6 +321,8 @@ __global__ void __launch_bounds__(256, 2) sygst_kernel(int n_clusters, const int
                                                     const int *__restrict__ n_orb) {
   __shared__ double L11[NB][NB + 1];
   __shared__ double Li[NB][NB + 1];
+  __shared__ double Pi[NB][NB + 1];
+  __shared__ double Bq[NB][NB + 1];
   __shared__ double gl[kGemmLds];
   const int tid = threadIdx.x, nthr = blockDim.x;
   for (int s = blockIdx.x; s < n_clusters; s += gridDim.x) {
@@ -332,7 +334,7 @@ __global__ void __launch_bounds__(256, 2) sygst_kernel(int n_clusters, const int
     const VecLayout vl = VecLayout::make(dmax[c]);
     double *cv = vec + vec_off[c];
     double *X = cv + vl.G0;
-    double *tmp = cv + vl.G1;  // n x NB scratch of the inversion
+    double *tmp = cv + vl.G1;  // n x 2 NB scratch of the inversion (the tracked-column partner and the T-factor area)
     const int b0 = n - M;
     __syncthreads();
     // tracked columns: X_v = L^T E_i (rows of L of the centre atom); X_u filled below
@@ -348,29 +350,63 @@ __global__ void __launch_bounds__(256, 2) sygst_kernel(int n_clusters, const int
       if (r < q) L[e] = 0.0;
     }
     __syncthreads();
-    // 1. L <- L^{-1}
-    const int nblk = (n + NB - 1) / NB;
+    // 1. L <- L^{-1}, block columns of 2 NB from the last.  The inverse of a diagonal block
+    //    [P 0; B Q] (P, Q of NB) is [P^{-1} 0; -Q^{-1} B P^{-1} Q^{-1}], from the two NB x NB
+    //    inverses; then L21 <- -L22^{-1} L21 L11^{-1} with two MFMA products of full 64-wide tiles.
+    constexpr int BW = 2 * NB;
+    const int nblk = (n + BW - 1) / BW;
     for (int bj = nblk - 1; bj >= 0; --bj) {
-      const int j = bj * NB, jb = min(NB, n - j);
+      const int j = bj * BW, jbt = min(BW, n - j);
+      const int ja = min(NB, jbt), jc = jbt - ja;
+      __syncthreads();
       for (int e = tid; e < NB * NB; e += nthr) {
         const int r = e % NB, q = e / NB;
-        L11[r][q] = (r < jb && q < jb && r >= q) ? L[(long long)(j + q) * ld + j + r] : 0.0;
+        L11[r][q] = (r < ja && q < ja && r >= q) ? L[(long long)(j + q) * ld + j + r] : 0.0;
       }
       __syncthreads();
-      lds_tri_inverse(L11, Li, jb);
-      const int m = n - j - jb;
+      lds_tri_inverse(L11, Li, ja);
+      for (int e = tid; e < NB * NB; e += nthr) Pi[e % NB][e / NB] = Li[e % NB][e / NB];
+      __syncthreads();
+      if (jc > 0) {
+        for (int e = tid; e < NB * NB; e += nthr) {
+          const int r = e % NB, q = e / NB;
+          L11[r][q] = (r < jc && q < jc && r >= q) ? L[(long long)(j + NB + q) * ld + j + NB + r] : 0.0;
+          Bq[r][q] = (r < jc && q < ja) ? L[(long long)(j + q) * ld + j + NB + r] : 0.0;
+        }
+        __syncthreads();
+        lds_tri_inverse(L11, Li, jc);  // Li = Q^{-1}
+        // L11 <- B P^{-1}, then Bq <- -Q^{-1} (B P^{-1})
+        for (int e = tid; e < NB * NB; e += nthr) {
+          const int r = e % NB, q = e / NB;
+          double acc = 0.0;
+          for (int t = q; t < NB; ++t) acc += Bq[r][t] * Pi[t][q];
+          L11[r][q] = acc;
+        }
+        __syncthreads();
+        for (int e = tid; e < NB * NB; e += nthr) {
+          const int r = e % NB, q = e / NB;
+          double acc = 0.0;
+          for (int t = 0; t <= r; ++t) acc += Li[r][t] * L11[t][q];
+          Bq[r][q] = -acc;
+        }
+        __syncthreads();
+      }
+      // the inverse of the diagonal block into place (lower part)
+      for (int e = tid; e < NB * NB; e += nthr) {
+        const int r = e % NB, q = e / NB;
+        if (r < ja && q < ja && r >= q) L[(long long)(j + q) * ld + j + r] = Pi[r][q];
+        if (r < jc && q < jc && r >= q) L[(long long)(j + NB + q) * ld + j + NB + r] = Li[r][q];
+        if (r < jc && q < ja) L[(long long)(j + q) * ld + j + NB + r] = Bq[r][q];
+      }
+      __syncthreads();
+      const int m = n - j - jbt;
       if (m > 0) {
-        // tmp = -L22^{-1} L21
-        wg_gemm<G_OVERWRITE>(tmp, n, L + (long long)(j + jb) * ld + j + jb, ld,
-                                                       L + (long long)j * ld + j + jb, ld, m, jb, m, gl, 0);
+        double *L21 = L + (long long)j * ld + j + jbt;
+        // tmp = -L22^{-1} L21 (L22^{-1} lower triangular: K limited per tile row)
+        wg_gemm<G_OVERWRITE>(tmp, n, L + (long long)(j + jbt) * ld + j + jbt, ld, L21, ld, m, jbt, m, gl, 0);
         // L21 <- tmp L11^{-1}
-        wg_rows_times_small<false>(tmp, n, L + (long long)j * ld + j + jb, ld, m, jb, Li, gl);
+        wg_gemm<G_OVERWRITE | G_PLUS>(L21, ld, tmp, n, L + (long long)j * ld + j, ld, m, jbt, jbt, gl);
       }
-      for (int e = tid; e < NB * NB; e += nthr) {
-        const int r = e % NB, q = e / NB;
-        if (r < jb && q < jb && r >= q) L[(long long)(j + q) * ld + j + r] = Li[r][q];
-      }
-      __syncthreads();
     }
     // X_u = L^{-1} E_i: rows b0.. of the last M columns of L^{-1}
     for (int e = tid; e < M * M; e += nthr) {
