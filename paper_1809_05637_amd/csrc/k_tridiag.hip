@@ -9,8 +9,8 @@
 // All four products run on the FP64 matrix cores; only the QR of the tall-skinny panel is
 // vector code (leaves of 8 columns factored in LDS).  The reflectors stay below the band
 // (reflector k: unit at row k + b, the rest in A(k+b+1:, k)), tau in the tau vector and the
-// T factors in the compact-WY area, one b x b block per panel.  The tracked columns get
-// X <- Q1^T X at the end.
+// T factors in the compact-WY area, one b x b block per panel.  Each panel also applies its
+// block reflector to the tracked columns (X <- Q1^T X panel by panel).
 //
 // Stage 2 (sb2st_kernel), band to tridiagonal by bulge chasing on a band array holding the
 // lower band and the bulge (2b + 1 diagonals).  Sweep s removes column s below its
@@ -225,7 +225,7 @@ __device__ void panel_qr(double *__restrict__ A, int ld, int n, int j0, double *
 __device__ __noinline__ void band_panel(double *__restrict__ A, int ld, int n, int j0, double *__restrict__ tt,
                                         double *__restrict__ Tp, double *__restrict__ VW, double *__restrict__ VT,
                                         double *__restrict__ Kst, double *__restrict__ Gst, double *sh, double *sm,
-                                        double *red) {
+                                        double *red, double *__restrict__ X, int nx) {
   const int tid = threadIdx.x, nthr = blockDim.x;
   constexpr int b = kBand;
   const int r = j0 + b, m = n - r;
@@ -279,6 +279,10 @@ __device__ __noinline__ void band_panel(double *__restrict__ A, int ld, int n, i
   // A22 -= V W^T + W V^T (lower triangle)
   wg_gemm<G_TRANS_B | G_LOWER | G_A_RM | G_B_RM>(A22, ld, VW, 2 * b, VW, 2 * b, m, m, 2 * b, sh, -1,
                                                              b);
+  // tracked columns, rows r..: X <- (I - V T V^T)^T X = X - V (T^T V^T X), with
+  // T^T V^T X = -(VT)^T X from the stored -V T (K free now holds it)
+  wg_gemm<G_B_RM | G_OVERWRITE | G_C_RM>(Kst, b, VT, b, X + (long long)r * kTrack, kTrack, b, nx, m, sh);
+  wg_gemm<G_A_RM | G_B_RM | G_C_RM, 128, 32>(X + (long long)r * kTrack, kTrack, VW, 2 * b, Kst, b, m, nx, b, sh);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -314,11 +318,8 @@ __global__ void __launch_bounds__(256, 2) sy2sb_kernel(int n_clusters, const int
         if (tid == 0) tt[j0] = 0.0;
         continue;
       }
-      band_panel(A, ld, n, j0, tt, Tp, VW, VT, Kst, Gst, sh, sm, red);
+      band_panel(A, ld, n, j0, tt, Tp, VW, VT, Kst, Gst, sh, sm, red, X, 2 * M);
     }
-    // tracked columns: X <- Q1^T X
-    __syncthreads();
-    wg_apply_q(A, ld, n, tt, Tq, false, X, kTrack, 2 * M, true, sh, b);
   }
 }
 
