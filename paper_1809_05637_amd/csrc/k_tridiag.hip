@@ -30,12 +30,14 @@ namespace ldc {
 
 constexpr int LEAF = 8;                     // columns per LDS-resident leaf of the panel QR
 constexpr int kRowRegs = kMaxDimTri / 64;   // rows of a panel column held per lane
+constexpr int kLeafRows = (kMaxDimTri + kWG - 1) / kWG;  // leaf rows held per thread
 
 // ---------------------------------------------------------------------------------------
 // QR of the panel P = A(r:n, j0:j0+kBand) (column-major, ld), r = j0 + kBand, m = n - r.
 // On return P holds R on and above its diagonal and the Householder vectors below it (unit
 // diagonal implicit); tau_k goes to tt[j0 + k] (0 where the reflector has length <= 1).
 // lf: LEAF * m doubles of LDS; sm: 2 * LEAF * LEAF + 4 * LEAF doubles; red: 10 * LEAF.
+// Needs blockDim.x == kWG (four waves).
 __device__ void panel_qr(double *__restrict__ A, int ld, int n, int j0, double *__restrict__ tt, double *lf,
                          double *sm, double *red) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nthr = blockDim.x, nw = nthr >> 6;
@@ -50,59 +52,67 @@ __device__ void panel_qr(double *__restrict__ A, int ld, int n, int j0, double *
       if (tid < LEAF) tt[j0 + c0 + tid] = 0.0;
       continue;
     }
-    // leaf into LDS, column-major with stride mp
+    // leaf in registers: thread tid holds rows i = tid + kWG t (rows past mp read as zero;
+    // the loads are clamped so that they issue back to back).  The barrier orders these reads
+    // after the writes of the previous leaf or panel.
     __syncthreads();
-    for (int e = tid; e < LEAF * mp; e += nthr) {
-      const int k = e / mp, i = e % mp;
-      lf[e] = A[(long long)(j0 + c0 + k) * ld + R0 + i];
-    }
-    __syncthreads();
-    // Column k of the leaf: every thread owns rows i = tid + t nthr.  One pass over its rows
-    // applies reflector k - 1 and accumulates the sums for reflector k (|x(k+1:)|^2 and the dots
-    // of x(k+1:) with the later leaf columns); the owner of row k publishes that row, so a
-    // single barrier per column suffices (red and rk are double-buffered by k).
+    double x[LEAF][kLeafRows];
+#pragma unroll
+    for (int c = 0; c < LEAF; ++c)
+#pragma unroll
+      for (int t = 0; t < kLeafRows; ++t) {
+        const int i = tid + kWG * t;
+        const double v = A[(long long)(j0 + c0 + c) * ld + R0 + (i < mp ? i : mp - 1)];
+        x[c][t] = i < mp ? v : 0.0;
+      }
+    // Column k of the leaf: one pass over the thread's rows applies reflector k - 1 and
+    // accumulates the sums for reflector k (|x(k+1:)|^2 and the dots of x(k+1:) with the later
+    // leaf columns); thread k publishes row k, so a single barrier per column suffices (red and
+    // rk are double-buffered by k).  The loop is unrolled so that every column index is fixed.
     double tau_p = 0.0, beta_p = 0.0, sc_p = 0.0, wc_p[LEAF];
 #pragma unroll
     for (int c = 0; c < LEAF; ++c) wc_p[c] = 0.0;
+#pragma unroll
     for (int k = 0; k <= LEAF; ++k) {
       if (k >= 1) {
         const int kp = k - 1;
-        for (int i = tid; i < mp; i += nthr) {
-          if (i < kp) continue;
-          const double v = (i == kp) ? 1.0 : lf[kp * mp + i] * sc_p;
 #pragma unroll
-          for (int c = 1; c < LEAF; ++c)
-            if (kp + c < LEAF) lf[(kp + c) * mp + i] -= tau_p * v * wc_p[c];
-          lf[kp * mp + i] = (i == kp) ? beta_p : v;
+        for (int t = 0; t < kLeafRows; ++t) {
+          const int i = tid + kWG * t;
+          if (i >= kp) {  // rows above kp hold R
+            const double v = (i == kp) ? 1.0 : x[kp][t] * sc_p;
+#pragma unroll
+            for (int c = kp + 1; c < LEAF; ++c) x[c][t] -= tau_p * v * wc_p[c - kp];
+            x[kp][t] = (i == kp) ? beta_p : v;
+          }
         }
       }
       if (k == LEAF) break;
       double *rkk = rk + (k & 1) * LEAF, *redk = red + (k & 1) * 4 * LEAF;
-      if (k < mp && k % nthr == tid) {
+      if (tid == k && k < mp) {
 #pragma unroll
-        for (int c = 0; c < LEAF; ++c)
-          if (k + c < LEAF) rkk[c] = lf[(k + c) * mp + k];
+        for (int c = 0; c < LEAF - k; ++c) rkk[c] = x[k + c][0];
       }
       double part[LEAF];
 #pragma unroll
       for (int q = 0; q < LEAF; ++q) part[q] = 0.0;
-      for (int i = tid; i < mp; i += nthr) {
-        if (i <= k) continue;
-        const double a = lf[k * mp + i];
+#pragma unroll
+      for (int t = 0; t < kLeafRows; ++t) {
+        const int i = tid + kWG * t;
+        const double a = i > k ? x[k][t] : 0.0;
         part[0] += a * a;
 #pragma unroll
-        for (int c = 1; c < LEAF; ++c)
-          if (k + c < LEAF) part[c] += a * lf[(k + c) * mp + i];
+        for (int c = 1; c < LEAF - k; ++c) part[c] += a * x[k + c][t];
       }
 #pragma unroll
-      for (int q = 0; q < LEAF; ++q) {
+      for (int q = 0; q < LEAF - k; ++q) {
         const double t = wave_sum(part[q]);
         if (lane == 0) redk[wave * LEAF + q] = t;
       }
       __syncthreads();
       double tot[LEAF];
 #pragma unroll
-      for (int q = 0; q < LEAF; ++q) {
+      for (int q = 0; q < LEAF - k; ++q) {
         double a = 0.0;
         for (int w = 0; w < nw; ++w) a += redk[w * LEAF + q];
         tot[q] = a;
@@ -119,18 +129,25 @@ __device__ void panel_qr(double *__restrict__ A, int ld, int n, int j0, double *
         sc_p = 1.0 / (alpha - beta_p);
       }
 #pragma unroll
-      for (int c = 1; c < LEAF; ++c) wc_p[c] = (k + c < LEAF && k < mp) ? rkk[c] + sc_p * tot[c] : 0.0;
+      for (int c = 1; c < LEAF; ++c) wc_p[c] = (c < LEAF - k && k < mp) ? rkk[c] + sc_p * tot[c] : 0.0;
       if (tid == 0) {
         tt[j0 + c0 + k] = tau_p;
         tl[k] = tau_p;
       }
     }
+    // leaf back to A, and into LDS (column-major, stride mp) for the Gram matrix and the
+    // later panel columns
+#pragma unroll
+    for (int c = 0; c < LEAF; ++c)
+#pragma unroll
+      for (int t = 0; t < kLeafRows; ++t) {
+        const int i = tid + kWG * t;
+        if (i < mp) {
+          A[(long long)(j0 + c0 + c) * ld + R0 + i] = x[c][t];
+          lf[c * mp + i] = x[c][t];
+        }
+      }
     __syncthreads();
-    // leaf back to A
-    for (int e = tid; e < LEAF * mp; e += nthr) {
-      const int k = e / mp, i = e % mp;
-      A[(long long)(j0 + c0 + k) * ld + R0 + i] = lf[e];
-    }
     if (c0 + LEAF >= kBand) break;  // no later panel columns
     // leaf Gram matrix G(a, b) = v_a . v_b (a < b): 8 lanes per pair, rows strided by 8
     {
