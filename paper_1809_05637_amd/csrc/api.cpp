@@ -50,7 +50,7 @@ void free_all(Plan &p) {
                   p.d_pair_ptr, p.d_pair_ab,  p.d_pair_blk, p.d_fna_ptr, p.d_fna_blk, p.d_p_rows,   p.d_dmax,
                   p.d_order,    p.d_mat_off,  p.d_vec_off,  p.d_ivec_off, p.d_mat,    p.d_vec,      p.d_ivec,
                   p.d_dim,      p.d_rank,     p.d_U,        p.d_lambda,  p.d_fixed,   p.d_mu,       p.d_partial,
-                  p.d_counter,  p.d_status};
+                  p.d_counter,  p.d_status,   p.d_lno_blk};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   for (int s = 0; s < LDC_NUM_STAGES; ++s) {
@@ -208,6 +208,7 @@ ldc_status ldc_plan_create(ldc_plan_t *out, int n_atoms, const double *pos, cons
       o += (long long)p.n_orb[i] * p.n_orb[p.col[b]];
     }
   }
+  p.blk_total = o;
   ldc_status s = ldc::build_regions(p, pos, cell, periodic);
   if (s != LDC_OK) {
     h->p.msg = p.msg;
@@ -378,6 +379,10 @@ ldc_status ldc_lno(ldc_plan_t plan, const double *d_S, const double *d_Dprev, co
     return LDC_OK;
   }
   if (!d_S || !rule) return LDC_ERR_ARG;
+  if (!p.d_lno_blk) {
+    ldc_status s = dev_alloc(p, &p.d_lno_blk, (size_t)(6 * p.blk_total));
+    if (s != LDC_OK) return s;
+  }
   std::vector<int> fixed(p.n_atoms, -1);
   if (rule->fixed_rank)
     for (int i = 0; i < p.n_atoms; ++i) fixed[i] = rule->fixed_rank[i];

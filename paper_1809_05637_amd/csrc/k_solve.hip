@@ -13,8 +13,77 @@ namespace ldc {
 constexpr int NB = 32;  // panel width of the blocked factorizations
 
 // ---------------------------------------------------------------------------------------
+// LNO blocks of Eq. 26 for every pattern block (i, j), formed once per call and shared by all
+// clusters in which i or j is a long member: out[(2 v + x) total + blk_off[b] + ...] holds,
+// row-major, v = 0: U_i^T X_ij (k_i x M_j), v = 1: X_ij U_j (M_i x k_j), v = 2: U_i^T X_ij U_j
+// (k_i x k_j), for x = 0: X = H, x = 1: X = S.  U_j is column-major M_j x k_j (ld M_j).
+// One workgroup per atom row i; each wave takes one block of the row at a time.
+__global__ void __launch_bounds__(256) lno_blocks_kernel(int n_atoms, const int *__restrict__ row_ptr,
+                                                         const int *__restrict__ col, const int *__restrict__ n_orb,
+                                                         const long long *__restrict__ blk_off,
+                                                         const int *__restrict__ rank, const double *__restrict__ U,
+                                                         const double *__restrict__ H, const double *__restrict__ S,
+                                                         double *__restrict__ out, long long total) {
+  constexpr int Q = kMaxOrb * kMaxOrb;
+  __shared__ double ui[Q];
+  __shared__ double uj[4][Q], xs[4][Q], xu[4][Q];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = blockIdx.x; i < n_atoms; i += gridDim.x) {
+    const int Mi = n_orb[i], ki = rank[i];
+    const int b0 = row_ptr[i], nb = row_ptr[i + 1] - b0;
+    __syncthreads();
+    for (int e = tid; e < Mi * ki; e += blockDim.x) ui[e] = U[(long long)i * Q + e];
+    // every wave runs the same number of rounds so that the barriers match
+    for (int t0 = 0; t0 < nb; t0 += 4) {
+      const int bl = t0 + wave;
+      const bool act = bl < nb;
+      const int b = b0 + (act ? bl : 0), j = col[b];
+      const int Mj = n_orb[j], kj = rank[j];
+      const long long bo = blk_off[b];
+      if (act)
+        for (int e = lane; e < Mj * kj; e += 64) uj[wave][e] = U[(long long)j * Q + e];
+      for (int x = 0; x < 2; ++x) {
+        const double *X = (x ? S : H) + bo;
+        __syncthreads();
+        if (act)
+          for (int e = lane; e < Mi * Mj; e += 64) xs[wave][e] = X[e];
+        __syncthreads();
+        if (act) {
+          double *o0 = out + (long long)x * total + bo;            // U_i^T X
+          double *o1 = out + (long long)(2 + x) * total + bo;      // X U_j
+          for (int e = lane; e < Mi * kj; e += 64) {
+            const int r = e / kj, q = e % kj;
+            double a = 0.0;
+            for (int be = 0; be < Mj; ++be) a += xs[wave][r * Mj + be] * uj[wave][be + q * Mj];
+            xu[wave][e] = a;
+            o1[e] = a;
+          }
+          for (int e = lane; e < ki * Mj; e += 64) {
+            const int r = e / Mj, q = e % Mj;
+            double a = 0.0;
+            for (int al = 0; al < Mi; ++al) a += ui[al + r * Mi] * xs[wave][al * Mj + q];
+            o0[e] = a;
+          }
+        }
+        __syncthreads();
+        if (act) {
+          double *o2 = out + (long long)(4 + x) * total + bo;      // U_i^T X U_j
+          for (int e = lane; e < ki * kj; e += 64) {
+            const int r = e / kj, q = e % kj;
+            double a = 0.0;
+            for (int al = 0; al < Mi; ++al) a += ui[al + r * Mi] * xu[wave][al * kj + q];
+            o2[e] = a;
+          }
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
 // (a)+(c) gather: dense column-major H^(i), S^(i) (leading dimension = cluster dimension).
-// Long members enter through their LNOs: blocks U_a^T X, X U_b or U_a^T X U_b.
+// Long members enter through their LNOs: the blocks U_a^T X, X U_b or U_a^T X U_b formed by
+// lno_blocks_kernel, so every pair is a plain copy of a da x db row-major block.
 __global__ void __launch_bounds__(256) gather_kernel(int n_clusters, const int *__restrict__ order,
                                                      const int *__restrict__ mem_ptr, const int *__restrict__ mem_atom,
                                                      const int *__restrict__ mem_long, const int *__restrict__ pair_ptr,
@@ -22,12 +91,12 @@ __global__ void __launch_bounds__(256) gather_kernel(int n_clusters, const int *
                                                      const int *__restrict__ n_orb, const long long *__restrict__ blk_off,
                                                      const double *__restrict__ H, const double *__restrict__ S,
                                                      int lno_mode, const int *__restrict__ rank,
-                                                     const double *__restrict__ U, double *__restrict__ mat,
+                                                     const double *__restrict__ lno_blk, long long total,
+                                                     double *__restrict__ mat,
                                                      const long long *__restrict__ mat_off, const int *__restrict__ dmax,
                                                      int *__restrict__ dim) {
   __shared__ int off[kMaxMembers + 1];
   __shared__ int dm[kMaxMembers];
-  __shared__ int matom[kMaxMembers];
   __shared__ int morb[kMaxMembers];  // M_j, negated for a long member (LNO contraction)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   for (int s = blockIdx.x; s < n_clusters; s += gridDim.x) {
@@ -39,7 +108,6 @@ __global__ void __launch_bounds__(256) gather_kernel(int n_clusters, const int *
       const int m = n_orb[atom];
       const bool lg = lno_mode && mem_long[mb + a];
       dm[a] = lg ? rank[atom] : m;
-      matom[a] = atom;
       morb[a] = lg ? -m : m;
     }
     __syncthreads();
@@ -75,67 +143,30 @@ __global__ void __launch_bounds__(256) gather_kernel(int n_clusters, const int *
                                          (unsigned)__shfl(bo_lo, src, 64));
         const int a = ab & 0xffff, b = ab >> 16;
         const int da = dm[a], db = dm[b];
-        const int ma_s = morb[a], mb_s = morb[b];
-        const bool la = ma_s < 0, lb = mb_s < 0;
-        const int ma = la ? -ma_s : ma_s, mbb = lb ? -mb_s : mb_s;
+        const bool la = morb[a] < 0, lb = morb[b] < 0;
         const int ne = (i + half < np) ? da * db : 0;
-        const double *hb = H + bo;
-        const double *sb = S + bo;
+        // source: the pattern block itself, or its LNO contraction (row stride db either way)
+        const int v = la ? (lb ? 2 : 0) : 1;
+        const double *hb = (la || lb) ? lno_blk + (long long)(2 * v) * total + bo : H + bo;
+        const double *sb = (la || lb) ? lno_blk + (long long)(2 * v + 1) * total + bo : S + bo;
         const long long ob = (long long)off[b] * n + off[a];
-        if (!la && !lb) {
-          // plain block copy: four elements per lane in flight (clamped loads, masked stores)
-          for (int e0 = hl; e0 < ne; e0 += 128) {
-            double hv[4], sv[4];
+        // four elements per lane in flight (clamped loads, masked stores)
+        for (int e0 = hl; e0 < ne; e0 += 128) {
+          double hv[4], sv[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              const int e = min(e0 + 32 * u, ne - 1), r = e % da, q = e / da;
-              hv[u] = hb[r * mbb + q];
-              sv[u] = sb[r * mbb + q];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              const int e = e0 + 32 * u;
-              if (e < ne) {
-                const long long o = ob + (long long)(e / da) * n + e % da;
-                Hc[o] = hv[u];
-                Sc[o] = sv[u];
-              }
-            }
+          for (int u = 0; u < 4; ++u) {
+            const int e = min(e0 + 32 * u, ne - 1), r = e % da, q = e / da;
+            hv[u] = hb[r * db + q];
+            sv[u] = sb[r * db + q];
           }
-        } else {
-          const double *Ua = U + (long long)matom[a] * kMaxOrb * kMaxOrb;
-          const double *Ub = U + (long long)matom[b] * kMaxOrb * kMaxOrb;
-          for (int e = hl; e < ne; e += 32) {
-            const int r = e % da, q = e / da;
-            double h = 0.0, sv = 0.0;
-            if (la && !lb) {
-              for (int al = 0; al < ma; ++al) {
-                const double u = Ua[al + r * ma];
-                h += u * hb[al * mbb + q];
-                sv += u * sb[al * mbb + q];
-              }
-            } else if (!la && lb) {
-              for (int be = 0; be < mbb; ++be) {
-                const double u = Ub[be + q * mbb];
-                h += hb[r * mbb + be] * u;
-                sv += sb[r * mbb + be] * u;
-              }
-            } else {
-              for (int al = 0; al < ma; ++al) {
-                double th = 0.0, ts = 0.0;
-                for (int be = 0; be < mbb; ++be) {
-                  const double u = Ub[be + q * mbb];
-                  th += hb[al * mbb + be] * u;
-                  ts += sb[al * mbb + be] * u;
-                }
-                const double u = Ua[al + r * ma];
-                h += u * th;
-                sv += u * ts;
-              }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int e = e0 + 32 * u;
+            if (e < ne) {
+              const long long o = ob + (long long)(e / da) * n + e % da;
+              Hc[o] = hv[u];
+              Sc[o] = sv[u];
             }
-            const long long o = ob + (long long)q * n + r;
-            Hc[o] = h;
-            Sc[o] = sv;
           }
         }
       }
@@ -433,9 +464,13 @@ __global__ void __launch_bounds__(256, 2) sygst_kernel(int n_clusters, const int
 
 // ---------------------------------------------------------------------------------------
 void launch_gather(Plan &p, const double *d_H, const double *d_S) {
+  if (p.lno_mode)
+    hipLaunchKernelGGL(lno_blocks_kernel, dim3(std::min(p.n_atoms, 8 * p.n_cu)), dim3(kWG), 0, p.stream, p.n_atoms,
+                       p.d_row_ptr, p.d_col, p.d_n_orb, p.d_blk_off, p.d_rank, p.d_U, d_H, d_S, p.d_lno_blk,
+                       p.blk_total);
   hipLaunchKernelGGL(gather_kernel, dim3(p.workgroups), dim3(kWG), 0, p.stream, p.n_atoms, p.d_order, p.d_mem_ptr,
                      p.d_mem_atom, p.d_mem_long, p.d_pair_ptr, p.d_pair_ab, p.d_pair_blk, p.d_n_orb, p.d_blk_off, d_H,
-                     d_S, p.lno_mode, p.d_rank, p.d_U, p.d_mat, p.d_mat_off, p.d_dmax, p.d_dim);
+                     d_S, p.lno_mode, p.d_rank, p.d_lno_blk, p.blk_total, p.d_mat, p.d_mat_off, p.d_dmax, p.d_dim);
 }
 
 void launch_potrf(Plan &p) {

@@ -44,6 +44,7 @@ struct Plan {
   // host copies of the geometry and pattern
   std::vector<int> n_orb, row_ptr, col;
   std::vector<long long> blk_off;
+  long long blk_total = 0;                       // elements of one block-sparse matrix
 
   // regions, in the library's member order: long, short \ F, F \ {i}, i
   std::vector<int> mem_ptr, mem_atom, mem_long;
@@ -76,6 +77,10 @@ struct Plan {
   double *d_U = nullptr;            // n_atoms x kMaxOrb^2, U_j column-major M_j x k_j
   double *d_lambda = nullptr;       // n_atoms x kMaxOrb^2 scratch (Lambda matrices)
   int *d_fixed = nullptr;           // n_atoms fixed ranks (-1: rule)
+  // LNO-contracted pattern blocks (Eq. 26), 6 x blk_total: for v = 0 (U_i^T X_ij),
+  // 1 (X_ij U_j), 2 (U_i^T X_ij U_j) and X = H, S, slot 2 v + (X == S); allocated by the
+  // first ldc_lno with a previous density, rebuilt by every ldc_solve in LNO mode
+  double *d_lno_blk = nullptr;
 
   // chemical potential state and reductions
   double *d_mu = nullptr;           // [lo, hi, mid, done, n_at_mid, bracket checks...]
