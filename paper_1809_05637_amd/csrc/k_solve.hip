@@ -81,9 +81,14 @@ __global__ void __launch_bounds__(256) lno_blocks_kernel(int n_atoms, const int 
 }
 
 // ---------------------------------------------------------------------------------------
-// (a)+(c) gather: dense column-major H^(i), S^(i) (leading dimension = cluster dimension).
-// Long members enter through their LNOs: the blocks U_a^T X, X U_b or U_a^T X U_b formed by
-// lno_blocks_kernel, so every pair is a plain copy of a da x db row-major block.
+// (a)+(c) gather: dense column-major H^(i), S^(i) (leading dimension = cluster dimension n),
+// written column block by column block, every element once (zeros included), each column in
+// full.  The (a, b) block of the cluster matrix is C_a X_ab C_b with C the LNO contraction of a
+// long member (identity otherwise); by the symmetry of H and S it is read as the transpose of
+// the row-b pattern block X_ba or its contraction from lno_blocks_kernel (U_b^T X_ba, X_ba U_a
+// or U_b^T X_ba U_a), whose rows have length d_a either way, so that a column of the cluster
+// matrix reads contiguous runs of each block row.
+// Dynamic LDS: n 16-bit member indices (row -> member).
 __global__ void __launch_bounds__(256) gather_kernel(int n_clusters, const int *__restrict__ order,
                                                      const int *__restrict__ mem_ptr, const int *__restrict__ mem_atom,
                                                      const int *__restrict__ mem_long, const int *__restrict__ pair_ptr,
@@ -95,20 +100,25 @@ __global__ void __launch_bounds__(256) gather_kernel(int n_clusters, const int *
                                                      double *__restrict__ mat,
                                                      const long long *__restrict__ mat_off, const int *__restrict__ dmax,
                                                      int *__restrict__ dim) {
+  extern __shared__ unsigned short rowmem[];
   __shared__ int off[kMaxMembers + 1];
   __shared__ int dm[kMaxMembers];
-  __shared__ int morb[kMaxMembers];  // M_j, negated for a long member (LNO contraction)
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  __shared__ unsigned char lng[kMaxMembers];
+  __shared__ int rs[kMaxMembers], re[kMaxMembers];  // pairs of member row a: [rs[a], re[a])
+  __shared__ long long pbo[kMaxMembers];            // block offset of (b, a) for the current b, or -1
+  const int tid = threadIdx.x;
   for (int s = blockIdx.x; s < n_clusters; s += gridDim.x) {
     const int c = order[s];
     const int mb = mem_ptr[c], nm = mem_ptr[c + 1] - mb;
+    const int p0 = pair_ptr[c], p1 = pair_ptr[c + 1];
     __syncthreads();
     for (int a = tid; a < nm; a += blockDim.x) {
       const int atom = mem_atom[mb + a];
-      const int m = n_orb[atom];
       const bool lg = lno_mode && mem_long[mb + a];
-      dm[a] = lg ? rank[atom] : m;
-      morb[a] = lg ? -m : m;
+      dm[a] = lg ? rank[atom] : n_orb[atom];
+      lng[a] = lg;
+      rs[a] = 0;
+      re[a] = 0;
     }
     __syncthreads();
     if (tid == 0) {
@@ -116,58 +126,50 @@ __global__ void __launch_bounds__(256) gather_kernel(int n_clusters, const int *
       for (int a = 0; a < nm; ++a) off[a + 1] = off[a] + dm[a];
       dim[c] = off[nm];
     }
-    __syncthreads();
-    const int n = off[nm];
-    double *Hc = mat + mat_off[c];
-    double *Sc = Hc + (long long)dmax[c] * dmax[c];
-    for (long long e = tid; e < (long long)n * n; e += blockDim.x) {
-      Hc[e] = 0.0;
-      Sc[e] = 0.0;
+    // the pairs are grouped by row member: mark where each group starts and ends
+    for (int q = p0 + tid; q < p1; q += blockDim.x) {
+      const int a = pair_ab[q] & 0xffff;
+      if (q == p0 || (pair_ab[q - 1] & 0xffff) != a) rs[a] = q;
+      if (q == p1 - 1 || (pair_ab[q + 1] & 0xffff) != a) re[a] = q + 1;
     }
     __syncthreads();
-    // Pairs in batches of 64 per wave: the lanes first load the batch's pair records and block
-    // offsets together, then each half-wave takes one pair at a time (records by shuffle), so
-    // a pair costs one round trip to its block instead of a chain of dependent loads.
-    const int p_end = pair_ptr[c + 1];
-    const int half = lane >> 5, hl = lane & 31;
-    for (int pb = pair_ptr[c] + wave * 64; pb < p_end; pb += nw * 64) {
-      const int pl = min(pb + lane, p_end - 1);
-      const int ab_l = pair_ab[pl];
-      const long long bo_l = blk_off[pair_blk[pl]];
-      const int bo_lo = (int)(unsigned long long)bo_l, bo_hi = (int)((unsigned long long)bo_l >> 32);
-      const int np = min(64, p_end - pb);
-      for (int i = 0; i < np; i += 2) {
-        const int src = min(i + half, np - 1);
-        const int ab = __shfl(ab_l, src, 64);
-        const long long bo = (long long)(((unsigned long long)(unsigned)__shfl(bo_hi, src, 64) << 32) |
-                                         (unsigned)__shfl(bo_lo, src, 64));
-        const int a = ab & 0xffff, b = ab >> 16;
-        const int da = dm[a], db = dm[b];
-        const bool la = morb[a] < 0, lb = morb[b] < 0;
-        const int ne = (i + half < np) ? da * db : 0;
-        // source: the pattern block itself, or its LNO contraction (row stride db either way)
-        const int v = la ? (lb ? 2 : 0) : 1;
-        const double *hb = (la || lb) ? lno_blk + (long long)(2 * v) * total + bo : H + bo;
-        const double *sb = (la || lb) ? lno_blk + (long long)(2 * v + 1) * total + bo : S + bo;
-        const long long ob = (long long)off[b] * n + off[a];
-        // four elements per lane in flight (clamped loads, masked stores)
-        for (int e0 = hl; e0 < ne; e0 += 128) {
+    const int n = off[nm];
+    for (int a = 0; a < nm; ++a)
+      for (int r = off[a] + tid; r < off[a + 1]; r += blockDim.x) rowmem[r] = (unsigned short)a;
+    double *Hc = mat + mat_off[c];
+    double *Sc = Hc + (long long)dmax[c] * dmax[c];
+    for (int b = 0; b < nm; ++b) {
+      __syncthreads();
+      for (int a = tid; a < nm; a += blockDim.x) pbo[a] = -1;
+      __syncthreads();
+      for (int q = rs[b] + tid; q < re[b]; q += blockDim.x) pbo[pair_ab[q] >> 16] = blk_off[pair_blk[q]];
+      __syncthreads();
+      const int db = dm[b], cb = off[b];
+      const bool lb = lng[b];
+      for (int r = tid; r < n; r += blockDim.x) {
+        const int a = rowmem[r], da = dm[a], rr = r - off[a];
+        const long long bo = pbo[a];
+        const bool la = lng[a];
+        // variant of the (b, a) block: rows contracted when b is long, columns when a is
+        const int v = lb ? (la ? 2 : 0) : 1;
+        const double *hb = (la || lb) ? lno_blk + (long long)(2 * v) * total : H;
+        const double *sb = (la || lb) ? lno_blk + (long long)(2 * v + 1) * total : S;
+        const long long src = bo + rr;
+        double *hc = Hc + (long long)cb * n + r, *sc = Sc + (long long)cb * n + r;
+        for (int q0 = 0; q0 < db; q0 += 4) {
           double hv[4], sv[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            const int e = min(e0 + 32 * u, ne - 1), r = e % da, q = e / da;
-            hv[u] = hb[r * db + q];
-            sv[u] = sb[r * db + q];
+            const int q = min(q0 + u, db - 1);
+            hv[u] = bo >= 0 ? hb[src + (long long)q * da] : 0.0;
+            sv[u] = bo >= 0 ? sb[src + (long long)q * da] : 0.0;
           }
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int e = e0 + 32 * u;
-            if (e < ne) {
-              const long long o = ob + (long long)(e / da) * n + e % da;
-              Hc[o] = hv[u];
-              Sc[o] = sv[u];
+          for (int u = 0; u < 4; ++u)
+            if (q0 + u < db) {
+              hc[(long long)(q0 + u) * n] = hv[u];
+              sc[(long long)(q0 + u) * n] = sv[u];
             }
-          }
         }
       }
     }
@@ -468,7 +470,7 @@ void launch_gather(Plan &p, const double *d_H, const double *d_S) {
     hipLaunchKernelGGL(lno_blocks_kernel, dim3(std::min(p.n_atoms, 8 * p.n_cu)), dim3(kWG), 0, p.stream, p.n_atoms,
                        p.d_row_ptr, p.d_col, p.d_n_orb, p.d_blk_off, p.d_rank, p.d_U, d_H, d_S, p.d_lno_blk,
                        p.blk_total);
-  hipLaunchKernelGGL(gather_kernel, dim3(p.workgroups), dim3(kWG), 0, p.stream, p.n_atoms, p.d_order, p.d_mem_ptr,
+  hipLaunchKernelGGL(gather_kernel, dim3(p.workgroups), dim3(kWG), sizeof(unsigned short) * p.max_dim, p.stream, p.n_atoms, p.d_order, p.d_mem_ptr,
                      p.d_mem_atom, p.d_mem_long, p.d_pair_ptr, p.d_pair_ab, p.d_pair_blk, p.d_n_orb, p.d_blk_off, d_H,
                      d_S, p.lno_mode, p.d_rank, p.d_lno_blk, p.blk_total, p.d_mat, p.d_mat_off, p.d_dmax, p.d_dim);
 }
