@@ -352,11 +352,14 @@ __global__ void __launch_bounds__(256, 2) sygst_kernel(int n_clusters, const int
                                                     double *__restrict__ vec, const long long *__restrict__ vec_off,
                                                     const int *__restrict__ dmax, const int *__restrict__ dim,
                                                     const int *__restrict__ n_orb) {
-  __shared__ double L11[NB][NB + 1];
-  __shared__ double Li[NB][NB + 1];
-  __shared__ double Pi[NB][NB + 1];
-  __shared__ double Bq[NB][NB + 1];
-  __shared__ double gl[kGemmLds];
+  // GEMM staging; the four NB x NB blocks of the inversion share it (they are dead whenever
+  // a product runs)
+  constexpr int kInvLds = 4 * NB * (NB + 1);
+  __shared__ double gl[kGemmLdsWide > kInvLds ? kGemmLdsWide : kInvLds];
+  double(*L11)[NB + 1] = reinterpret_cast<double(*)[NB + 1]>(gl);
+  double(*Li)[NB + 1] = L11 + NB;
+  double(*Pi)[NB + 1] = Li + NB;
+  double(*Bq)[NB + 1] = Pi + NB;
   const int tid = threadIdx.x, nthr = blockDim.x;
   for (int s = blockIdx.x; s < n_clusters; s += gridDim.x) {
     const int c = order[s];
@@ -452,14 +455,14 @@ __global__ void __launch_bounds__(256, 2) sygst_kernel(int n_clusters, const int
     const int nblk2 = (n + GT - 1) / GT;
     for (int bj = nblk2 - 1; bj >= 0; --bj) {
       const int r0 = bj * GT, jb = min(GT, n - r0), r1 = r0 + jb;
-      wg_gemm<G_OVERWRITE | G_PLUS>(H + r0, ld, L + r0, ld, H, ld, jb, n, r1, gl, r0);
+      wg_gemm<G_OVERWRITE | G_PLUS, 64, 128>(H + r0, ld, L + r0, ld, H, ld, jb, n, r1, gl, r0);
     }
     // 3. A = L^{-1} W^T in place, lower part: block row b of A = L^{-1}(rows b, cols 0:r1)
     //    W(0:r1, 0:r1)^T.  Only the diagonal tile reads W's rows b, so the tiles run from the
     //    last (diagonal) one.
     for (int bj = nblk2 - 1; bj >= 0; --bj) {
       const int r0 = bj * GT, jb = min(GT, n - r0), r1 = r0 + jb;
-      wg_gemm<G_TRANS_B | G_OVERWRITE | G_PLUS | G_REV>(H + r0, ld, L + r0, ld, H, ld, jb, r1, r1, gl, r0);
+      wg_gemm<G_TRANS_B | G_OVERWRITE | G_PLUS | G_REV, 64, 128>(H + r0, ld, L + r0, ld, H, ld, jb, r1, r1, gl, r0);
     }
   }
 }

@@ -11,9 +11,11 @@ constexpr int GK = 32;    // K chunk
 constexpr int GPAD = 1;   // LDS padding (doubles)
 
 // LDS needed by wg_gemm: 2 * GK * (GT + GPAD) doubles; by the tall 128 x 32 tiles
-// (wg_gemm<F, 128, 32>): GK * (128 + 32 + 2 GPAD).
+// (wg_gemm<F, 128, 32>): GK * (128 + 32 + 2 GPAD); by the wide 64 x 128 tiles
+// (wg_gemm<F, 64, 128>, K chunks of GK / 2): GK / 2 * (64 + 128 + 2 GPAD).
 constexpr int kGemmLds = 2 * GK * (GT + GPAD);
 constexpr int kGemmLdsTall = GK * (128 + 32 + 2 * GPAD);
+constexpr int kGemmLdsWide = GK / 2 * (64 + 128 + 2 * GPAD);
 
 typedef double ldc_double4 __attribute__((ext_vector_type(4)));
 
@@ -41,8 +43,9 @@ enum : unsigned {
 // is read along rows of the stored lower triangle, the others down its columns (coalesced
 // except in the chunks that cross the diagonal).
 //
-// TM x TN output tiles (64 x 64, or 128 x 32 for outputs 32 columns wide); each of the 4
-// waves owns a 32 x 32 part as 2 x 2 blocks of v_mfma_f64_16x16x4 (FP64 matrix cores).  Operands are swapped so that each output
+// TM x TN output tiles: 64 x 64, 128 x 32 (outputs 32 columns wide) or 64 x 128 (fewer
+// re-reads of A); each of the 4 waves owns a 32 x 32 part (32 x 64 for 64 x 128 tiles) as
+// 2 x BN blocks of v_mfma_f64_16x16x4 (FP64 matrix cores).  Operands are swapped so that each output
 // register covers 16 consecutive rows of one column (coalesced column-major stores):
 // the instruction's A operand takes op(B) (lane l: op(B)[k0 + l/16][c0 + l%16]) and its B
 // operand takes A (lane l: A[r0 + l%16][k0 + l/16]); register r of lane l then holds
@@ -56,17 +59,20 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
   constexpr bool OVERWRITE = F & G_OVERWRITE, PREFETCH_C = !(F & G_LATE_C), C_RM = F & G_C_RM;
   constexpr bool A_SYM = F & G_A_SYM, PLUS = F & G_PLUS, REV = F & G_REV;
   static_assert(!(A_SYM && A_RM), "a symmetric A is stored column-major");
-  static_assert(TM * TN == 4 * 32 * 32 && TM % 32 == 0 && TN % 32 == 0, "four 32 x 32 wave parts");
+  constexpr int KC = (TN == 128) ? GK / 2 : GK;  // K chunk (halved for the wide tiles: fewer registers)
+  // wave grid GR x GC (GR = TM / 32 rows of waves), each wave 32 x (16 BN)
+  constexpr int GR = TM / 32, GC = 4 / GR, BN = TN / (16 * GC), WN = 16 * BN;
+  static_assert(TM % 32 == 0 && GR * GC == 4 && (BN == 2 || BN == 4) && WN * GC == TN, "tile shape");
   static_assert(!LOWER || TM == TN, "lower-triangle tiling needs square tiles");
   constexpr int LSA = TM + GPAD, LSB = TN + GPAD;
-  constexpr int PERA = TM * GK / 256, PERB = TN * GK / 256;  // staged elements per thread
-  double *As = lds;                   // [GK][LSA]
-  double *Bs = lds + GK * LSA;        // [GK][LSB]
+  constexpr int PERA = TM * KC / 256, PERB = TN * KC / 256;  // staged elements per thread
+  double *As = lds;                   // [KC][LSA]
+  double *Bs = lds + KC * LSA;        // [KC][LSB]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave / (TN / 32), wc = wave % (TN / 32);
+  const int wr = wave / GC, wc = wave % GC;
   const int li = lane & 15, lk = lane >> 4;
   const int mt = (m + TM - 1) / TM, nt = (n + TN - 1) / TN;
-  // Staging: element q of this thread's share of a 64 x GK tile sits at (e + q STEP) along
+  // Staging: element q of this thread's share of a 64 x KC tile sits at (e + q STEP) along
   // the 64 edge and kk along K (K-fast layout), or at e along the edge and (kk + q STEP)
   // along K (edge-fast layout); the faster-running index follows the operand's memory
   // layout (coalesced loads).  Offsets are 32-bit (a cluster matrix has far fewer than 2^31
@@ -74,8 +80,8 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
   constexpr bool B_KFAST = !((TRANS_B && !B_RM) || (!TRANS_B && B_RM));
   const int ef = tid % TM, kf = tid / TM;      // edge-fast position (A)
   const int efb = tid % TN, kfb = tid / TN;    // edge-fast position (B)
-  const int ek = tid / GK, kk0 = tid % GK;     // K-fast position
-  constexpr int STEP_E = 256 / TM, STEP_EB = 256 / TN, STEP_K = 256 / GK;
+  const int ek = tid / KC, kk0 = tid % KC;     // K-fast position
+  constexpr int STEP_E = 256 / TM, STEP_EB = 256 / TN, STEP_K = 256 / KC;
   const int b_e = B_KFAST ? ek : efb, b_k = B_KFAST ? kk0 : kfb;
   constexpr int B_STEP = B_KFAST ? STEP_K : STEP_EB;
   const int a_rs = A_RM ? lda : 1, a_ks = A_RM ? 1 : lda;
@@ -166,20 +172,20 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
     const int nxt = next_tile(tile + 1);
     const int r0n = (nxt >= 0) ? (tile_of(nxt) / nt) * TM : 0, c0n = (nxt >= 0) ? (tile_of(nxt) % nt) * TN : 0;
     const bool fetch_next = nxt >= 0 && k_end(r0n) > 0;
-    ldc_double4 acc[2][2];
+    ldc_double4 acc[2][BN];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) acc[a][b] = ldc_double4{0.0, 0.0, 0.0, 0.0};
-    double cold[2][2][4];
-    for (int k0 = 0; k0 < kend; k0 += GK) {
+      for (int b = 0; b < BN; ++b) acc[a][b] = ldc_double4{0.0, 0.0, 0.0, 0.0};
+    double cold[2][BN][4];
+    for (int k0 = 0; k0 < kend; k0 += KC) {
       __syncthreads();
       stage(amode, ra, rb);
       __syncthreads();
-      if (k0 + GK < kend) {
-        amode = a_mode_of(r0, k0 + GK);
-        fetchA(r0, k0 + GK, amode, ra);
-        fetchB(c0, k0 + GK, rb);
+      if (k0 + KC < kend) {
+        amode = a_mode_of(r0, k0 + KC);
+        fetchA(r0, k0 + KC, amode, ra);
+        fetchB(c0, k0 + KC, rb);
       } else {
         if (fetch_next) {
           amode = a_mode_of(r0n, 0);
@@ -190,26 +196,26 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
 #pragma unroll
           for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
+            for (int b = 0; b < BN; ++b)
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
-                const int gr = r0 + wr * 32 + a * 16 + li, gc = c0 + wc * 32 + b * 16 + 4 * r + lk;
+                const int gr = r0 + wr * 32 + a * 16 + li, gc = c0 + wc * WN + b * 16 + 4 * r + lk;
                 cold[a][b][r] = (gr < m && gc < n) ? C[cidx(gr, gc)] : 0.0;
               }
         }
       }
 #pragma unroll
-      for (int s4 = 0; s4 < GK / 4; ++s4) {
+      for (int s4 = 0; s4 < KC / 4; ++s4) {
         const int kra = (4 * s4 + lk) * LSA, krb = (4 * s4 + lk) * LSB;
-        double af[2], bf[2];
+        double af[2], bf[BN];
 #pragma unroll
         for (int a = 0; a < 2; ++a) af[a] = As[kra + wr * 32 + a * 16 + li];
 #pragma unroll
-        for (int b = 0; b < 2; ++b) bf[b] = Bs[krb + wc * 32 + b * 16 + li];
+        for (int b = 0; b < BN; ++b) bf[b] = Bs[krb + wc * WN + b * 16 + li];
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
-          for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[b], af[a], acc[a][b], 0, 0, 0);
+          for (int b = 0; b < BN; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[b], af[a], acc[a][b], 0, 0, 0);
       }
     }
     if (kend <= 0 && fetch_next) {
@@ -223,10 +229,10 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
     for (int a = 0; a < 2; ++a) {
       const int gr = r0 + wr * 32 + a * 16 + li;
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
+      for (int b = 0; b < BN; ++b) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int gc = c0 + wc * 32 + b * 16 + 4 * r + lk;
+          const int gc = c0 + wc * WN + b * 16 + 4 * r + lk;
           if (gr < m && gc < n) {
             const double v = PLUS ? acc[a][b][r] : -acc[a][b][r];
             if (OVERWRITE) C[cidx(gr, gc)] = v;
