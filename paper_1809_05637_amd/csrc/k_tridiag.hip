@@ -257,7 +257,7 @@ __device__ __noinline__ void band_panel(double *__restrict__ A, int ld, int n, i
   }
   __syncthreads();
   // Gst = -V^T V
-  wg_gemm<G_B_RM | G_OVERWRITE>(Gst, b, VW, 2 * b, VW, 2 * b, b, b, m, sh);
+  wg_atb32<false>(Gst, b, VW, 2 * b, VW, 2 * b, m, b, sh);
   // T (row-major), T(a, i) = -tau_i sum_{a <= q < i} T(a, q) G(q, i) for i > a, T(a, a) = tau_a:
   // G = V^T V and tau in LDS, lane a keeps row a in registers (T(a, q) = 0 for q < a, so every
   // lane runs the same fully unrolled recurrence)
@@ -288,7 +288,7 @@ __device__ __noinline__ void band_panel(double *__restrict__ A, int ld, int n, i
   double *A22 = A + (long long)r * ld + r;
   wg_gemm<G_A_SYM | G_B_RM | G_OVERWRITE | G_C_RM, 128, 32>(VW + b, 2 * b, A22, ld, VT, b, m, b, m, sh);
   // K = (V T)^T X, then K/2
-  wg_gemm<G_B_RM | G_OVERWRITE>(Kst, b, VT, b, VW + b, 2 * b, b, b, m, sh);
+  wg_atb32<false>(Kst, b, VT, b, VW + b, 2 * b, m, b, sh);
   for (int e = tid; e < b * b; e += nthr) Kst[e] *= 0.5;
   __syncthreads();
   // W = X - V K/2
@@ -298,13 +298,13 @@ __device__ __noinline__ void band_panel(double *__restrict__ A, int ld, int n, i
                                                              b);
   // tracked columns, rows r..: X <- (I - V T V^T)^T X = X - V (T^T V^T X), with
   // T^T V^T X = -(VT)^T X from the stored -V T (K free now holds it)
-  wg_gemm<G_B_RM | G_OVERWRITE | G_C_RM>(Kst, b, VT, b, X + (long long)r * kTrack, kTrack, b, nx, m, sh);
+  wg_atb32<true>(Kst, b, VT, b, X + (long long)r * kTrack, kTrack, m, nx, sh);
   wg_gemm<G_A_RM | G_B_RM | G_C_RM, 128, 32>(X + (long long)r * kTrack, kTrack, VW, 2 * b, Kst, b, m, nx, b, sh);
 }
 
 // ---------------------------------------------------------------------------------------
 // Stage 1: reduction to band form (see the top of the file).  Dynamic LDS: max(LEAF * nmax,
-// kGemmLds, kGemmLdsTall, kQapplyLds) doubles.
+// kGemmLds, kGemmLdsTall, kQapplyLds, kAtbLds) doubles.
 __global__ void __launch_bounds__(256, 2) sy2sb_kernel(int n_clusters, const int *__restrict__ order,
                                                        double *__restrict__ mat, const long long *__restrict__ mat_off,
                                                        double *__restrict__ vec, const long long *__restrict__ vec_off,
@@ -652,7 +652,7 @@ __global__ void __launch_bounds__(256, 2) q2x_kernel(int n_clusters, const int *
 // ---------------------------------------------------------------------------------------
 void launch_sy2sb(Plan &p) {
   const size_t lds =
-      sizeof(double) * std::max({(size_t)LEAF * p.max_dim, (size_t)kGemmLds, (size_t)kGemmLdsTall, (size_t)kQapplyLds});
+      sizeof(double) * std::max({(size_t)LEAF * p.max_dim, (size_t)kGemmLds, (size_t)kGemmLdsTall, (size_t)kQapplyLds, (size_t)kAtbLds});
   hipLaunchKernelGGL(sy2sb_kernel, dim3(p.workgroups), dim3(kWG), lds, p.stream, p.n_atoms, p.d_order, p.d_mat,
                      p.d_mat_off, p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb);
 }

@@ -246,4 +246,66 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
   __syncthreads();
 }
 
+// C = -(A^T B) for a tall A (m x 32) and B (m x N, N <= 32), both row-major (row strides lda,
+// ldb >= 32 resp. N), m >= 1; C is 32 x N, column-major (ldc) or row-major (C_RM).  The K
+// range (the m rows) is split over the four waves in steps of 4 rows; each wave accumulates
+// a full 32 x 32 partial product on the matrix cores (loads of 8 steps in flight) and the
+// partial sums meet in LDS (4 x 32 x 33 doubles of lds).
+constexpr int kAtbLds = 4 * 32 * 33;
+template <bool C_RM>
+__device__ void wg_atb32(double *C, int ldc, const double *A, int lda, const double *B, int ldb, int m, int N,
+                         double *lds) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  constexpr int U = 8;
+  ldc_double4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = ldc_double4{0.0, 0.0, 0.0, 0.0};
+  const int nsteps = (m + 3) / 4;
+  for (int s0 = wave; s0 < nsteps; s0 += 4 * U) {
+    double av[U][2], bv[U][2];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int row = (s0 + 4 * u) * 4 + lk;
+      const int rr = row < m ? row : m - 1;  // clamped: every load is in bounds
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[u][a] = A[rr * lda + a * 16 + li];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int col = b * 16 + li;
+        bv[u][b] = B[rr * ldb + (col < N ? col : N - 1)];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int row = (s0 + 4 * u) * 4 + lk;
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[u][a] = row < m ? av[u][a] : 0.0;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[u][b], av[u][a], acc[a][b], 0, 0, 0);
+    }
+  }
+  // register r of block (a, b) holds the partial C[a 16 + li][b 16 + 4 r + lk]
+  double *P = lds + wave * 32 * 33;
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) P[(a * 16 + li) * 33 + b * 16 + 4 * r + lk] = acc[a][b][r];
+  __syncthreads();
+  for (int e = tid; e < 32 * N; e += blockDim.x) {
+    const int i = C_RM ? e / N : e % 32, j = C_RM ? e % N : e / 32;
+    const int o = i * 33 + j;
+    const double v = (lds[o] + lds[32 * 33 + o]) + (lds[2 * 32 * 33 + o] + lds[3 * 32 * 33 + o]);
+    C[C_RM ? i * ldc + j : j * ldc + i] = -v;
+  }
+  __syncthreads();
+}
+
 }  // namespace ldc
