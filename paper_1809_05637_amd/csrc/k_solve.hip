@@ -328,7 +328,7 @@ __global__ void __launch_bounds__(256, 2) potrf_kernel(int n_clusters, const int
           // second panel: A22 -= [L21 of both panels] [L21 of both panels]^T (the first
           // panel's L21 rows below this panel sit in the NB columns to the left)
           const double *P2 = S + (long long)(j0 - NB) * ld + j0 + jb;
-          wg_gemm<G_TRANS_B | G_LOWER>(C, ld, P2, ld, P2, ld, m, m, NB + jb, gl);
+          wg_gemm<G_TRANS_B | G_LOWER | G_EARLY_C>(C, ld, P2, ld, P2, ld, m, m, NB + jb, gl);
         }
       }
     }

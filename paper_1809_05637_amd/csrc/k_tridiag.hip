@@ -37,9 +37,11 @@ constexpr int kLeafRows = (kMaxDimTri + kWG - 1) / kWG;  // leaf rows held per t
 // On return P holds R on and above its diagonal and the Householder vectors below it (unit
 // diagonal implicit); tau_k goes to tt[j0 + k] (0 where the reflector has length <= 1).
 // lf: LEAF * m doubles of LDS; sm: 2 * LEAF * LEAF + 4 * LEAF doubles; red: 10 * LEAF.
+// The reflectors also go to VW (row-major, row stride 2 kBand, rows from r): V explicitly,
+// unit diagonal and zeros above it.
 // Needs blockDim.x == kWG (four waves).
 __device__ void panel_qr(double *__restrict__ A, int ld, int n, int j0, double *__restrict__ tt, double *lf,
-                         double *sm, double *red) {
+                         double *sm, double *red, double *__restrict__ VW) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nthr = blockDim.x, nw = nthr >> 6;
   const int r = j0 + kBand;
   double *Tl = sm;                  // [LEAF][LEAF] leaf T (row-major)
@@ -50,6 +52,9 @@ __device__ void panel_qr(double *__restrict__ A, int ld, int n, int j0, double *
     const int R0 = r + c0, mp = n - R0;
     if (mp <= 0) {
       if (tid < LEAF) tt[j0 + c0 + tid] = 0.0;
+      for (int i = tid; i < n - r; i += nthr)
+#pragma unroll
+        for (int c = 0; c < LEAF; ++c) VW[(long long)i * 2 * kBand + c0 + c] = 0.0;
       continue;
     }
     // leaf in registers: thread tid holds rows i = tid + kWG t (rows past mp read as zero;
@@ -135,8 +140,8 @@ __device__ void panel_qr(double *__restrict__ A, int ld, int n, int j0, double *
         tl[k] = tau_p;
       }
     }
-    // leaf back to A, and into LDS (column-major, stride mp) for the Gram matrix and the
-    // later panel columns
+    // leaf back to A, into LDS (column-major, stride mp) for the Gram matrix and the later
+    // panel columns, and V's columns c0.. into VW (rows c0 + i; the rows above are zero)
 #pragma unroll
     for (int c = 0; c < LEAF; ++c)
 #pragma unroll
@@ -147,6 +152,19 @@ __device__ void panel_qr(double *__restrict__ A, int ld, int n, int j0, double *
           lf[c * mp + i] = x[c][t];
         }
       }
+#pragma unroll
+    for (int t = 0; t < kLeafRows; ++t) {
+      const int i = tid + kWG * t;
+      if (i < mp) {
+        double *vr = VW + (long long)(c0 + i) * 2 * kBand + c0;
+#pragma unroll
+        for (int c = 0; c < LEAF; ++c) vr[c] = (i == c) ? 1.0 : (i > c ? x[c][t] : 0.0);
+      }
+    }
+    if (tid < c0) {
+#pragma unroll
+      for (int c = 0; c < LEAF; ++c) VW[(long long)tid * 2 * kBand + c0 + c] = 0.0;
+    }
     __syncthreads();
     if (c0 + LEAF >= kBand) break;  // no later panel columns
     // leaf Gram matrix G(a, b) = v_a . v_b (a < b): 8 lanes per pair, rows strided by 8
@@ -246,16 +264,8 @@ __device__ __noinline__ void band_panel(double *__restrict__ A, int ld, int n, i
   const int tid = threadIdx.x, nthr = blockDim.x;
   constexpr int b = kBand;
   const int r = j0 + b, m = n - r;
-  panel_qr(A, ld, n, j0, tt, sh, sm, red);
-  // V (explicit, unit diagonal) into the first half of the rows of [V | W]
-  for (long long e = tid; e < (long long)m * b; e += nthr) {
-    const int i = (int)(e / b), k = (int)(e % b);
-    double v = 0.0;
-    if (i == k) v = 1.0;
-    else if (i > k) v = A[(long long)(j0 + k) * ld + r + i];
-    VW[(long long)i * 2 * b + k] = v;
-  }
-  __syncthreads();
+  // QR of the panel; V (explicit, unit diagonal) into the first half of the rows of [V | W]
+  panel_qr(A, ld, n, j0, tt, sh, sm, red, VW);
   // Gst = -V^T V
   wg_atb32<false>(Gst, b, VW, 2 * b, VW, 2 * b, m, b, sh);
   // T (row-major), T(a, i) = -tau_i sum_{a <= q < i} T(a, q) G(q, i) for i > a, T(a, a) = tau_a:
@@ -294,8 +304,7 @@ __device__ __noinline__ void band_panel(double *__restrict__ A, int ld, int n, i
   // W = X - V K/2
   wg_gemm<G_A_RM | G_C_RM, 128, 32>(VW + b, 2 * b, VW, 2 * b, Kst, b, m, b, b, sh);
   // A22 -= V W^T + W V^T (lower triangle)
-  wg_gemm<G_TRANS_B | G_LOWER | G_A_RM | G_B_RM>(A22, ld, VW, 2 * b, VW, 2 * b, m, m, 2 * b, sh, -1,
-                                                             b);
+  wg_gemm<G_TRANS_B | G_LOWER | G_A_RM | G_B_RM | G_EARLY_C>(A22, ld, VW, 2 * b, VW, 2 * b, m, m, 2 * b, sh, -1, b);
   // tracked columns, rows r..: X <- (I - V T V^T)^T X = X - V (T^T V^T X), with
   // T^T V^T X = -(VT)^T X from the stored -V T (K free now holds it)
   wg_atb32<true>(Kst, b, VT, b, X + (long long)r * kTrack, kTrack, m, nx, sh);

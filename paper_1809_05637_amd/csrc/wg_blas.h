@@ -31,6 +31,7 @@ enum : unsigned {
   G_A_SYM = 128u,     // A is symmetric, held in the lower triangle of a column-major array
   G_PLUS = 256u,      // add instead of subtract: C += A op(B) (G_OVERWRITE: C = A op(B))
   G_REV = 512u,       // tiles from the last to the first
+  G_EARLY_C = 1024u,  // fetch C with the tile's first K chunk (short K: more time to arrive)
 };
 
 // C[m x n] -= A[m x k] * op(B)   (G_OVERWRITE: C = -A op(B); G_PLUS: + instead of -).
@@ -51,13 +52,13 @@ enum : unsigned {
 // operand takes A (lane l: A[r0 + l%16][k0 + l/16]); register r of lane l then holds
 // C[r0 + l%16][c0 + 4 r + l/16].  The next K chunk of A and op(B) (after a tile's last
 // chunk: the next tile's first) is fetched into registers while the current one is multiplied;
-// with the last chunk C is fetched too (unless G_LATE_C).
+// with the last chunk C is fetched too (with the first under G_EARLY_C; not under G_LATE_C).
 template <unsigned F, int TM = GT, int TN = GT>
 __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const double *B, int ldb, int m, int n, int k,
                         double *lds, int a_diag = -1, int b_rot = 0) {
   constexpr bool TRANS_B = F & G_TRANS_B, LOWER = F & G_LOWER, A_RM = F & G_A_RM, B_RM = F & G_B_RM;
   constexpr bool OVERWRITE = F & G_OVERWRITE, PREFETCH_C = !(F & G_LATE_C), C_RM = F & G_C_RM;
-  constexpr bool A_SYM = F & G_A_SYM, PLUS = F & G_PLUS, REV = F & G_REV;
+  constexpr bool A_SYM = F & G_A_SYM, PLUS = F & G_PLUS, REV = F & G_REV, EARLY_C = F & G_EARLY_C;
   static_assert(!(A_SYM && A_RM), "a symmetric A is stored column-major");
   constexpr int KC = (TN == 128) ? GK / 2 : GK;  // K chunk (halved for the wide tiles: fewer registers)
   // wave grid GR x GC (GR = TM / 32 rows of waves), each wave 32 x (16 BN)
@@ -192,17 +193,17 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
           fetchA(r0n, 0, amode, ra);
           fetchB(c0n, 0, rb);
         }
-        if (!OVERWRITE && PREFETCH_C) {
+      }
+      if (!OVERWRITE && PREFETCH_C && (EARLY_C ? k0 == 0 : k0 + KC >= kend)) {
 #pragma unroll
-          for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int b = 0; b < BN; ++b)
+          for (int b = 0; b < BN; ++b)
 #pragma unroll
-              for (int r = 0; r < 4; ++r) {
-                const int gr = r0 + wr * 32 + a * 16 + li, gc = c0 + wc * WN + b * 16 + 4 * r + lk;
-                cold[a][b][r] = (gr < m && gc < n) ? C[cidx(gr, gc)] : 0.0;
-              }
-        }
+            for (int r = 0; r < 4; ++r) {
+              const int gr = r0 + wr * 32 + a * 16 + li, gc = c0 + wc * WN + b * 16 + 4 * r + lk;
+              cold[a][b][r] = (gr < m && gc < n) ? C[cidx(gr, gc)] : 0.0;
+            }
       }
 #pragma unroll
       for (int s4 = 0; s4 < KC / 4; ++s4) {
