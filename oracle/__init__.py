@@ -19,6 +19,8 @@ It is a plain, slow, step-by-step restatement of the method in the paper's order
 * ``exact``    -- the conventional O(N^3) density matrix of the whole system by the Loewdin
                   route (Eq. 2, 8-12), used for the whole-system identity checks.
 * ``driver``   -- ``density_build``: the whole pipeline for one build.
+* ``scf``      -- a toy self-consistent loop around the build (LNOs regenerated every step,
+                  Sec. II.C (i)): Mulliken populations, a Hubbard-like potential, linear mixing.
 
 Readings of points the paper leaves open are listed in each module's docstring.
 Parity status: every function is pinned by tests under tests/test_oracle_*.py (paper
@@ -30,3 +32,4 @@ from .cluster import cluster_matrices, solve_cluster  # noqa: F401
 from .density import fermi, bisect_mu, density_rows, energy_density_rows, band_energy_and_count  # noqa: F401
 from .exact import exact_density, exact_density_blocks  # noqa: F401
 from .driver import density_build  # noqa: F401
+from .scf import mulliken, potential, reference_populations, scf_loop  # noqa: F401
