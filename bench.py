@@ -143,6 +143,94 @@ def cpu_baseline(s, sample_n, seed=0):
                        f"{time.time() - t_start:.1f} s wall; build time extrapolated to all clusters: {est:.1f} s")}
 
 
+def scf_bench(s, plan, H0, S, rule, use_lno, args, log):
+    """Toy SCF loop: one untimed step (plain DC, seeds the LNOs), then args.scf steps timed with
+    HIP events on the plan's stream; then Mulliken, potential and mixing timed alone."""
+    import torch
+    import paper_1809_05637_amd.scf as scf
+    stream = torch.cuda.current_stream()
+    U, alpha = args.scf_u, args.scf_alpha
+    ev = []
+
+    def on_step(k, rec):
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(stream)
+        ev.append(e)
+        log(f"[scf] step {k}: residual {rec['residual']:.3e} mu={rec['mu']:.10f} "
+            f"E_band/atom={rec['e_band'] / s['n_atoms']:.10f}")
+        if k == 0:
+            plan.profile(True)
+
+    torch.cuda.synchronize()
+    hist = scf.scf_loop(plan, H0, S, s["n_electrons"], s["kT"], U, alpha, args.scf + 1, lno=use_lno,
+                        on_step=on_step, **rule)
+    torch.cuda.synchronize()
+    ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(len(ev) - 1)]
+    ms_step = float(np.mean(ms))
+    stages, builds = plan.stage_times()
+    per_stage = {k: v / max(1, builds) for k, v in stages.items()}
+    # the SCF kernels alone (10 calls each, on the last step's buffers)
+    q0 = torch.as_tensor(scf.reference_populations(s["n_orb"], s["n_electrons"]), device=S.device)
+    q_in, q_out, v = q0.clone(), torch.zeros_like(q0), torch.zeros_like(q0)
+    D, H = torch.zeros_like(S), torch.empty_like(H0)
+
+    def timed(fn, reps=10):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    ms_mull = timed(lambda: plan.mulliken(D, S, q_out))
+    ms_pot = timed(lambda: plan.potential(H0, S, v, H))
+    ms_mix = timed(lambda: plan.scf_mix(q_out, q_in, q0, U, alpha, v, want_residual=False))
+    nb = float(len(s["S"])) * 8.0
+    kern = {"mulliken_ms": round(ms_mull, 4), "potential_ms": round(ms_pot, 4), "mix_ms": round(ms_mix, 4),
+            "mulliken_bytes": 2 * nb, "potential_bytes": 3 * nb,
+            "mulliken_GBps": round(2 * nb / (ms_mull * 1e-3) / 1e9, 1),
+            "potential_GBps": round(3 * nb / (ms_pot * 1e-3) / 1e9, 1), "hbm_peak_GBps": HBM_PEAK_GBS}
+    log(f"[scf] {args.scf} timed steps: {ms_step:.1f} ms/step; kernels: " +
+        ", ".join(f"{k}={v}" for k, v in kern.items()))
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        log("[scf] cpu baseline (oracle) ...")
+        cb = cpu_baseline(s, args.cpu_sample)
+        t0 = time.time()
+        q = oracle.mulliken(s, s["S"])
+        oracle.potential(s, s["H"], 0.1 * (q - oracle.reference_populations(s)))
+        t_scf = time.time() - t0
+        build_s = s["n_atoms"] / cb["value"]
+        cpu = {"value": round(s["n_atoms"] / (build_s + t_scf), 3), "unit": "atoms/s", "cores": cb["cores"],
+               "kind": "oracle",
+               "sample": cb["sample"] + f"; plus the oracle's Mulliken populations and potential on the whole "
+                                        f"system, one process: {t_scf:.2f} s"}
+    out = {
+        "metric": "atoms/s per toy SCF step (FP64 form; LNOs regenerated every step)",
+        "value": round(s["n_atoms"] / (ms_step * 1e-3), 2),
+        "unit": "atoms/s",
+        "n_gpus": 1,
+        "steps": args.scf,
+        "warmup": 1,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": s["name"] + "_scf_fp64", "U": U, "alpha": alpha, "atoms": int(s["n_atoms"])},
+        "residuals": [round(h["residual"], 8) for h in hist],
+        "build_stage_ms": {k: round(v, 3) for k, v in per_stage.items()},
+        "scf_kernels": kern,
+    }
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +240,11 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--scf", type=int, default=0, metavar="K",
+                    help="instead of the build benchmark: K timed steps of the toy SCF loop (LNOs regenerated "
+                         "every step) after one untimed step, and the SCF kernels timed alone")
+    ap.add_argument("--scf-u", type=float, default=0.2)
+    ap.add_argument("--scf-alpha", type=float, default=0.3)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run three device-to-device copies of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -185,6 +278,10 @@ def main():
     rule = dict(lambda_th=s["lambda_th"], k_min=s["k_min"], k_max=s["k_max"],
                 fixed_rank=s["fixed_k"] if s["fixed_k"] >= 0 else None)
     use_lno = bool(s["lno"])
+    if args.scf > 0:
+        print(json.dumps(scf_bench(s, plan, H, S, rule, use_lno, args, log)), flush=True)
+        plan.close()
+        return
     # step 0: plain DC seeds the first LNOs
     t2 = time.time()
     plan.lno(S, None)

@@ -151,6 +151,30 @@ ldc_status ldc_density_at(ldc_plan_t plan, double mu, double kT, double *d_D_out
  * since the last ldc_solve. */
 ldc_status ldc_energy_density(ldc_plan_t plan, double *d_E_out, double *tr_es_out);
 
+/* Toy self-consistent loop (Sec. II.C step (i): the LNOs are recomputed from the previous SCF
+ * step's density at every step, so that they become self-consistent).  A step is
+ *   ldc_potential (H from H0 and v)  ->  ldc_lno (from the previous D)  ->  ldc_solve  ->
+ *   ldc_density  ->  ldc_mulliken  ->  ldc_scf_mix,
+ * with the model Hamiltonian H_ij = H0_ij + (v_i + v_j)/2 S_ij, v_i = U (q_i - q0_i), on the
+ * Mulliken populations q_i.  All vectors below are device arrays of n_atoms doubles; the
+ * calls are enqueued on the plan's stream.
+ *
+ * ldc_mulliken: q_i = g sum_{j in the pattern row of i} sum_ab D_ij[a,b] S_ij[a,b] from the
+ * density rows d_D (row i of D comes from cluster i; for the full density matrix this is
+ * g sum_{a in i} (D S)_aa).  Inputs in the layout of S. */
+ldc_status ldc_mulliken(ldc_plan_t plan, const double *d_D, const double *d_S, double *d_q);
+
+/* ldc_potential: H_ij = H0_ij + (v_i + v_j)/2 S_ij on every pattern block (a uniform v shifts
+ * every cluster eigenvalue by v).  d_H may be d_H0 (in place). */
+ldc_status ldc_potential(ldc_plan_t plan, const double *d_H0, const double *d_S, const double *d_v, double *d_H);
+
+/* ldc_scf_mix: linear mixing of the input populations, q_in <- q_in + alpha (q_out - q_in)
+ * (d_q_in updated in place, 0 <= alpha <= 1), then d_v = U (q_in - q0) for the next step.
+ * residual_out (host, may be NULL): max_i |q_out - q_in| before the mixing; when given, the
+ * call synchronizes. */
+ldc_status ldc_scf_mix(ldc_plan_t plan, const double *d_q_out, double *d_q_in, const double *d_q0, double U,
+                       double alpha, double *d_v, double *residual_out);
+
 /* Copy one cluster's spectrum (eps ascending, weights) to host arrays of capacity
  * >= max_dim_pao; *dim receives its dimension.  Synchronizes. */
 ldc_status ldc_cluster_spectrum(ldc_plan_t plan, int atom, double *eps, double *w, int *dim);

@@ -81,6 +81,9 @@ def load():
         "ldc_density": (c_int, [c_void_p, c_double, c_double, c_void_p, P_double, P_double, P_double]),
         "ldc_density_at": (c_int, [c_void_p, c_double, c_double, c_void_p, P_double, P_double]),
         "ldc_energy_density": (c_int, [c_void_p, c_void_p, P_double]),
+        "ldc_mulliken": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+        "ldc_potential": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+        "ldc_scf_mix": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_double, c_void_p, P_double]),
         "ldc_cluster_spectrum": (c_int, [c_void_p, c_int, P_double, P_double, P_int]),
         "ldc_last_error": (ctypes.c_char_p, [c_void_p, P_int]),
         "ldc_cluster_dims": (c_int, [c_void_p, P_int]),
@@ -218,6 +221,22 @@ class Plan:
         tr = c_double()
         self._check(self._lib.ldc_energy_density(self._h, _ptr(E_out), ctypes.byref(tr)))
         return tr.value
+
+    def mulliken(self, D, S, q_out):
+        """ldc_mulliken: Mulliken populations of every atom from the density rows into q_out."""
+        self._check(self._lib.ldc_mulliken(self._h, _ptr(D), _ptr(S), _ptr(q_out)))
+
+    def potential(self, H0, S, v, H_out):
+        """ldc_potential: H_out = H0 + (v_i + v_j)/2 S on every pattern block."""
+        self._check(self._lib.ldc_potential(self._h, _ptr(H0), _ptr(S), _ptr(v), _ptr(H_out)))
+
+    def scf_mix(self, q_out, q_in, q0, U, alpha, v_out, want_residual=True):
+        """ldc_scf_mix: q_in += alpha (q_out - q_in), v_out = U (q_in - q0).  Returns the residual
+        max |q_out - q_in| (before the mixing) when want_residual, else None."""
+        res = c_double()
+        self._check(self._lib.ldc_scf_mix(self._h, _ptr(q_out), _ptr(q_in), _ptr(q0), float(U), float(alpha),
+                                          _ptr(v_out), ctypes.byref(res) if want_residual else None))
+        return res.value if want_residual else None
 
     def cluster_dims(self):
         """Reduced dimension of every cluster after the last solve."""

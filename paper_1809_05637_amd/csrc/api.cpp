@@ -11,6 +11,9 @@ using ldc::Plan;
 
 namespace {
 
+// slot of the plan's small state array that receives the SCF mixing residual
+constexpr int kScfResidualSlot = 24;
+
 const char *kVersion = "ldc 0.1.0 (gfx950)";
 
 #define HIPCHK(expr)                                                                         \
@@ -50,7 +53,7 @@ void free_all(Plan &p) {
                   p.d_pair_ptr, p.d_pair_ab,  p.d_pair_blk, p.d_fna_ptr, p.d_fna_blk, p.d_p_rows,   p.d_dmax,
                   p.d_order,    p.d_mat_off,  p.d_vec_off,  p.d_ivec_off, p.d_mat,    p.d_vec,      p.d_ivec,
                   p.d_dim,      p.d_rank,     p.d_U,        p.d_lambda,  p.d_fixed,   p.d_mu,       p.d_partial,
-                  p.d_counter,  p.d_status,   p.d_lno_blk};
+                  p.d_counter,  p.d_status,   p.d_lno_blk,  p.d_row_elem};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   for (int s = 0; s < LDC_NUM_STAGES; ++s) {
@@ -209,6 +212,9 @@ ldc_status ldc_plan_create(ldc_plan_t *out, int n_atoms, const double *pos, cons
     }
   }
   p.blk_total = o;
+  p.row_elem.resize(n_atoms + 1);
+  for (int i = 0; i < n_atoms; ++i) p.row_elem[i] = p.row_ptr[i] < nnzb ? p.blk_off[p.row_ptr[i]] : o;
+  p.row_elem[n_atoms] = o;
   ldc_status s = ldc::build_regions(p, pos, cell, periodic);
   if (s != LDC_OK) {
     h->p.msg = p.msg;
@@ -260,6 +266,7 @@ ldc_status ldc_plan_create(ldc_plan_t *out, int n_atoms, const double *pos, cons
   TRY(upload(p, &p.d_row_ptr, p.row_ptr));
   TRY(upload(p, &p.d_col, p.col));
   TRY(upload(p, &p.d_blk_off, p.blk_off));
+  TRY(upload(p, &p.d_row_elem, p.row_elem));
   TRY(upload(p, &p.d_mem_ptr, p.mem_ptr));
   TRY(upload(p, &p.d_mem_atom, p.mem_atom));
   TRY(upload(p, &p.d_mem_long, p.mem_long));
@@ -523,6 +530,36 @@ ldc_status ldc_energy_density(ldc_plan_t plan, double *d_E_out, double *tr_es_ou
   double st[32];
   HIPCHK(hipMemcpy(st, p.d_mu, sizeof(st), hipMemcpyDeviceToHost));
   *tr_es_out = g * st[19];
+  return LDC_OK;
+}
+
+ldc_status ldc_mulliken(ldc_plan_t plan, const double *d_D, const double *d_S, double *d_q) {
+  if (!plan || !d_D || !d_S || !d_q) return LDC_ERR_ARG;
+  Plan &p = plan->p;
+  const double g = p.opt.spin_g > 0 ? p.opt.spin_g : 2;
+  ldc::launch_mulliken(p, d_D, d_S, d_q, g);
+  HIPCHK(hipGetLastError());
+  return LDC_OK;
+}
+
+ldc_status ldc_potential(ldc_plan_t plan, const double *d_H0, const double *d_S, const double *d_v, double *d_H) {
+  if (!plan || !d_H0 || !d_S || !d_v || !d_H) return LDC_ERR_ARG;
+  Plan &p = plan->p;
+  ldc::launch_potential(p, d_H0, d_S, d_v, d_H);
+  HIPCHK(hipGetLastError());
+  return LDC_OK;
+}
+
+ldc_status ldc_scf_mix(ldc_plan_t plan, const double *d_q_out, double *d_q_in, const double *d_q0, double U,
+                       double alpha, double *d_v, double *residual_out) {
+  if (!plan || !d_q_out || !d_q_in || !d_q0 || !d_v) return LDC_ERR_ARG;
+  if (!(alpha >= 0.0 && alpha <= 1.0)) return LDC_ERR_ARG;
+  Plan &p = plan->p;
+  ldc::launch_scf_mix(p, d_q_out, d_q_in, d_q0, U, alpha, d_v, p.d_mu + kScfResidualSlot);
+  HIPCHK(hipGetLastError());
+  if (!residual_out) return LDC_OK;
+  HIPCHK(hipStreamSynchronize(p.stream));
+  HIPCHK(hipMemcpy(residual_out, p.d_mu + kScfResidualSlot, sizeof(double), hipMemcpyDeviceToHost));
   return LDC_OK;
 }
 

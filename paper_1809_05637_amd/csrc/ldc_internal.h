@@ -45,6 +45,7 @@ struct Plan {
   std::vector<int> n_orb, row_ptr, col;
   std::vector<long long> blk_off;
   long long blk_total = 0;                       // elements of one block-sparse matrix
+  std::vector<long long> row_elem;               // first element of every block row (n_atoms + 1)
 
   // regions, in the library's member order: long, short \ F, F \ {i}, i
   std::vector<int> mem_ptr, mem_atom, mem_long;
@@ -57,7 +58,7 @@ struct Plan {
 
   // device tables
   int *d_n_orb = nullptr, *d_row_ptr = nullptr, *d_col = nullptr;
-  long long *d_blk_off = nullptr;
+  long long *d_blk_off = nullptr, *d_row_elem = nullptr;
   int *d_mem_ptr = nullptr, *d_mem_atom = nullptr, *d_mem_long = nullptr;
   int *d_pair_ptr = nullptr, *d_pair_ab = nullptr, *d_pair_blk = nullptr;
   int *d_fna_ptr = nullptr, *d_fna_blk = nullptr, *d_p_rows = nullptr;
@@ -170,6 +171,11 @@ void launch_mu_fixed(Plan &p, double mu);
 // energy = 0: density rows (sums of D.H and D.S to state[16..17]); 1: energy density rows
 // (sums of E.H and E.S to state[18..19]); at mu = state[MU_MU], kT = state[MU_KT].
 void launch_density(Plan &p, int energy, double *d_D, const double *d_H, const double *d_S);
+// toy SCF loop: Mulliken populations, potential on H0, linear mixing (residual to d_res[0])
+void launch_mulliken(Plan &p, const double *d_D, const double *d_S, double *d_q, double g);
+void launch_potential(Plan &p, const double *d_H0, const double *d_S, const double *d_v, double *d_H);
+void launch_scf_mix(Plan &p, const double *d_q_out, double *d_q_in, const double *d_q0, double U, double alpha,
+                    double *d_v, double *d_res);
 
 }  // namespace ldc
 
