@@ -231,6 +231,140 @@ def scf_bench(s, plan, H0, S, rule, use_lno, args, log):
     return out
 
 
+def exact_band_energy(s):
+    """Conventional O(N^3) reference of the sweep: all generalized eigenvalues of the whole
+    system's Gamma-folded H and S (scipy), mu by bisection on g sum f = N_e, E_band = g sum f eps."""
+    import scipy.linalg
+    n_orb = np.asarray(s["n_orb"])
+    offs = np.concatenate([[0], np.cumsum(n_orb)])
+    hd = np.zeros((offs[-1], offs[-1]))
+    sd = np.zeros_like(hd)
+    for i in range(s["n_atoms"]):
+        for b in range(s["row_ptr"][i], s["row_ptr"][i + 1]):
+            j = s["col"][b]
+            o, m = s["blk_off"][b], n_orb[i] * n_orb[j]
+            hd[offs[i]:offs[i + 1], offs[j]:offs[j + 1]] = s["H"][o:o + m].reshape(n_orb[i], n_orb[j])
+            sd[offs[i]:offs[i + 1], offs[j]:offs[j + 1]] = s["S"][o:o + m].reshape(n_orb[i], n_orb[j])
+    e = scipy.linalg.eigh(hd, sd, eigvals_only=True)
+    kT, g = s["kT"], 2.0
+    f = lambda x: 0.5 * (1.0 - np.tanh(0.5 * x))  # noqa: E731
+    lo, hi = e[0] - 40 * kT, e[-1] + 40 * kT
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if hi - lo <= 4e-16 * max(1.0, abs(mid)):
+            break
+        if g * np.sum(f((e - mid) / kT)) < s["n_electrons"]:
+            lo = mid
+        else:
+            hi = mid
+    mu = 0.5 * (lo + hi)
+    return float(g * np.sum(f((e - mu) / kT) * e)), mu
+
+
+def eq28_ratio(n_short, n_long, m_p, m_l):
+    """Eq. 28 with the short and long atom counts of the cluster:
+    t_DC-LNO / t_DC = [M_P n_short + M_L n_long]^3 / [M_P (n_short + n_long)]^3.  The paper's worked
+    example (275 short, 190 long, 13 PAOs, 4 LNOs -> 0.37) evaluates it this way."""
+    return (m_p * n_short + m_l * n_long) ** 3 / (m_p * (n_short + n_long)) ** 3
+
+
+def eq28_kappa(n_f, n_s, m_p, m_l, kappa=0.3):
+    """Eq. 28 as printed, with the buffer at exactly kappa N_S:
+    [M_P (N_F + kappa N_S) + M_L (1 - kappa) N_S]^3 / [M_P (N_F + N_S)]^3."""
+    return eq28_ratio(n_f + kappa * n_s, (1 - kappa) * n_s, m_p, m_l)
+
+
+def _timed_build(plan, H, S, s, dprev, rule, D, stream):
+    import torch
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ranks = plan.lno(S, dprev, want_ranks=dprev is not None, **rule)
+    a.record(stream)
+    plan.solve(H, S)
+    mu, eb, ne = plan.density(s["n_electrons"], s["kT"], D)
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b), mu, eb, ranks
+
+
+def sweep_bench():
+    """Error of plain DC and DC-LNO against exact diagonalization versus the cluster radius
+    (Sec. IV, Fig. 5's measurement on synthetic systems), and t_DC-LNO / t_DC (solve + density,
+    HIP events) against Eq. 28 and against the cube ratio of the actual dimensions."""
+    import torch
+    import synth
+    import paper_1809_05637_amd as ldc
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    out = {"metric": "band-energy error vs cluster radius and DC-LNO/DC time ratio", "unit": "Ha/atom",
+           "n_gpus": 1, "dtype": "f64", "data": "synthetic", "systems": {}}
+    for name, shells in (("dia216", synth.SHELLS["diamond"][1:8]), ("fcc256", synth.SHELLS["fcc"][2:6])):
+        s = synth.small(name)
+        e_ex, mu_ex = exact_band_energy(s)
+        n = s["n_atoms"]
+        log(f"[sweep] {name}: {n} atoms, exact E_band/atom {e_ex / n:.12f}")
+        H = torch.from_numpy(s["H"]).to(dev)
+        S = torch.from_numpy(s["S"]).to(dev)
+        D0, D1 = torch.zeros_like(S), torch.zeros_like(S)
+        rule = dict(lambda_th=s["lambda_th"], k_min=s["k_min"], k_max=s["k_max"],
+                    fixed_rank=s["fixed_k"] if s["fixed_k"] >= 0 else None)
+        pts = []
+        for r in shells:
+            r_L = r * (1 + 1e-9)
+            plan = ldc.Plan(s["pos"], s["cell"], s["periodic"], s["n_orb"], s["row_ptr"], s["col"], r_L,
+                            kappa=s["kappa"], stream=stream)
+            ptr, _, lng = ldc.regions(s["pos"], s["cell"], s["periodic"], s["n_orb"], s["row_ptr"], s["col"], r_L)
+            n_mem = np.diff(ptr)
+            n_long = np.add.reduceat(lng, ptr[:-1]) if len(lng) else np.zeros(n, dtype=int)
+            n_f = np.diff(s["row_ptr"])
+            t_dc, _, e_dc, _ = _timed_build(plan, H, S, s, None, rule, D0, stream)
+            dims_dc = plan.cluster_dims()
+            pt = {"r_L": round(r, 4), "atoms": float(n_mem.mean()), "long": float(n_long.mean()),
+                  "dim_dc": int(dims_dc.max()), "err_dc": abs(e_dc - e_ex) / n, "ms_dc": round(t_dc, 3)}
+            if n_long.max() > 0:
+                t_l, _, e_l, ranks = _timed_build(plan, H, S, s, D0, rule, D1, stream)
+                dims_l = plan.cluster_dims()
+                m_l = float(np.mean(ranks))
+                pt.update(dim_lno=int(dims_l.max()), err_lno=abs(e_l - e_ex) / n, ms_lno=round(t_l, 3),
+                          mean_rank=m_l, cube_ratio=float(np.sum(dims_l.astype(float) ** 3) / np.sum(dims_dc.astype(float) ** 3)),
+                          eq28=float(np.mean(eq28_ratio(n_mem - n_long, n_long, float(s["n_orb"][0]), m_l))),
+                          eq28_kappa=float(np.mean(eq28_kappa(n_f, n_mem - n_f, float(s["n_orb"][0]), m_l))))
+            plan.close()
+            pts.append(pt)
+            log(f"[sweep] {name} r_L={r:.3f}: " + ", ".join(f"{k}={v:.3e}" if isinstance(v, float) else f"{k}={v}"
+                                                          for k, v in pt.items()))
+        out["systems"][name] = {"atoms": n, "basis": int(s["n_basis"]), "kT": s["kT"], "exact_e_band_per_atom": e_ex / n,
+                                "points": pts}
+    # the benchmark workload: plain DC (PAOs everywhere) against DC-LNO, two builds each
+    s = synth.load_config(2)
+    H = torch.from_numpy(s["H"]).to(dev)
+    S = torch.from_numpy(s["S"]).to(dev)
+    D0, D1 = torch.zeros_like(S), torch.zeros_like(S)
+    rule = dict(lambda_th=s["lambda_th"], k_min=s["k_min"], k_max=s["k_max"],
+                fixed_rank=s["fixed_k"] if s["fixed_k"] >= 0 else None)
+    plan = ldc.Plan.from_system(s, stream=stream)
+    ptr, _, lng = ldc.regions(s["pos"], s["cell"], s["periodic"], s["n_orb"], s["row_ptr"], s["col"], s["r_L"])
+    n_mem = np.diff(ptr)
+    n_long = np.add.reduceat(lng, ptr[:-1])
+    n_f = np.diff(s["row_ptr"])
+    t_dc = [_timed_build(plan, H, S, s, None, rule, D0, stream)[0] for _ in range(2)]
+    dims_dc = plan.cluster_dims()
+    res = [_timed_build(plan, H, S, s, D0, rule, D1, stream) for _ in range(2)]
+    dims_l = plan.cluster_dims()
+    m_l = float(np.mean(res[-1][3]))
+    t_l = [r[0] for r in res]
+    plan.close()
+    out["workload"] = {
+        "name": s["name"], "atoms": int(s["n_atoms"]), "ms_dc": round(min(t_dc), 3), "ms_lno": round(min(t_l), 3),
+        "measured_ratio": round(min(t_l) / min(t_dc), 4),
+        "cube_ratio": round(float(np.sum(dims_l.astype(float) ** 3) / np.sum(dims_dc.astype(float) ** 3)), 4),
+        "eq28_mean": round(float(np.mean(eq28_ratio(n_mem - n_long, n_long, 9.0, m_l))), 4),
+        "eq28_kappa_mean": round(float(np.mean(eq28_kappa(n_f, n_mem - n_f, 9.0, m_l))), 4), "mean_rank": round(m_l, 3),
+        "dim_dc_mean": round(float(dims_dc.mean()), 1), "dim_lno_mean": round(float(dims_l.mean()), 1)}
+    log(f"[sweep] workload: {out['workload']}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -243,6 +377,10 @@ def main():
     ap.add_argument("--scf", type=int, default=0, metavar="K",
                     help="instead of the build benchmark: K timed steps of the toy SCF loop (LNOs regenerated "
                          "every step) after one untimed step, and the SCF kernels timed alone")
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the build benchmark: band-energy error of plain DC and DC-LNO against "
+                         "exact diagonalization versus the cluster radius (a gapped and a metallic system), "
+                         "and the DC-LNO / DC time ratio on the benchmark workload against Eq. 28")
     ap.add_argument("--scf-u", type=float, default=0.2)
     ap.add_argument("--scf-alpha", type=float, default=0.3)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -250,6 +388,9 @@ def main():
     args = ap.parse_args()
     if args.copy_probe > 0:
         copy_probe(args.copy_probe)
+        return
+    if args.sweep:
+        print(json.dumps(sweep_bench()), flush=True)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs one density build on one GPU; --gpus must be 1 "

@@ -358,6 +358,7 @@ def small(name: str, seed: int = SEED_BASE + 100):
     'sc27':   simple cubic 3x3x3 torus, 4 orbitals, plain DC (r_L = 1.5).
     'dia216': diamond 3x3x3 cells (216 atoms), config-1 recipe, r_L = 2.52 (5 shells).
     'fcc_slab': fcc 4x4x3 cells periodic in x,y, 4 vacancies, config-2 recipe.
+    'fcc256':  bulk fcc 4x4x4 cells, periodic, config-2 recipe without vacancies.
     'chain_gap' / 'chain_metal': 1D rings for truncation-behaviour checks.
     """
     if name == "sc27":
@@ -375,6 +376,11 @@ def small(name: str, seed: int = SEED_BASE + 100):
     if name == "fcc_slab":
         s = make_system("fcc", (4, 4, 3), (1, 1, 0), 9, _onsite_zero, 1.0, 1.0, SHELLS["fcc"][2] + 1e-6,
                         seed, vacancies=4)
+        return _params(s, name, math.sqrt(5.0), 0.01, lno=True, lambda_th=1e-3, k_min=2, k_max=6)
+    if name == "fcc256":
+        # bulk fcc 4x4x4 cells, periodic, config-2 recipe (no vacancies): the metal of the
+        # error-versus-cluster-radius sweep (box half-width 2.83 d_NN > the largest swept r_L)
+        s = make_system("fcc", (4, 4, 4), (1, 1, 1), 9, _onsite_zero, 1.0, 1.0, SHELLS["fcc"][2] + 1e-6, seed)
         return _params(s, name, math.sqrt(5.0), 0.01, lno=True, lambda_th=1e-3, k_min=2, k_max=6)
     raise ValueError(f"unknown small system {name}")
 
