@@ -14,7 +14,8 @@ It is a plain, slow, step-by-step restatement of the method in the paper's order
                   generalized eigenproblem H c = eps S c, and the atom's spectral weights.
 * ``density``  -- common chemical potential by bisection on the electron count (Eq. 13, 16,
                   Sec. II.C step (iv)), density-matrix rows from the spectral Green function
-                  (Eq. 24 with Eq. 27, Sec. II.C step (v)), energy density rows (Eq. 25 with
+                  (Eq. 24 with Eq. 27, Sec. II.C step (v)), windowed density rows for
+                  energy-window LNOs (Sec. II.B), energy density rows (Eq. 25 with
                   Eq. 27), band energy and electron count.
 * ``exact``    -- the conventional O(N^3) density matrix of the whole system by the Loewdin
                   route (Eq. 2, 8-12), used for the whole-system identity checks.
@@ -29,7 +30,8 @@ counts, closed forms, identities, brute force in 40-digit arithmetic).
 from .regions import plan_regions, Region  # noqa: F401
 from .lno import lambda_matrix, lno_basis, select_rank, all_lnos  # noqa: F401
 from .cluster import cluster_matrices, solve_cluster  # noqa: F401
-from .density import fermi, bisect_mu, density_rows, energy_density_rows, band_energy_and_count  # noqa: F401
+from .density import (fermi, bisect_mu, density_rows, energy_density_rows, band_energy_and_count,  # noqa: F401
+                      window_weights, window_rows)
 from .exact import exact_density, exact_density_blocks  # noqa: F401
 from .driver import density_build  # noqa: F401
 from .scf import mulliken, potential, reference_populations, scf_loop  # noqa: F401

@@ -11,6 +11,10 @@ Readings where the text is open (the paper defers the mu search to earlier work)
   after 200 halvings; mu = (lo + hi)/2;
 * D is the per-spin density matrix: row block (i, j) comes from cluster i only, for every j
   in the overlap pattern of i (Sec. II.C); it is not symmetrised.
+* energy window (Sec. II.B: the projector may select another energy window than the occupied
+  states): the smooth box w(eps) = f((eps - e_hi)/kT) - f((eps - e_lo)/kT), the states
+  between e_lo and e_hi with Fermi-Dirac edges of width kT; its rows W_ij = C_i diag(w) C_j^T
+  take the place of the density for the LNOs.
 """
 from __future__ import annotations
 
@@ -55,6 +59,17 @@ def density_rows(rows_center, rows, eps, mu, kT):
     """Eq. 24 with Eq. 27: D_{ij} = C_i diag(f) C_j^T for every j in ``rows``."""
     f = fermi((eps - mu) / kT)
     ci = rows_center * f[None, :]
+    return {j: ci @ cj.T for j, cj in rows.items()}
+
+
+def window_weights(eps, e_lo, e_hi, kT):
+    """The energy window of the projector: f((eps - e_hi)/kT) - f((eps - e_lo)/kT)."""
+    return fermi((eps - e_hi) / kT) - fermi((eps - e_lo) / kT)
+
+
+def window_rows(rows_center, rows, eps, e_lo, e_hi, kT):
+    """Windowed density rows W_ij = C_i diag(w) C_j^T for every j in ``rows``."""
+    ci = rows_center * window_weights(eps, e_lo, e_hi, kT)[None, :]
     return {j: ci @ cj.T for j, cj in rows.items()}
 
 

@@ -19,7 +19,8 @@ import numpy as np
 from .regions import plan_regions
 from .lno import all_lnos
 from .cluster import solve_cluster
-from .density import bisect_mu, density_rows, energy_density_rows, band_energy_and_count
+from .density import (bisect_mu, density_rows, energy_density_rows, band_energy_and_count, window_rows,
+                      window_weights)
 
 _G = {}
 
@@ -42,6 +43,8 @@ def _solve(i):
         out["D"] = density_rows(ci, out["rows"], out["eps"], mu, kT)
         if _G.get("energy"):
             out["E"] = energy_density_rows(ci, out["rows"], out["eps"], mu, kT)
+        if _G.get("window") is not None:
+            out["W"] = window_rows(ci, out["rows"], out["eps"], *_G["window"])
         del out["rows"]
     return i, out
 
@@ -59,7 +62,7 @@ def default_workers():
 
 
 def density_build(sysd, dprev=None, fixed_rank=None, mu=None, clusters=None, workers=None,
-                  lno=None, regions=None, verbose=False, energy=False):
+                  lno=None, regions=None, verbose=False, energy=False, window=None):
     """One density build.
 
     dprev: previous density matrix (BSR values) for the LNOs; None or lno=False gives plain
@@ -68,7 +71,9 @@ def density_build(sysd, dprev=None, fixed_rank=None, mu=None, clusters=None, wor
     these atoms (needs mu for density rows).  Returns a dict with D (BSR values, rows of
     the computed clusters), mu, e_band, n_e, spectra {i: (eps, w)}, ranks, us, regions,
     dims, iters and timings.  energy: also the energy density rows (Eq. 25) as E and
-    tr_es = g Tr(E S).
+    tr_es = g Tr(E S).  window: (e_lo, e_hi, kT) -- also the windowed density rows as W,
+    tr_ws = g Tr(W S) and window_count = g sum_i sum_mu w(eps) w_mu (the projector of
+    Sec. II.B with another energy window).
     """
     t0 = time.time()
     kT = sysd["kT"]
@@ -92,7 +97,7 @@ def density_build(sysd, dprev=None, fixed_rank=None, mu=None, clusters=None, wor
     est = est / max(1, min(len(idx), 8)) * len(idx)
     keep_rows = est < 3e9
     _G.update(sys=sysd, regions=regions, us=us, ranks=ranks, keep_rows=keep_rows and mu is None,
-              mu=mu, kT=kT, energy=energy)
+              mu=mu, kT=kT, energy=energy, window=window)
     res = dict(_map(_solve, idx, workers))
     t_solve = time.time()
     spectra = {i: (res[i]["eps"], res[i]["w"]) for i in idx}
@@ -107,6 +112,8 @@ def density_build(sysd, dprev=None, fixed_rank=None, mu=None, clusters=None, wor
                 res[i]["D"] = density_rows(r["rows"][i], r["rows"], r["eps"], mu, kT)
                 if energy:
                     res[i]["E"] = energy_density_rows(r["rows"][i], r["rows"], r["eps"], mu, kT)
+                if window is not None:
+                    res[i]["W"] = window_rows(r["rows"][i], r["rows"], r["eps"], *window)
         else:
             _G.update(mu=mu)
             res2 = dict(_map(_solve, idx, workers))
@@ -114,6 +121,8 @@ def density_build(sysd, dprev=None, fixed_rank=None, mu=None, clusters=None, wor
                 res[i]["D"] = res2[i]["D"]
                 if energy:
                     res[i]["E"] = res2[i]["E"]
+                if window is not None:
+                    res[i]["W"] = res2[i]["W"]
     t_mu = time.time()
     row_ptr, col, blk_off, n_orb = sysd["row_ptr"], sysd["col"], sysd["blk_off"], sysd["n_orb"]
 
@@ -136,6 +145,11 @@ def density_build(sysd, dprev=None, fixed_rank=None, mu=None, clusters=None, wor
     if energy:
         out["E"] = assemble("E")
         out["tr_es"] = g * float(np.dot(out["E"], sysd["S"]))
+    if window is not None:
+        out["W"] = assemble("W")
+        out["tr_ws"] = g * float(np.dot(out["W"], sysd["S"]))
+        out["window_count"] = g * sum(float(np.sum(window_weights(spectra[i][0], *window) * spectra[i][1]))
+                                      for i in idx)
     if verbose:
         print(f"[oracle] {sysd.get('name')} clusters={len(idx)} mu={mu:.12f} e_band={e_band:.10f} "
               f"times={out['times']}", flush=True)
