@@ -151,6 +151,18 @@ ldc_status ldc_density_at(ldc_plan_t plan, double mu, double kT, double *d_D_out
  * since the last ldc_solve. */
 ldc_status ldc_energy_density(ldc_plan_t plan, double *d_E_out, double *tr_es_out);
 
+/* Energy-window density rows (Sec. II.B: the projector that defines Lambda may select another
+ * energy window than the occupied states, e.g. bands near the Fermi level):
+ *   W_{i alpha, j beta} = sum_mu w(eps) c_{i alpha,mu} c_{j beta,mu},
+ *   w(eps) = f((eps - e_hi)/kT) - f((eps - e_lo)/kT)   (f the Fermi function: a smooth box),
+ * for every j in the pattern row of i, written to d_W_out (same layout as S), from the spectra
+ * and tracked projections of the last ldc_solve (no chemical potential needed).  Passing d_W_out
+ * to ldc_lno as the previous density gives energy-window LNOs.  tr_ws_out (host, may be NULL):
+ * g Tr(W S), the window's state count g sum_i sum_mu w(eps) w_mu; when given, the call
+ * synchronizes.  LDC_ERR_ARG unless e_lo < e_hi and kT > 0; LDC_ERR_STATE before ldc_solve. */
+ldc_status ldc_window_density(ldc_plan_t plan, double e_lo, double e_hi, double kT, double *d_W_out,
+                              double *tr_ws_out);
+
 /* Toy self-consistent loop (Sec. II.C step (i): the LNOs are recomputed from the previous SCF
  * step's density at every step, so that they become self-consistent).  A step is
  *   ldc_potential (H from H0 and v)  ->  ldc_lno (from the previous D)  ->  ldc_solve  ->

@@ -81,6 +81,7 @@ def load():
         "ldc_density": (c_int, [c_void_p, c_double, c_double, c_void_p, P_double, P_double, P_double]),
         "ldc_density_at": (c_int, [c_void_p, c_double, c_double, c_void_p, P_double, P_double]),
         "ldc_energy_density": (c_int, [c_void_p, c_void_p, P_double]),
+        "ldc_window_density": (c_int, [c_void_p, c_double, c_double, c_double, c_void_p, P_double]),
         "ldc_mulliken": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
         "ldc_potential": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
         "ldc_scf_mix": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_double, c_void_p, P_double]),
@@ -220,6 +221,14 @@ class Plan:
         Returns g Tr(E S)."""
         tr = c_double()
         self._check(self._lib.ldc_energy_density(self._h, _ptr(E_out), ctypes.byref(tr)))
+        return tr.value
+
+    def window_density(self, e_lo, e_hi, kT, W_out):
+        """ldc_window_density: energy-window density rows over (e_lo, e_hi) with edge width kT into
+        W_out.  Returns g Tr(W S)."""
+        tr = c_double()
+        self._check(self._lib.ldc_window_density(self._h, float(e_lo), float(e_hi), float(kT), _ptr(W_out),
+                                                 ctypes.byref(tr)))
         return tr.value
 
     def mulliken(self, D, S, q_out):

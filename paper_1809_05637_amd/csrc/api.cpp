@@ -483,7 +483,7 @@ ldc_status ldc_density(ldc_plan_t plan, double n_electrons, double kT, double *d
   }
   stage_end(p, 9);
   stage_begin(p, 10);
-  ldc::launch_density(p, 0, d_D_out, p.last_H, p.last_S);
+  ldc::launch_density(p, ldc::kRowsDensity, d_D_out, p.last_H, p.last_S);
   stage_end(p, 10);
   HIPCHK(hipGetLastError());
   ldc_status s = finish_density(p, g, mu_out, e_band_out, n_e_out);
@@ -509,7 +509,7 @@ ldc_status ldc_density_at(ldc_plan_t plan, double mu, double kT, double *d_D_out
   st[7] = g;
   st[8] = mu;
   HIPCHK(hipMemcpyAsync(p.d_mu, st, sizeof(st), hipMemcpyHostToDevice, p.stream));
-  ldc::launch_density(p, 0, d_D_out, p.last_H, p.last_S);
+  ldc::launch_density(p, ldc::kRowsDensity, d_D_out, p.last_H, p.last_S);
   HIPCHK(hipGetLastError());
   return finish_density(p, g, nullptr, e_band_out, n_e_out);
 }
@@ -522,7 +522,7 @@ ldc_status ldc_energy_density(ldc_plan_t plan, double *d_E_out, double *tr_es_ou
     return LDC_ERR_STATE;
   }
   const double g = p.opt.spin_g > 0 ? p.opt.spin_g : 2;
-  ldc::launch_density(p, 1, d_E_out, p.last_H, p.last_S);
+  ldc::launch_density(p, ldc::kRowsEnergy, d_E_out, p.last_H, p.last_S);
   HIPCHK(hipGetLastError());
   if (!tr_es_out) return LDC_OK;
   ldc_status s = check_status(p);
@@ -530,6 +530,27 @@ ldc_status ldc_energy_density(ldc_plan_t plan, double *d_E_out, double *tr_es_ou
   double st[32];
   HIPCHK(hipMemcpy(st, p.d_mu, sizeof(st), hipMemcpyDeviceToHost));
   *tr_es_out = g * st[19];
+  return LDC_OK;
+}
+
+ldc_status ldc_window_density(ldc_plan_t plan, double e_lo, double e_hi, double kT, double *d_W_out,
+                              double *tr_ws_out) {
+  if (!plan || !d_W_out) return LDC_ERR_ARG;
+  if (!(e_lo < e_hi) || !(kT > 0.0)) return LDC_ERR_ARG;
+  Plan &p = plan->p;
+  if (!p.solved) {
+    p.msg = "ldc_window_density called before ldc_solve";
+    return LDC_ERR_STATE;
+  }
+  const double g = p.opt.spin_g > 0 ? p.opt.spin_g : 2;
+  ldc::launch_density(p, ldc::kRowsWindow, d_W_out, p.last_H, p.last_S, e_lo, e_hi, kT);
+  HIPCHK(hipGetLastError());
+  if (!tr_ws_out) return LDC_OK;
+  ldc_status s = check_status(p);
+  if (s != LDC_OK) return s;
+  double st[32];
+  HIPCHK(hipMemcpy(st, p.d_mu, sizeof(st), hipMemcpyDeviceToHost));
+  *tr_ws_out = g * st[21];
   return LDC_OK;
 }
 

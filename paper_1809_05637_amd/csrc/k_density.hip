@@ -100,10 +100,12 @@ __global__ void mu_finalize_kernel(int mode, int nparts, double *__restrict__ st
   if (hi - lo <= 4e-16 * fmax(1.0, fabs(mid)) || state[MU_IT] >= 200.0) state[MU_DONE] = 1.0;
 }
 
-// Density rows (Eq. 24 with Eq. 27, weights f) or energy density rows (Eq. 25 with Eq. 27,
-// weights f eps; energy != 0) of every cluster at mu = state[MU_MU].
+// Rows of every cluster at mu = state[MU_MU] with weights by mode: density rows (Eq. 24 with
+// Eq. 27, weights f), energy density rows (Eq. 25 with Eq. 27, weights f eps), or windowed
+// density rows for energy-window LNOs (Sec. II.B: the projector over another energy window,
+// weights f((eps - w_hi)/w_kT) - f((eps - w_lo)/w_kT)).
 __global__ void __launch_bounds__(256, 2) density_kernel(
-    int energy, int n_clusters, const int *__restrict__ order, double *__restrict__ mat, const long long *__restrict__ mat_off,
+    int mode, double w_lo, double w_hi, double w_kT, int n_clusters, const int *__restrict__ order, double *__restrict__ mat, const long long *__restrict__ mat_off,
     double *__restrict__ vec, const long long *__restrict__ vec_off, int *__restrict__ ivec,
     const long long *__restrict__ ivec_off, const int *__restrict__ dmax, const int *__restrict__ dim,
     const int *__restrict__ n_orb, const int *__restrict__ p_rows, const int *__restrict__ mem_ptr,
@@ -135,11 +137,12 @@ __global__ void __launch_bounds__(256, 2) density_kernel(
     const double *tt = cv + vl.tau;
     double *ya = cv + vl.y0, *yb = cv + vl.y1;
     __syncthreads();
-    // y = f o u (energy rows: (f eps) o u)
+    // y = w o u with the mode's weights w
     for (long long e = tid; e < (long long)n * M; e += nthr) {
       const int i = (int)(e / M), a = (int)(e % M);
       const double li = ws.lam[i];
-      const double wt = fermi((li - mu) / kT) * (energy ? li : 1.0);
+      const double wt = mode == kRowsWindow ? fermi((li - w_hi) / w_kT) - fermi((li - w_lo) / w_kT)
+                                            : fermi((li - mu) / kT) * (mode == kRowsEnergy ? li : 1.0);
       ya[(long long)i * kMaxOrb + a] = wt * ws.G0[(long long)i * kTrack + a];
     }
     __syncthreads();
@@ -234,14 +237,16 @@ void launch_mu_step(Plan &p, double, double, double) {
                      p.d_status);
 }
 
-void launch_density(Plan &p, int energy, double *d_D, const double *d_H, const double *d_S) {
+void launch_density(Plan &p, int mode, double *d_D, const double *d_H, const double *d_S, double w_lo, double w_hi,
+                    double w_kT) {
   double *cl_partial = p.d_partial + 4 * p.workgroups;
-  hipLaunchKernelGGL(density_kernel, dim3(p.workgroups), dim3(kWG), 0, p.stream, energy, p.n_atoms, p.d_order, p.d_mat,
+  hipLaunchKernelGGL(density_kernel, dim3(p.workgroups), dim3(kWG), 0, p.stream, mode, w_lo, w_hi, w_kT, p.n_atoms,
+                     p.d_order, p.d_mat,
                      p.d_mat_off, p.d_vec, p.d_vec_off, p.d_ivec, p.d_ivec_off, p.d_dmax, p.d_dim, p.d_n_orb,
                      p.d_p_rows, p.d_mem_ptr, p.d_mem_atom, p.d_fna_ptr, p.d_fna_blk, p.d_blk_off, p.d_mu, d_H, d_S,
                      d_D, cl_partial);
   hipLaunchKernelGGL(sum_pairs_kernel, dim3(1), dim3(kWG), 0, p.stream, p.n_atoms, cl_partial,
-                     p.d_mu + (energy ? 18 : 16));
+                     p.d_mu + (mode == kRowsWindow ? 20 : (mode == kRowsEnergy ? 18 : 16)));
 }
 
 }  // namespace ldc

@@ -168,9 +168,12 @@ void launch_stedc(Plan &p);
 void launch_mu_init(Plan &p, double kT);
 void launch_mu_step(Plan &p, double n_electrons, double kT, double g);
 void launch_mu_fixed(Plan &p, double mu);
-// energy = 0: density rows (sums of D.H and D.S to state[16..17]); 1: energy density rows
-// (sums of E.H and E.S to state[18..19]); at mu = state[MU_MU], kT = state[MU_KT].
-void launch_density(Plan &p, int energy, double *d_D, const double *d_H, const double *d_S);
+// Row modes of launch_density: density rows (sums of D.H and D.S to state[16..17]), energy
+// density rows (E.H, E.S to state[18..19]), both at mu = state[MU_MU], kT = state[MU_KT]; or
+// windowed density rows over (w_lo, w_hi) with edge width w_kT (W.H, W.S to state[20..21]).
+enum { kRowsDensity = 0, kRowsEnergy = 1, kRowsWindow = 2 };
+void launch_density(Plan &p, int mode, double *d_D, const double *d_H, const double *d_S, double w_lo = 0.0,
+                    double w_hi = 0.0, double w_kT = 1.0);
 // toy SCF loop: Mulliken populations, potential on H0, linear mixing (residual to d_res[0])
 void launch_mulliken(Plan &p, const double *d_D, const double *d_S, double *d_q, double g);
 void launch_potential(Plan &p, const double *d_H0, const double *d_S, const double *d_v, double *d_H);
