@@ -290,7 +290,7 @@ ldc_status ldc_plan_create(ldc_plan_t *out, int n_atoms, const double *pos, cons
   TRY(dev_alloc(p, &p.d_lambda, (size_t)n_atoms * ldc::kMaxOrb * ldc::kMaxOrb));
   TRY(dev_alloc(p, &p.d_fixed, (size_t)n_atoms));
   TRY(dev_alloc(p, &p.d_mu, 32));
-  TRY(dev_alloc(p, &p.d_partial, (size_t)(4 * p.workgroups + 2 * n_atoms)));
+  TRY(dev_alloc(p, &p.d_partial, (size_t)(16 * p.workgroups + 2 * n_atoms)));  // mu tree partials, cluster pairs
   TRY(dev_alloc(p, &p.d_counter, 4));
   TRY(dev_alloc(p, &p.d_status, 1));
 #undef TRY
@@ -473,7 +473,7 @@ ldc_status ldc_density(ldc_plan_t plan, double n_electrons, double kT, double *d
   ldc::launch_mu_init(p, kT);
   int iters = 0;
   while (true) {
-    for (int q = 0; q < 64; ++q) ldc::launch_mu_step(p, n_electrons, kT, g);
+    for (int q = 0; q < 64 / ldc::kMuLevels; ++q) ldc::launch_mu_step(p, n_electrons, kT, g);
     iters += 64;
     HIPCHK(hipGetLastError());
     double chk[32];

@@ -91,6 +91,11 @@ __device__ inline double rcp_nr(double x) {
 
 // Fermi-Dirac occupation f(x) = 1/(1+e^x), evaluated as (1 - tanh(x/2))/2.
 __device__ inline double fermi(double x) { return 0.5 * (1.0 - tanh(0.5 * x)); }
+// The same values without the tanh far from the step: for |x| > 80, tanh(x / 2) rounds to +-1
+// in double precision (1 - tanh(40) < 1e-34), so f is exactly 0 or 1 there.
+__device__ inline double fermi_fast(double x) {
+  return x > 80.0 ? 0.0 : (x < -80.0 ? 1.0 : 0.5 * (1.0 - tanh(0.5 * x)));
+}
 
 // Per-cluster workspace pointers.
 struct ClusterWs {

@@ -3,7 +3,9 @@
 // N(mu) = g sum_i sum_mu f((eps_mu - mu)/kT) w_mu is evaluated by a grid of workgroups
 // (one partial per workgroup, fixed cluster assignment) and combined in order by a
 // one-workgroup kernel that also performs the bisection update, so every run takes the
-// same decisions.  Density rows of atom i: with C = L^{-T} Q Z the cluster eigenvectors,
+// same decisions.  One launch pair advances the bisection by kMuLevels halvings: the grid
+// evaluates N at every node of the next kMuLevels levels of the bisection tree (each node the
+// midpoint the halving rule would form on that path), and the combine walks the tree.  Density rows of atom i: with C = L^{-T} Q Z the cluster eigenvectors,
 //   rho^(i)(:, i) = C f C_i^T = L^{-T} Q Z (f o u),  u = Z^T Q^T L^{-1} E_i = C_i^T,
 // so only the tracked u, the merge records (Z y), the stored reflectors (Q r) and the
 // trailing rows of L (P = F_i placed last) are needed.
@@ -19,6 +21,10 @@ static_assert(4 * kMaxDimTri + (kMaxDimTri + 1) / 2 + kApplyChunk * kMaxOrb <= k
 // state layout of Plan::d_mu
 enum { MU_LO = 0, MU_HI, MU_DONE, MU_IT, MU_SUMW, MU_NE, MU_KT, MU_G, MU_MU, MU_BAD };
 
+// the tree's node count and the per-workgroup partial stride (kMuLevels halvings per launch pair)
+constexpr int kMuNodes = (1 << kMuLevels) - 1, kMuStride = 16;
+static_assert(kMuNodes < kMuStride, "tree partials fit the stride");
+
 __global__ void __launch_bounds__(256) mu_partial_kernel(int mode, int n_clusters, const double *__restrict__ vec,
                                                          const long long *__restrict__ vec_off,
                                                          const int *__restrict__ dmax, const int *__restrict__ dim,
@@ -27,37 +33,59 @@ __global__ void __launch_bounds__(256) mu_partial_kernel(int mode, int n_cluster
   __shared__ double red[8];
   if (mode == 1 && state[MU_DONE] != 0.0) return;
   const double kT = state[MU_KT];
-  const double mid = 0.5 * (state[MU_LO] + state[MU_HI]);
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   if (mode == 0) {
-    a0 = 1e300;
-    a1 = -1e300;
+    double a0 = 1e300, a1 = -1e300, a2 = 0.0;
+    for (int c = blockIdx.x; c < n_clusters; c += gridDim.x) {
+      const VecLayout vl = VecLayout::make(dmax[c]);
+      const double *lam = vec + vec_off[c] + vl.lam;
+      const double *w = vec + vec_off[c] + vl.w;
+      const int n = dim[c];
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        a0 = fmin(a0, lam[i]);
+        a1 = fmax(a1, lam[i]);
+        a2 += w[i];
+      }
+    }
+    const double s = block_sum(a2, red);
+    const double mn = -block_max(-a0, red);
+    const double mx = block_max(a1, red);
+    if (threadIdx.x == 0) {
+      partial[blockIdx.x * kMuStride + 0] = mn;
+      partial[blockIdx.x * kMuStride + 1] = mx;
+      partial[blockIdx.x * kMuStride + 2] = s;
+    }
+    return;
   }
+  // the tree's nodes in heap order: node k covers (nl, nh), its children 2k + 1 (hi = mid) and
+  // 2k + 2 (lo = mid), each evaluated at its midpoint
+  double nl[kMuNodes], nh[kMuNodes], m[kMuNodes], acc[kMuNodes];
+  nl[0] = state[MU_LO];
+  nh[0] = state[MU_HI];
+  m[0] = 0.5 * (nl[0] + nh[0]);
+#pragma unroll
+  for (int k = 1; k < kMuNodes; ++k) {
+    const int p = (k - 1) / 2;
+    nl[k] = (k == 2 * p + 1) ? nl[p] : m[p];
+    nh[k] = (k == 2 * p + 1) ? m[p] : nh[p];
+    m[k] = 0.5 * (nl[k] + nh[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < kMuNodes; ++k) acc[k] = 0.0;
   for (int c = blockIdx.x; c < n_clusters; c += gridDim.x) {
     const VecLayout vl = VecLayout::make(dmax[c]);
     const double *lam = vec + vec_off[c] + vl.lam;
     const double *w = vec + vec_off[c] + vl.w;
     const int n = dim[c];
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      if (mode == 0) {
-        a0 = fmin(a0, lam[i]);
-        a1 = fmax(a1, lam[i]);
-        a2 += w[i];
-      } else {
-        a2 += fermi((lam[i] - mid) / kT) * w[i];
-      }
+      const double li = lam[i], wi = w[i];
+#pragma unroll
+      for (int k = 0; k < kMuNodes; ++k) acc[k] += fermi_fast((li - m[k]) / kT) * wi;
     }
   }
-  const double s = block_sum(a2, red);
-  double mn = 0.0, mx = 0.0;
-  if (mode == 0) {
-    mn = -block_max(-a0, red);
-    mx = block_max(a1, red);
-  }
-  if (threadIdx.x == 0) {
-    partial[blockIdx.x * 4 + 0] = mn;
-    partial[blockIdx.x * 4 + 1] = mx;
-    partial[blockIdx.x * 4 + 2] = s;
+#pragma unroll
+  for (int k = 0; k < kMuNodes; ++k) {
+    const double s = block_sum(acc[k], red);
+    if (threadIdx.x == 0) partial[blockIdx.x * kMuStride + k] = s;
   }
 }
 
@@ -65,15 +93,15 @@ __global__ void mu_finalize_kernel(int mode, int nparts, double *__restrict__ st
                                    DevStatus *st) {
   if (threadIdx.x != 0) return;
   if (mode == 1 && state[MU_DONE] != 0.0) return;
-  double s = 0.0, mn = 1e300, mx = -1e300;
-  for (int b = 0; b < nparts; ++b) {
-    s += partial[b * 4 + 2];
-    mn = fmin(mn, partial[b * 4 + 0]);
-    mx = fmax(mx, partial[b * 4 + 1]);
-  }
   const double kT = state[MU_KT], g = state[MU_G], ne = state[MU_NE];
   double lo, hi;
   if (mode == 0) {
+    double s = 0.0, mn = 1e300, mx = -1e300;
+    for (int b = 0; b < nparts; ++b) {
+      s += partial[b * kMuStride + 2];
+      mn = fmin(mn, partial[b * kMuStride + 0]);
+      mx = fmax(mx, partial[b * kMuStride + 1]);
+    }
     lo = mn - 40.0 * kT;
     hi = mx + 40.0 * kT;
     state[MU_SUMW] = s;
@@ -85,19 +113,38 @@ __global__ void mu_finalize_kernel(int mode, int nparts, double *__restrict__ st
       state[MU_DONE] = 1.0;
       report(st, LDC_ERR_MU_BRACKET, -1);
     }
+    state[MU_LO] = lo;
+    state[MU_HI] = hi;
+    const double mid = 0.5 * (lo + hi);
+    state[MU_MU] = mid;
+    if (hi - lo <= 4e-16 * fmax(1.0, fabs(mid)) || state[MU_IT] >= 200.0) state[MU_DONE] = 1.0;
   } else {
+    // kMuLevels halvings down the evaluated tree, each with the stopping test
     lo = state[MU_LO];
     hi = state[MU_HI];
-    const double mid = 0.5 * (lo + hi);
-    if (g * s < ne) lo = mid;
-    else hi = mid;
-    state[MU_IT] += 1.0;
+    int node = 0;
+    for (int level = 0; level < kMuLevels; ++level) {
+      double s = 0.0;
+      for (int b = 0; b < nparts; ++b) s += partial[b * kMuStride + node];
+      const double mid = 0.5 * (lo + hi);
+      if (g * s < ne) {
+        lo = mid;
+        node = 2 * node + 2;
+      } else {
+        hi = mid;
+        node = 2 * node + 1;
+      }
+      state[MU_IT] += 1.0;
+      const double mid2 = 0.5 * (lo + hi);
+      if (hi - lo <= 4e-16 * fmax(1.0, fabs(mid2)) || state[MU_IT] >= 200.0) {
+        state[MU_DONE] = 1.0;
+        break;
+      }
+    }
+    state[MU_LO] = lo;
+    state[MU_HI] = hi;
+    state[MU_MU] = 0.5 * (lo + hi);
   }
-  state[MU_LO] = lo;
-  state[MU_HI] = hi;
-  const double mid = 0.5 * (lo + hi);
-  state[MU_MU] = mid;
-  if (hi - lo <= 4e-16 * fmax(1.0, fabs(mid)) || state[MU_IT] >= 200.0) state[MU_DONE] = 1.0;
 }
 
 // Rows of every cluster at mu = state[MU_MU] with weights by mode: density rows (Eq. 24 with
@@ -239,7 +286,7 @@ void launch_mu_step(Plan &p, double, double, double) {
 
 void launch_density(Plan &p, int mode, double *d_D, const double *d_H, const double *d_S, double w_lo, double w_hi,
                     double w_kT) {
-  double *cl_partial = p.d_partial + 4 * p.workgroups;
+  double *cl_partial = p.d_partial + kMuStride * p.workgroups;
   hipLaunchKernelGGL(density_kernel, dim3(p.workgroups), dim3(kWG), 0, p.stream, mode, w_lo, w_hi, w_kT, p.n_atoms,
                      p.d_order, p.d_mat,
                      p.d_mat_off, p.d_vec, p.d_vec_off, p.d_ivec, p.d_ivec_off, p.d_dmax, p.d_dim, p.d_n_orb,

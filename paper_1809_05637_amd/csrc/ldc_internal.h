@@ -165,6 +165,8 @@ void launch_sy2sb(Plan &p);
 void launch_sb2st(Plan &p);
 void launch_q2x(Plan &p);
 void launch_stedc(Plan &p);
+// halvings of the chemical-potential bisection per launch pair (a tree of 2^k - 1 points)
+constexpr int kMuLevels = 2;
 void launch_mu_init(Plan &p, double kT);
 void launch_mu_step(Plan &p, double n_electrons, double kT, double g);
 void launch_mu_fixed(Plan &p, double mu);
