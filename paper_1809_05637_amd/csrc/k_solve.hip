@@ -82,8 +82,8 @@ __global__ void __launch_bounds__(256) lno_blocks_kernel(int n_atoms, const int 
 
 // ---------------------------------------------------------------------------------------
 // (a)+(c) gather: dense column-major H^(i), S^(i) (leading dimension = cluster dimension n),
-// written column block by column block, every element once (zeros included), each column in
-// full.  The (a, b) block of the cluster matrix is C_a X_ab C_b with C the LNO contraction of a
+// written column block by column block, every element once (zeros included), each column of
+// H in full and each column of S from its diagonal block down.  The (a, b) block of the cluster matrix is C_a X_ab C_b with C the LNO contraction of a
 // long member (identity otherwise); by the symmetry of H and S it is read as the transpose of
 // the row-b pattern block X_ba or its contraction from lno_blocks_kernel (U_b^T X_ba, X_ba U_a
 // or U_b^T X_ba U_a), whose rows have length d_a either way, so that a column of the cluster
@@ -155,6 +155,9 @@ __global__ void __launch_bounds__(256) gather_kernel(int n_clusters, const int *
         const double *hb = (la || lb) ? lno_blk + (long long)(2 * v) * total : H;
         const double *sb = (la || lb) ? lno_blk + (long long)(2 * v + 1) * total : S;
         const long long src = bo + rr;
+        // S above the diagonal block is never read (the Cholesky reads the lower triangle and
+        // the standard form clears the strict upper one first): not loaded, not written
+        const bool s_rows = r >= cb;
         double *hc = Hc + (long long)cb * n + r, *sc = Sc + (long long)cb * n + r;
         for (int q0 = 0; q0 < db; q0 += 4) {
           double hv[4], sv[4];
@@ -162,13 +165,13 @@ __global__ void __launch_bounds__(256) gather_kernel(int n_clusters, const int *
           for (int u = 0; u < 4; ++u) {
             const int q = min(q0 + u, db - 1);
             hv[u] = bo >= 0 ? hb[src + (long long)q * da] : 0.0;
-            sv[u] = bo >= 0 ? sb[src + (long long)q * da] : 0.0;
+            sv[u] = (bo >= 0 && s_rows) ? sb[src + (long long)q * da] : 0.0;
           }
 #pragma unroll
           for (int u = 0; u < 4; ++u)
             if (q0 + u < db) {
               hc[(long long)(q0 + u) * n] = hv[u];
-              sc[(long long)(q0 + u) * n] = sv[u];
+              if (s_rows) sc[(long long)(q0 + u) * n] = sv[u];
             }
         }
       }
