@@ -82,8 +82,10 @@ __global__ void __launch_bounds__(256) lno_blocks_kernel(int n_atoms, const int 
 
 // ---------------------------------------------------------------------------------------
 // (a)+(c) gather: dense column-major H^(i), S^(i) (leading dimension = cluster dimension n),
-// written column block by column block, every element once (zeros included), each column of
-// H in full and each column of S from its diagonal block down.  The (a, b) block of the cluster matrix is C_a X_ab C_b with C the LNO contraction of a
+// written column block by column block, every element once (zeros included).  The H slot
+// receives H_L, the lower triangle of H^(i) with half its diagonal and zeros above
+// (H^(i) = H_L + H_L^T; the standard form works from H_L), each column in full; the S slot
+// each column of S^(i) from its diagonal block down.  The (a, b) block of the cluster matrix is C_a X_ab C_b with C the LNO contraction of a
 // long member (identity otherwise); by the symmetry of H and S it is read as the transpose of
 // the row-b pattern block X_ba or its contraction from lno_blocks_kernel (U_b^T X_ba, X_ba U_a
 // or U_b^T X_ba U_a), whose rows have length d_a either way, so that a column of the cluster
@@ -170,7 +172,8 @@ __global__ void __launch_bounds__(256) gather_kernel(int n_clusters, const int *
 #pragma unroll
           for (int u = 0; u < 4; ++u)
             if (q0 + u < db) {
-              hc[(long long)(q0 + u) * n] = hv[u];
+              const int c = cb + q0 + u;
+              hc[(long long)(q0 + u) * n] = r > c ? hv[u] : (r == c ? 0.5 * hv[u] : 0.0);
               if (s_rows) sc[(long long)(q0 + u) * n] = sv[u];
             }
         }
@@ -340,14 +343,21 @@ __global__ void __launch_bounds__(256, 2) potrf_kernel(int n_clusters, const int
   }
 }
 
-// Standard form (Sec. II.C (iii) via Cholesky): with S = L L^T,
-//   A = L^{-1} H L^{-T}.
+// Standard form (Sec. II.C (iii) via Cholesky): with S = L L^T and H = H_L + H_L^T (H_L the lower
+// triangle with half the diagonal, as the gather stores it),
+//   A = L^{-1} H L^{-T} = P L^{-T} + L^{-1} P^T,  P = L^{-1} H_L,
+// with P lower triangular (a product of two lower triangles), so both steps run only over
+// their nonzero K ranges: n^3 / 3 + 2 n^3 / 3 flops instead of n^3 + 2 n^3 / 3 with a full
+// L^{-1} H.
 // 1. L^{-1} in place of L (block columns of 2 NB from the last: B21 <- -L22^{-1} L21 L11^{-1},
 //    L11 <- L11^{-1}); the strictly-upper part of the S slot is cleared first.
-// 2. W = L^{-1} H in place of H, block rows from the last (each block row only needs rows
-//    of H above it and its own, which are still intact), each tile written in place.
-// 3. A = L^{-1} W^T (lower part) in place of W, block rows from the last.
-// All products are MFMA GEMMs that skip the structurally zero part of L^{-1}.  The tracked
+// 2. P = L^{-1} H_L in place of H_L, block rows from the last (a block row needs rows of H_L
+//    above it and its own, still intact), each tile's K range from its first column (H_L is
+//    lower) to the end of its block row (L^{-1} is lower).
+// 3. A = P L^{-T} + L^{-1} P^T (lower part) in place of P, block rows from the last and tiles
+//    right to left: tile (I, J) reads P of block row I only in columns up to its own, and
+//    rows of P above block row I; both products run over K up to the tile's last column.
+// All products are MFMA GEMMs.  The tracked
 // columns of the tridiagonal solver are set up here: X_u = L^{-1} E_i (the last M columns of
 // L^{-1}) and X_v = L^T E_i (the last M rows of L, taken before the inversion).
 __global__ void __launch_bounds__(256, 2) sygst_kernel(int n_clusters, const int *__restrict__ order,
@@ -452,20 +462,20 @@ __global__ void __launch_bounds__(256, 2) sygst_kernel(int n_clusters, const int
       const int r = e % M, al = e / M;
       X[(long long)(b0 + r) * kTrack + al] = (r >= al) ? L[(long long)(b0 + al) * ld + b0 + r] : 0.0;
     }
-    // 2. W = L^{-1} H in place, block rows of GT from the last; full MFMA tiles, K limited to
-    //    the nonzero part of the block row of L^{-1}.  A tile of block row b reads only its own
-    //    columns of H (rows 0..r1, its own rows included) and is written after its last read.
+    // 2. P = L^{-1} H_L in place, block rows of GT from the last; a tile of block row b reads
+    //    only its own columns of H_L (rows 0..r1, its own rows included) and is written after its
+    //    last read.  P is lower triangular (its diagonal tile's upper part comes out zero).
     const int nblk2 = (n + GT - 1) / GT;
     for (int bj = nblk2 - 1; bj >= 0; --bj) {
       const int r0 = bj * GT, jb = min(GT, n - r0), r1 = r0 + jb;
-      wg_gemm<G_OVERWRITE | G_PLUS, 64, 128>(H + r0, ld, L + r0, ld, H, ld, jb, n, r1, gl, r0);
+      wg_gemm<G_OVERWRITE | G_PLUS | G_B_LOWER, 64, 128>(H + r0, ld, L + r0, ld, H, ld, jb, r1, r1, gl, r0);
     }
-    // 3. A = L^{-1} W^T in place, lower part: block row b of A = L^{-1}(rows b, cols 0:r1)
-    //    W(0:r1, 0:r1)^T.  Only the diagonal tile reads W's rows b, so the tiles run from the
-    //    last (diagonal) one.
+    // 3. A = P L^{-T} + L^{-1} P^T in place, lower part: block row b of A from L^{-1} and P of
+    //    rows b and of rows 0:r1, in one pass of both products per tile.
     for (int bj = nblk2 - 1; bj >= 0; --bj) {
       const int r0 = bj * GT, jb = min(GT, n - r0), r1 = r0 + jb;
-      wg_gemm<G_TRANS_B | G_OVERWRITE | G_PLUS | G_REV, 64, 128>(H + r0, ld, L + r0, ld, H, ld, jb, r1, r1, gl, r0);
+      wg_gemm<G_TRANS_B | G_OVERWRITE | G_PLUS | G_REV | G_DUAL, 64, 128>(H + r0, ld, L + r0, ld, H, ld, jb, r1, r1,
+                                                                           gl, -1, 0, H + r0, L);
     }
   }
 }

@@ -32,12 +32,18 @@ enum : unsigned {
   G_PLUS = 256u,      // add instead of subtract: C += A op(B) (G_OVERWRITE: C = A op(B))
   G_REV = 512u,       // tiles from the last to the first
   G_EARLY_C = 1024u,  // fetch C with the tile's first K chunk (short K: more time to arrive)
+  G_B_LOWER = 2048u,  // op(B) is lower triangular (op(B)[kk][c] = 0 for kk < c): a tile's K loop
+                      // starts at its first column
+  G_DUAL = 4096u,     // two products in one pass: A op(B) + A2 op(B2), A2 and B2 laid out like A
+                      // and B; op(B) and op(B2) vanish for kk beyond the tile's last column, so each
+                      // product runs over K < (tile's column end)
 };
 
 // C[m x n] -= A[m x k] * op(B)   (G_OVERWRITE: C = -A op(B); G_PLUS: + instead of -).
 // G_LOWER: the strictly-upper part of diagonal tiles is computed too and must be unused.
 // a_diag >= 0: A is zero above its a_diag-th superdiagonal (A[r][kk] = 0 for kk > r + a_diag),
 // so each tile row only runs over the K range that can be nonzero.
+// G_DUAL: the K loop runs over both products, the second's chunks after the first's.
 // 0 < b_rot < k: the K index of op(B) is rotated, op(B)[kk][c] = op(B')[(kk + b_rot) mod k][c];
 // with A = [V | W] row-major and B = A this forms V W^T + W V^T in one pass.
 // G_A_SYM: A[r][kk] = A_lo[max(r,kk)][min(r,kk)]; a K chunk wholly right of the tile's rows
@@ -55,10 +61,13 @@ enum : unsigned {
 // with the last chunk C is fetched too (with the first under G_EARLY_C; not under G_LATE_C).
 template <unsigned F, int TM = GT, int TN = GT>
 __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const double *B, int ldb, int m, int n, int k,
-                        double *lds, int a_diag = -1, int b_rot = 0) {
+                        double *lds, int a_diag = -1, int b_rot = 0, const double *A2 = nullptr,
+                        const double *B2 = nullptr) {
   constexpr bool TRANS_B = F & G_TRANS_B, LOWER = F & G_LOWER, A_RM = F & G_A_RM, B_RM = F & G_B_RM;
   constexpr bool OVERWRITE = F & G_OVERWRITE, PREFETCH_C = !(F & G_LATE_C), C_RM = F & G_C_RM;
   constexpr bool A_SYM = F & G_A_SYM, PLUS = F & G_PLUS, REV = F & G_REV, EARLY_C = F & G_EARLY_C;
+  constexpr bool B_LOWER = F & G_B_LOWER, DUAL = F & G_DUAL;
+  static_assert(!(DUAL && (A_SYM || B_LOWER)), "the two-product pass takes plain operands");
   static_assert(!(A_SYM && A_RM), "a symmetric A is stored column-major");
   constexpr int KC = (TN == 128) ? GK / 2 : GK;  // K chunk (halved for the wide tiles: fewer registers)
   // wave grid GR x GC (GR = TM / 32 rows of waves), each wave 32 x (16 BN)
@@ -92,7 +101,8 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
     if (A_SYM) return (k0 >= r0 + TM) ? 1 : 0;
     return A_RM ? 1 : 0;
   };
-  auto fetchA = [&](int r0, int k0, int mode, double *ra) {
+  auto fetchA = [&](const double *Ap, int r0, int k0, int mode, double *ra) {
+    const double *Asrc = DUAL ? Ap : A;
 #pragma unroll
     for (int q = 0; q < PERA; ++q) {
       int gr, gk;
@@ -107,15 +117,16 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
       if (gr < m && gk < k) {
         if (A_SYM) {
           const int hi = gr > gk ? gr : gk, lo = gr > gk ? gk : gr;
-          val = A[lo * lda + hi];
+          val = Asrc[lo * lda + hi];
         } else {
-          val = A[gr * a_rs + gk * a_ks];
+          val = Asrc[gr * a_rs + gk * a_ks];
         }
       }
       ra[q] = val;
     }
   };
-  auto fetchB = [&](int c0, int k0, double *rb) {
+  auto fetchB = [&](const double *Bp, int c0, int k0, double *rb) {
+    const double *Bsrc = DUAL ? Bp : B;
 #pragma unroll
     for (int q = 0; q < PERB; ++q) {
       const int gc = c0 + b_e + (B_KFAST ? q * B_STEP : 0);
@@ -125,7 +136,7 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
         gk += b_rot;
         if (gk >= k) gk -= k;
       }
-      rb[q] = in ? B[gc * b_cs + gk * b_ks] : 0.0;
+      rb[q] = in ? Bsrc[gc * b_cs + gk * b_ks] : 0.0;
     }
   };
   auto stage = [&](int mode, const double *ra, const double *rb) {
@@ -152,49 +163,72 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
     return -1;
   };
   auto k_end = [&](int r0) { return (a_diag >= 0) ? min(k, r0 + TM + a_diag) : k; };
+  // a tile's K loop: [k_beg, k_stop); under G_DUAL the first product takes [0, k_half) and the
+  // second [k_half, 2 k_half) (k_half a whole number of chunks)
+  auto k_half = [&](int c0) { return ((min(k, c0 + TN) + KC - 1) / KC) * KC; };
+  auto k_beg = [&](int c0) { return B_LOWER ? c0 : 0; };
+  auto k_stop = [&](int r0, int c0) { return DUAL ? 2 * k_half(c0) : k_end(r0); };
+  // operands and local K index of the chunk starting at k0 of the tile with column start c0
+  auto chunk_src = [&](int c0, int k0, const double *&pa, const double *&pb) -> int {
+    if (DUAL) {
+      const int kh = k_half(c0);
+      if (k0 >= kh) {
+        pa = A2;
+        pb = B2;
+        return k0 - kh;
+      }
+    }
+    pa = A;
+    pb = B;
+    return k0;
+  };
 
   // Software pipeline over (tile, K chunk): the chunk after the one being multiplied is always
   // in flight, including the first chunk of the next tile while the last chunk of this one runs.
   double ra[PERA], rb[PERB];
   int tile = next_tile(0);
   int amode = 0;
+  const double *pa = A, *pb = B;
   if (tile >= 0) {
     const int r0 = (tile_of(tile) / nt) * TM, c0 = (tile_of(tile) % nt) * TN;
-    amode = a_mode_of(r0, 0);
-    if (k_end(r0) > 0) {
-      fetchA(r0, 0, amode, ra);
-      fetchB(c0, 0, rb);
+    if (k_stop(r0, c0) > k_beg(c0)) {
+      const int kk = chunk_src(c0, k_beg(c0), pa, pb);
+      amode = a_mode_of(r0, kk);
+      fetchA(pa, r0, kk, amode, ra);
+      fetchB(pb, c0, kk, rb);
     }
   }
   while (tile >= 0) {
     const int ti = tile_of(tile) / nt, tj = tile_of(tile) % nt;
     const int r0 = ti * TM, c0 = tj * TN;
-    const int kend = k_end(r0);
+    const int kbeg = k_beg(c0), kend = k_stop(r0, c0);
     const int nxt = next_tile(tile + 1);
     const int r0n = (nxt >= 0) ? (tile_of(nxt) / nt) * TM : 0, c0n = (nxt >= 0) ? (tile_of(nxt) % nt) * TN : 0;
-    const bool fetch_next = nxt >= 0 && k_end(r0n) > 0;
+    const bool fetch_next = nxt >= 0 && k_stop(r0n, c0n) > k_beg(c0n);
     ldc_double4 acc[2][BN];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int b = 0; b < BN; ++b) acc[a][b] = ldc_double4{0.0, 0.0, 0.0, 0.0};
     double cold[2][BN][4];
-    for (int k0 = 0; k0 < kend; k0 += KC) {
+    for (int k0 = kbeg; k0 < kend; k0 += KC) {
       __syncthreads();
       stage(amode, ra, rb);
       __syncthreads();
       if (k0 + KC < kend) {
-        amode = a_mode_of(r0, k0 + KC);
-        fetchA(r0, k0 + KC, amode, ra);
-        fetchB(c0, k0 + KC, rb);
+        const int kk = chunk_src(c0, k0 + KC, pa, pb);
+        amode = a_mode_of(r0, kk);
+        fetchA(pa, r0, kk, amode, ra);
+        fetchB(pb, c0, kk, rb);
       } else {
         if (fetch_next) {
-          amode = a_mode_of(r0n, 0);
-          fetchA(r0n, 0, amode, ra);
-          fetchB(c0n, 0, rb);
+          const int kk = chunk_src(c0n, k_beg(c0n), pa, pb);
+          amode = a_mode_of(r0n, kk);
+          fetchA(pa, r0n, kk, amode, ra);
+          fetchB(pb, c0n, kk, rb);
         }
       }
-      if (!OVERWRITE && PREFETCH_C && (EARLY_C ? k0 == 0 : k0 + KC >= kend)) {
+      if (!OVERWRITE && PREFETCH_C && (EARLY_C ? k0 == kbeg : k0 + KC >= kend)) {
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -219,13 +253,14 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
           for (int b = 0; b < BN; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[b], af[a], acc[a][b], 0, 0, 0);
       }
     }
-    if (kend <= 0 && fetch_next) {
-      amode = a_mode_of(r0n, 0);
-      fetchA(r0n, 0, amode, ra);
-      fetchB(c0n, 0, rb);
+    if (kend <= kbeg && fetch_next) {
+      const int kk = chunk_src(c0n, k_beg(c0n), pa, pb);
+      amode = a_mode_of(r0n, kk);
+      fetchA(pa, r0n, kk, amode, ra);
+      fetchB(pb, c0n, kk, rb);
     }
     tile = nxt;
-    if (kend <= 0 && !OVERWRITE) continue;  // nothing to subtract
+    if (kend <= kbeg && !OVERWRITE) continue;  // nothing to subtract
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
       const int gr = r0 + wr * 32 + a * 16 + li;
