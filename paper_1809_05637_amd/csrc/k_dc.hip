@@ -497,7 +497,7 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
   }
 }
 
-__global__ void __launch_bounds__(256) stedc_kernel(int n_clusters, const int *__restrict__ order,
+__global__ void __launch_bounds__(256, 3) stedc_kernel(int n_clusters, const int *__restrict__ order,
                                                     double *__restrict__ vec, const long long *__restrict__ vec_off,
                                                     int *__restrict__ ivec, const long long *__restrict__ ivec_off,
                                                     const int *__restrict__ dmax, const int *__restrict__ dim,
@@ -527,7 +527,9 @@ __global__ void __launch_bounds__(256) stedc_kernel(int n_clusters, const int *_
 
 void launch_stedc(Plan &p) {
   const size_t lds = (size_t)p.max_dim * DcLds::kBytesPerRow + DcLds::kFixedBytes;
-  hipLaunchKernelGGL(stedc_kernel, dim3(p.workgroups), dim3(kWG), lds, p.stream, p.n_atoms, p.d_order, p.d_vec,
+  // three workgroups per CU (at most 168 VGPRs; the LDS of a 711-row cluster is 51 KB): more
+  // waves in flight for the latency-bound merges
+  hipLaunchKernelGGL(stedc_kernel, dim3(3 * p.n_cu), dim3(kWG), lds, p.stream, p.n_atoms, p.d_order, p.d_vec,
                      p.d_vec_off, p.d_ivec, p.d_ivec_off, p.d_dmax, p.d_dim, p.d_n_orb, p.d_status, p.max_dim);
 }
 
