@@ -89,43 +89,65 @@ __global__ void __launch_bounds__(256) mu_partial_kernel(int mode, int n_cluster
   }
 }
 
-__global__ void mu_finalize_kernel(int mode, int nparts, double *__restrict__ state, const double *__restrict__ partial,
-                                   DevStatus *st) {
-  if (threadIdx.x != 0) return;
+// Combines the per-workgroup partials in a fixed order (lane l adds partials l, l + 64, ...,
+// then a fixed DPP tree) and updates the bisection state; one wavefront, every lane takes the
+// same decisions and lane 0 writes the state.
+__global__ void __launch_bounds__(64) mu_finalize_kernel(int mode, int nparts, double *__restrict__ state,
+                                                         const double *__restrict__ partial, DevStatus *st) {
+  const int lane = threadIdx.x;
   if (mode == 1 && state[MU_DONE] != 0.0) return;
   const double kT = state[MU_KT], g = state[MU_G], ne = state[MU_NE];
   double lo, hi;
   if (mode == 0) {
     double s = 0.0, mn = 1e300, mx = -1e300;
-    for (int b = 0; b < nparts; ++b) {
+    for (int b = lane; b < nparts; b += 64) {
       s += partial[b * kMuStride + 2];
       mn = fmin(mn, partial[b * kMuStride + 0]);
       mx = fmax(mx, partial[b * kMuStride + 1]);
     }
+    s = wave_sum(s);
+    mn = -wave_max(-mn);
+    mx = wave_max(mx);
     lo = mn - 40.0 * kT;
     hi = mx + 40.0 * kT;
-    state[MU_SUMW] = s;
-    state[MU_IT] = 0.0;
-    state[MU_DONE] = 0.0;
-    state[MU_BAD] = 0.0;
-    if (!(ne > 0.0 && ne < g * s)) {
-      state[MU_BAD] = 1.0;
-      state[MU_DONE] = 1.0;
-      report(st, LDC_ERR_MU_BRACKET, -1);
-    }
-    state[MU_LO] = lo;
-    state[MU_HI] = hi;
+    const bool bad = !(ne > 0.0 && ne < g * s);
     const double mid = 0.5 * (lo + hi);
-    state[MU_MU] = mid;
-    if (hi - lo <= 4e-16 * fmax(1.0, fabs(mid)) || state[MU_IT] >= 200.0) state[MU_DONE] = 1.0;
+    if (lane == 0) {
+      state[MU_SUMW] = s;
+      state[MU_IT] = 0.0;
+      state[MU_DONE] = 0.0;
+      state[MU_BAD] = 0.0;
+      if (bad) {
+        state[MU_BAD] = 1.0;
+        state[MU_DONE] = 1.0;
+        report(st, LDC_ERR_MU_BRACKET, -1);
+      }
+      state[MU_LO] = lo;
+      state[MU_HI] = hi;
+      state[MU_MU] = mid;
+      if (hi - lo <= 4e-16 * fmax(1.0, fabs(mid))) state[MU_DONE] = 1.0;
+    }
   } else {
-    // kMuLevels halvings down the evaluated tree, each with the stopping test
+    // N at every node of the evaluated tree, then kMuLevels halvings down it, each with the
+    // stopping test
+    double sn[kMuNodes];
+#pragma unroll
+    for (int k = 0; k < kMuNodes; ++k) sn[k] = 0.0;
+    for (int b = lane; b < nparts; b += 64) {
+#pragma unroll
+      for (int k = 0; k < kMuNodes; ++k) sn[k] += partial[b * kMuStride + k];
+    }
+#pragma unroll
+    for (int k = 0; k < kMuNodes; ++k) sn[k] = wave_sum(sn[k]);
     lo = state[MU_LO];
     hi = state[MU_HI];
+    double it = state[MU_IT];
+    bool done = false;
     int node = 0;
     for (int level = 0; level < kMuLevels; ++level) {
       double s = 0.0;
-      for (int b = 0; b < nparts; ++b) s += partial[b * kMuStride + node];
+#pragma unroll
+      for (int k = 0; k < kMuNodes; ++k) s = (k == node) ? sn[k] : s;
       const double mid = 0.5 * (lo + hi);
       if (g * s < ne) {
         lo = mid;
@@ -134,16 +156,20 @@ __global__ void mu_finalize_kernel(int mode, int nparts, double *__restrict__ st
         hi = mid;
         node = 2 * node + 1;
       }
-      state[MU_IT] += 1.0;
+      it += 1.0;
       const double mid2 = 0.5 * (lo + hi);
-      if (hi - lo <= 4e-16 * fmax(1.0, fabs(mid2)) || state[MU_IT] >= 200.0) {
-        state[MU_DONE] = 1.0;
+      if (hi - lo <= 4e-16 * fmax(1.0, fabs(mid2)) || it >= 200.0) {
+        done = true;
         break;
       }
     }
-    state[MU_LO] = lo;
-    state[MU_HI] = hi;
-    state[MU_MU] = 0.5 * (lo + hi);
+    if (lane == 0) {
+      state[MU_IT] = it;
+      if (done) state[MU_DONE] = 1.0;
+      state[MU_LO] = lo;
+      state[MU_HI] = hi;
+      state[MU_MU] = 0.5 * (lo + hi);
+    }
   }
 }
 
