@@ -223,8 +223,9 @@ def make_system(kind, cells, periodic, n_orb_per_atom, onsite, t0, lam_h, hop_cu
                 s_amp=0.05, lam_s=0.8, vacancies=0, min_s_eig=0.2, a=None):
     """Build one synthetic system.
 
-    kind/cells/periodic: lattice; n_orb_per_atom: orbitals per atom; onsite: callable
-    (rng, sublattice (N,), M) -> (N, M) onsite energies; t0, lam_h: hopping amplitude and
+    kind/cells/periodic: lattice; n_orb_per_atom: orbitals per atom, an int or a sequence
+    tiled over the atoms; onsite: callable (rng, sublattice (N,), M) -> (N, M) onsite energies
+    (M the largest count; atom i uses its first M_i); t0, lam_h: hopping amplitude and
     decay length (blocks scaled by t0*exp(-r/lam_h)); hop_cut: bond cutoff; s_amp, lam_s:
     overlap blocks scaled by s_amp*exp(-r/lam_s) on the same bonds; vacancies: number of
     sites removed, drawn from a second stream (seed + 1).  If the smallest eigenvalue of S
@@ -239,12 +240,15 @@ def make_system(kind, cells, periodic, n_orb_per_atom, onsite, t0, lam_h, hop_cu
         keep[drop] = False
         pos, sub = pos[keep], sub[keep]
     n_atoms = len(pos)
-    n_orb = np.full(n_atoms, n_orb_per_atom, dtype=np.int32)
+    if np.ndim(n_orb_per_atom) == 0:
+        n_orb = np.full(n_atoms, n_orb_per_atom, dtype=np.int32)
+    else:
+        n_orb = np.resize(np.asarray(n_orb_per_atom, dtype=np.int32), n_atoms)
     bi, bj, bR, br = bonds(pos, cell, periodic, hop_cut)
     factor = 1.0
     while True:
         rng = Generator(PCG64(seed))
-        eps = onsite(rng, sub, n_orb_per_atom)
+        eps = onsite(rng, sub, int(n_orb.max()))
         h_scale = t0 * np.exp(-br / lam_h)
         s_scale = factor * s_amp * np.exp(-br / lam_s)
         row_ptr, col, blk_off, H, S = assemble(n_atoms, n_orb, bi, bj, br, eps, h_scale, s_scale, rng)
@@ -359,6 +363,11 @@ def small(name: str, seed: int = SEED_BASE + 100):
     'dia216': diamond 3x3x3 cells (216 atoms), config-1 recipe, r_L = 2.52 (5 shells).
     'fcc_slab': fcc 4x4x3 cells periodic in x,y, 4 vacancies, config-2 recipe.
     'fcc256':  bulk fcc 4x4x4 cells, periodic, config-2 recipe without vacancies.
+    'mixed27', 'mixed64': simple cubic with 1..16 orbitals per atom (plain DC; DC-LNO).
+    'isolated': no bonds, one-atom clusters of 1..16 orbitals.
+    'maxdim':  simple cubic 5x5x5, 16 orbitals, 57-atom clusters (dimension 912).
+    'maxdim952': fcc 3x3x3 cells, orbital pattern 16,16,16,16,4, r_L = 2.4: clusters of
+               dimension 880..952 (past 947 the tridiagonal solver's LDS exceeds 64 KB).
     'chain_gap' / 'chain_metal': 1D rings for truncation-behaviour checks.
     """
     if name == "sc27":
@@ -377,6 +386,26 @@ def small(name: str, seed: int = SEED_BASE + 100):
         s = make_system("fcc", (4, 4, 3), (1, 1, 0), 9, _onsite_zero, 1.0, 1.0, SHELLS["fcc"][2] + 1e-6,
                         seed, vacancies=4)
         return _params(s, name, math.sqrt(5.0), 0.01, lno=True, lambda_th=1e-3, k_min=2, k_max=6)
+    if name == "mixed27":
+        # ragged blocks: 1, 4, 9, 16 and 5 orbitals per atom in turn (16 is the compiled limit)
+        s = make_system("sc", (3, 3, 3), (1, 1, 1), [1, 4, 9, 16, 5], _onsite_gauss(0.1), 1.0, 0.8, 1.5, seed)
+        return _params(s, name, 1.5, 0.01, lno=False)
+    if name == "mixed64":
+        # ragged blocks with a long region (DC-LNO, occupation rule, ranks 1..M_j)
+        s = make_system("sc", (4, 4, 4), (1, 1, 1), [4, 9, 16, 6, 1], _onsite_gauss(0.1), 1.0, 0.8, 1.5, seed)
+        return _params(s, name, 2.0, 0.01, lno=True, lambda_th=0.1, k_min=1, k_max=-1)
+    if name == "isolated":
+        # no bonds: every cluster is its own atom, of 1 to 16 orbitals (dimensions below one
+        # band panel, the smallest tridiagonal problems)
+        s = make_system("sc", (2, 2, 4), (1, 1, 1), list(range(1, 17)), _onsite_gauss(0.3), 1.0, 0.8, 0.5, seed)
+        return _params(s, name, 0.5, 0.01, lno=False)
+    if name == "maxdim":
+        # 57-atom clusters of 16 orbitals: dimension 912, close to the compiled limit of 960
+        s = make_system("sc", (5, 5, 5), (1, 1, 1), 16, _onsite_gauss(0.1), 1.0, 0.8, 1.5, seed)
+        return _params(s, name, math.sqrt(5.0), 0.01, lno=False)
+    if name == "maxdim952":
+        s = make_system("fcc", (3, 3, 3), (1, 1, 1), [16, 16, 16, 16, 4], _onsite_gauss(0.1), 1.0, 0.8, 1.5, seed)
+        return _params(s, name, 2.4, 0.01, lno=False)
     if name == "fcc256":
         # bulk fcc 4x4x4 cells, periodic, config-2 recipe (no vacancies): the metal of the
         # error-versus-cluster-radius sweep (box half-width 2.83 d_NN > the largest swept r_L)
