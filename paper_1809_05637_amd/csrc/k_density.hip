@@ -18,6 +18,12 @@ namespace ldc {
 static_assert(4 * kMaxDimTri + (kMaxDimTri + 1) / 2 + kApplyChunk * kMaxOrb <= kQapplyLds,
               "dc_apply staging must fit the compact-WY LDS area");
 
+// Q2 r with r in LDS, kept out of line: inlined into the density kernel it raises the register
+// pressure of the whole kernel and spills (44.8 vs 94 ms per build on the 3920-atom slab)
+__device__ __noinline__ void density_q2_lds(const double *A, int n, double *Xs, int nc, double *runs, int rstride) {
+  wg_apply_q2_lds(A, n, Xs, nc, runs, rstride, false);
+}
+
 // state layout of Plan::d_mu
 enum { MU_LO = 0, MU_HI, MU_DONE, MU_IT, MU_SUMW, MU_NE, MU_KT, MU_G, MU_MU, MU_BAD };
 
@@ -184,11 +190,13 @@ __global__ void __launch_bounds__(256, 2) density_kernel(
     const int *__restrict__ n_orb, const int *__restrict__ p_rows, const int *__restrict__ mem_ptr,
     const int *__restrict__ mem_atom, const int *__restrict__ fna_ptr, const int *__restrict__ fna_blk,
     const long long *__restrict__ blk_off, const double *__restrict__ state, const double *__restrict__ H,
-    const double *__restrict__ S, double *__restrict__ Dout, double *__restrict__ partial) {
+    const double *__restrict__ S, double *__restrict__ Dout, double *__restrict__ partial, int q2_lds, int max_dim) {
   __shared__ double red[16 * 17];
   __shared__ double sred[8];
   __shared__ int foff[kMaxMembers + 1];
-  __shared__ double qlds[kQapplyLds];
+  // dynamic LDS: the compact-WY and merge staging area, which the Q2 product reuses to hold
+  // the n x M rows and the reflector runs when q2_lds is set
+  extern __shared__ double qlds[];
   const int tid = threadIdx.x, nthr = blockDim.x;
   const double mu = state[MU_MU], kT = state[MU_KT];
   for (int s = blockIdx.x; s < n_clusters; s += gridDim.x) {
@@ -222,7 +230,16 @@ __global__ void __launch_bounds__(256, 2) density_kernel(
     double *r = dc_apply(n, M, ws, ya, yb, qlds);
     // r <- Q r = Q1 (Q2 r): the bulge-chasing reflectors, then the band reduction's compact-WY
     // panels (T factors stored by the band reduction)
-    wg_apply_q2(A, ld, n, r, kMaxOrb, M, false);
+    if (q2_lds && n >= 3) {
+      __syncthreads();  // the merge staging in the same LDS is done
+      double *Xs = qlds, *runs = qlds + (long long)max_dim * M;
+      for (int e = tid; e < n * M; e += nthr) Xs[e] = r[(long long)(e / M) * kMaxOrb + e % M];
+      density_q2_lds(A, n, Xs, M, runs, max_dim);
+      for (int e = tid; e < n * M; e += nthr) r[(long long)(e / M) * kMaxOrb + e % M] = Xs[e];
+      __syncthreads();
+    } else {
+      wg_apply_q2(A, ld, n, r, kMaxOrb, M, false);
+    }
     wg_apply_q(A, ld, n, tt, cv + vl.u, false, r, kMaxOrb, M, false, qlds, kBand);
     // x_P = L_PP^{-T} r_P = ((L^{-1})_PP)^T r_P (P = the last p rows; the S slot holds L^{-1}):
     // x(g) = sum_{t >= g} Linv(t, g) r(t), written to the other buffer
@@ -313,11 +330,21 @@ void launch_mu_step(Plan &p, double, double, double) {
 void launch_density(Plan &p, int mode, double *d_D, const double *d_H, const double *d_S, double w_lo, double w_hi,
                     double w_kT) {
   double *cl_partial = p.d_partial + kMuStride * p.workgroups;
-  hipLaunchKernelGGL(density_kernel, dim3(p.workgroups), dim3(kWG), 0, p.stream, mode, w_lo, w_hi, w_kT, p.n_atoms,
+  // the Q2 product runs in LDS when the n x M rows and three reflector runs of the largest
+  // cluster still let two workgroups share a CU (72 KB each besides the 6 KB of static LDS)
+  const size_t base = sizeof(double) * kQapplyLds;
+  const size_t q2 = sizeof(double) * (size_t)p.max_dim * (size_t)(p.mmax + 3);
+  int q2_lds = q2 <= 72 * 1024;
+  if (q2_lds && q2 > 64 * 1024 &&
+      hipFuncSetAttribute(reinterpret_cast<const void *>(density_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)q2) != hipSuccess)
+    q2_lds = 0;
+  const size_t lds = q2_lds ? std::max(base, q2) : base;
+  hipLaunchKernelGGL(density_kernel, dim3(p.workgroups), dim3(kWG), lds, p.stream, mode, w_lo, w_hi, w_kT, p.n_atoms,
                      p.d_order, p.d_mat,
                      p.d_mat_off, p.d_vec, p.d_vec_off, p.d_ivec, p.d_ivec_off, p.d_dmax, p.d_dim, p.d_n_orb,
                      p.d_p_rows, p.d_mem_ptr, p.d_mem_atom, p.d_fna_ptr, p.d_fna_blk, p.d_blk_off, p.d_mu, d_H, d_S,
-                     d_D, cl_partial);
+                     d_D, cl_partial, q2_lds, p.max_dim);
   hipLaunchKernelGGL(sum_pairs_kernel, dim3(1), dim3(kWG), 0, p.stream, p.n_atoms, cl_partial,
                      p.d_mu + (mode == kRowsWindow ? 20 : (mode == kRowsEnergy ? 18 : 16)));
 }

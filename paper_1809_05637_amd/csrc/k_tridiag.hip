@@ -556,20 +556,7 @@ __global__ void __launch_bounds__(64 * kChaseWaves, 4) sb2st_kernel(int n_cluste
 // reflectors on disjoint rows).  Each workgroup takes one half of a cluster's 2M tracked
 // columns (the [L^{-1} E_i] or the [L^T E_i] half), so two workgroups fit a CU.  That half
 // (n x M) stays in LDS for all sweeps: the only global traffic is X in and out once and every
-// reflector read once per half.  A sweep's reflectors are one contiguous run of n - 1 - s
-// doubles (column n - 1 - s of A from row 0: per step tau, then v(1:len)).  Runs are fetched
-// two sweeps ahead into registers and parked in a triple buffer, one barrier per sweep.
-// Groups of 16 lanes take one reflector each, lane q one column (M <= 16).
-constexpr int kQ2Run = (kMaxDimTri + kWG - 1) / kWG;  // run elements per thread
-
-__device__ inline void q2_fetch_run(double *nx, const double *A, int n, int s, int tid, int nthr) {
-  // run of sweep s (clamped unconditional loads; a run past the last sweep reads sweep n - 3)
-  const int ss = min(s, n - 3), len = n - 1 - ss;
-  const double *src = A + (long long)(n - 1 - ss) * n;
-#pragma unroll
-  for (int u = 0; u < kQ2Run; ++u) nx[u] = src[min(tid + u * nthr, len - 1)];
-}
-
+// reflector read once per half.
 __global__ void __launch_bounds__(256, 2) q2x_lds_kernel(int n_clusters, const int *__restrict__ order,
                                                       const double *__restrict__ mat,
                                                       const long long *__restrict__ mat_off,
@@ -577,9 +564,7 @@ __global__ void __launch_bounds__(256, 2) q2x_lds_kernel(int n_clusters, const i
                                                       const int *__restrict__ dmax, const int *__restrict__ dim,
                                                       const int *__restrict__ n_orb, int max_dim) {
   extern __shared__ double q2l[];
-  constexpr int b = kBand;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int grp = tid >> 4, q = tid & 15, ngrp = nthr >> 4;
   for (int item = blockIdx.x; item < 2 * n_clusters; item += gridDim.x) {
     const int c = order[item >> 1], half = item & 1;
     const int n = dim[c], nc = n_orb[c];
@@ -591,53 +576,7 @@ __global__ void __launch_bounds__(256, 2) q2x_lds_kernel(int n_clusters, const i
     __syncthreads();
     if (n < 3) continue;
     for (int e = tid; e < n * nc; e += nthr) Xs[e] = X[(e / nc) * kTrack + e % nc];
-    double nx0[kQ2Run], nx1[kQ2Run];
-    q2_fetch_run(nx0, A, n, 0, tid, nthr);
-    q2_fetch_run(nx1, A, n, 1, tid, nthr);
-#pragma unroll
-    for (int u = 0; u < kQ2Run; ++u)
-      if (tid + u * nthr < n - 1) runs[tid + u * nthr] = nx0[u];
-    __syncthreads();
-    const int qc = min(q, nc - 1);
-    const int nsw = n - 2;
-    for (int s = 0; s < nsw; ++s) {
-      // nx1 holds the run of sweep s + 1; fetch sweep s + 2's
-      q2_fetch_run(nx0, A, n, s + 2, tid, nthr);
-      const double *cur = runs + (s % 3) * max_dim;
-      const int nst = (n - 3 - s) / b + 1;
-      for (int j = grp; j < nst; j += ngrp) {
-        const int r0 = s + 1 + j * b, len = min(b, n - r0);
-        const double *vp = cur + j * b;
-        double *xp = Xs + (long long)r0 * nc + qc;
-        double vv[b], xv[b];
-#pragma unroll
-        for (int i = 0; i < b; ++i) {
-          const int ii = min(i, len - 1);
-          const double t = vp[ii];
-          vv[i] = (i < len) ? t : 0.0;
-          xv[i] = xp[ii * nc];
-        }
-        const double tau = vv[0];
-        vv[0] = 1.0;
-        double d = 0.0;
-#pragma unroll
-        for (int i = 0; i < b; ++i) d += vv[i] * xv[i];
-        d *= tau;
-        if (q < nc) {
-#pragma unroll
-          for (int i = 0; i < b; ++i)
-            if (i < len) xp[i * nc] = xv[i] - d * vv[i];
-        }
-      }
-      double *nxt = runs + ((s + 1) % 3) * max_dim;
-      const int nlen = n - 2 - s;
-#pragma unroll
-      for (int u = 0; u < kQ2Run; ++u)
-        if (tid + u * nthr < nlen) nxt[tid + u * nthr] = nx1[u];
-#pragma unroll
-      for (int u = 0; u < kQ2Run; ++u) nx1[u] = nx0[u];
-      __syncthreads();
-    }
+    wg_apply_q2_lds(A, n, Xs, nc, runs, max_dim, true);
     for (int e = tid; e < n * nc; e += nthr) X[(e / nc) * kTrack + e % nc] = Xs[e];
   }
 }
