@@ -439,7 +439,7 @@ def main():
         print(json.dumps(sweep_bench()), flush=True)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs one density build on one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "the benchmark times one density-matrix build on one GPU; --gpus must be 1 "
                                    "(the cluster loop would shard by atoms across GPUs, see the design notes)"}))
         sys.exit(2)
     import torch
