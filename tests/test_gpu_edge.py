@@ -1,4 +1,5 @@
-"""GPU path against the oracle on the edge-case systems (through the C ABI).
+"""GPU path against the oracle on the edge-case systems (through the C ABI): density rows, and
+energy density and energy-window rows.
 
 * mixed27: ragged blocks, 1..16 orbitals per atom (16 is the compiled limit), plain DC;
 * mixed64: ragged blocks with a long region (DC-LNO, occupation rule, ranks 1..M_j);
@@ -43,3 +44,28 @@ def test_dc_lno_ragged_blocks():
     assert np.array_equal(got["ranks"], ref["ranks"])
     assert len(set(int(k) for k in ref["ranks"])) > 1  # the ranks are ragged too
     _cmp(s, got, ref, "mixed64-lno")
+
+
+@pytest.mark.parametrize("name", ["mixed27", "maxdim"])
+def test_energy_and_window_rows_edge_cases(name):
+    """The other two row modes of the density kernel on ragged blocks (mixed27) and on 912-row
+    clusters, whose Q2 product runs on global memory instead of LDS (maxdim): energy density rows
+    (Eq. 25) and energy-window rows against the oracle, element by element."""
+    import torch
+    s = synth.small(name)
+    ref = oracle.density_build(s, energy=True)
+    win = (ref["mu"] - 0.3, ref["mu"] + 0.2, 0.02)
+    ref_w = oracle.density_build(s, mu=ref["mu"], window=win)
+    got = gpu_build(s, energy=True, keep_plan=True)
+    plan, (_, S, _) = got["plan"], got["dev"]
+    W = torch.zeros_like(S)
+    tr_w = plan.window_density(*win, W)
+    torch.cuda.synchronize()
+    dE = float(np.abs(got["E"] - ref["E"]).max())
+    dW = float(np.abs(W.cpu().numpy() - ref_w["W"]).max())
+    print(f"[{name}] max|dE|={dE:.3e} max|dW|={dW:.3e}", flush=True)
+    plan.close()
+    assert dE <= 1e-9, dE
+    assert abs(got["tr_es"] - ref["e_band"]) <= 1e-10 * s["n_atoms"]
+    assert dW <= 1e-9, dW
+    assert abs(tr_w - ref_w["window_count"]) <= 1e-9 * max(1.0, ref_w["window_count"])
