@@ -1,7 +1,7 @@
 """GPU toy SCF loop (LNOs regenerated every step, Sec. II.C (i)) against the oracle, through the C ABI.
 
 * ldc_mulliken, ldc_potential and ldc_scf_mix each against the oracle's function on the same
-  seeded inputs;
+  seeded inputs (uniform and ragged blocks);
 * whole trajectories (plain DC on sc27; DC-LNO on dia216 with fixed ranks and on fcc_slab with
   the occupation rule): every step's populations, mu, E_band and density rows.
 
@@ -25,9 +25,12 @@ def _plan(s):
     return ldc.Plan.from_system(s, stream=torch.cuda.current_stream())
 
 
-def test_mulliken_potential_mix_match_oracle():
+@pytest.mark.parametrize("name", ["fcc_slab", "mixed27"])
+def test_mulliken_potential_mix_match_oracle(name):
+    """fcc_slab: 9 orbitals per atom with surfaces and vacancies; mixed27: ragged blocks of 1 to
+    16 orbitals (the kernels walk the pattern block by block)."""
     import torch
-    s = synth.small("fcc_slab")
+    s = synth.small(name)
     print(f"[gpu] scf kernels {s['name']} atoms={s['n_atoms']}", flush=True)
     rng = np.random.default_rng(7)
     dvals = rng.standard_normal(len(s["S"]))
