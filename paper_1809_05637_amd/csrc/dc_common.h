@@ -60,7 +60,8 @@ __device__ inline DcWs dc_ws(double *cv, int *ci, int nb) {
 constexpr int kApplyChunk = 32;
 __device__ inline int dc_apply_lds_doubles(int n) { return 4 * n + (n + 1) / 2 + kApplyChunk * kMaxOrb; }
 
-__device__ inline double *dc_apply(int n, int ny, DcWs ws, double *ya, double *yb, double *lds) {
+template <int NC>
+__device__ inline double *dc_apply_nc(int n, int ny, DcWs ws, double *ya, double *yb, double *lds) {
   const int tid = threadIdx.x, nthr = blockDim.x;
   double *sdK = lds, *szt = lds + n, *stau = lds + 2 * n, *snrm = lds + 3 * n;
   int *sorig = reinterpret_cast<int *>(lds + 4 * n);
@@ -109,9 +110,9 @@ __device__ inline double *dc_apply(int n, int ny, DcWs ws, double *ya, double *y
         }
       }
       const bool kept = q < n && kp >= 0 && j < kp;
-      double acc[kMaxOrb];
+      double acc[NC];
 #pragma unroll
-      for (int cc = 0; cc < kMaxOrb; ++cc) acc[cc] = 0.0;
+      for (int cc = 0; cc < NC; ++cc) acc[cc] = 0.0;
       const int rlo = qb - qb % span, rhi = min(n, ((min(qb + nthr, n) - 1) / span + 1) * span);
       for (int c0 = rlo; c0 < rhi; c0 += kApplyChunk) {
         __syncthreads();
@@ -125,10 +126,10 @@ __device__ inline double *dc_apply(int n, int ny, DcWs ws, double *ya, double *y
           for (int t = ta; t < tb; ++t) {
             const double u = zj * rcp_nr(((dj - sdK[lo + sorig[t]]) - stau[t]) * snrm[t]);
             const double *y = sy + (t - c0) * kMaxOrb;
-            // all kMaxOrb columns, unguarded (a guard per column would serialize the LDS
-            // reads); the entries past ny are never stored
+            // all NC columns, unguarded (a guard per column would serialize the LDS reads);
+            // the entries past ny are never stored
 #pragma unroll
-            for (int cc = 0; cc < kMaxOrb; ++cc) acc[cc] += u * y[cc];
+            for (int cc = 0; cc < NC; ++cc) acc[cc] += u * y[cc];
           }
         }
       }
@@ -139,11 +140,11 @@ __device__ inline double *dc_apply(int n, int ny, DcWs ws, double *ya, double *y
           if (!kept) {
             const double *y = yb + (long long)(lo + j) * kMaxOrb;
 #pragma unroll
-            for (int cc = 0; cc < kMaxOrb; ++cc) acc[cc] = (cc < ny) ? y[cc] : 0.0;
+            for (int cc = 0; cc < NC; ++cc) acc[cc] = (cc < ny) ? y[cc] : 0.0;
           }
           const int pos = R.kpos[lo + j];
 #pragma unroll
-          for (int cc = 0; cc < kMaxOrb; ++cc)
+          for (int cc = 0; cc < NC; ++cc)
             if (cc < ny) ya[(long long)(lo + pos) * kMaxOrb + cc] = acc[cc];
         }
       }
@@ -181,6 +182,12 @@ __device__ inline double *dc_apply(int n, int ny, DcWs ws, double *ya, double *y
     yb = t;
   }
   return ya;
+}
+
+// NC >= ny columns in the row sums: 9 covers s, p and d shells (the 16-column form costs 1.9 ms
+// more per build on the 3920-atom slab)
+__device__ inline double *dc_apply(int n, int ny, DcWs ws, double *ya, double *yb, double *lds) {
+  return ny <= 9 ? dc_apply_nc<9>(n, ny, ws, ya, yb, lds) : dc_apply_nc<kMaxOrb>(n, ny, ws, ya, yb, lds);
 }
 
 }  // namespace ldc
