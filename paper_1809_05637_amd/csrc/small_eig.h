@@ -5,11 +5,18 @@
 //  * hessenberg(): orthogonal reduction to upper Hessenberg form by Householder reflectors,
 //    accumulating the transformation;
 //  * schur(): Francis double-shift QR iteration to real Schur form T = Z^T A Z (1x1 blocks
-//    for real eigenvalues, 2x2 blocks for complex-conjugate pairs), accumulating Z;
-//  * kept_basis(): eigenvectors of selected eigenvalues by back-substitution in T, mapped
-//    back with Z; a complex pair contributes the real and imaginary parts of one member;
+//    for real eigenvalues, 2x2 blocks for complex-conjugate pairs), accumulating Z; written
+//    from the statement of the algorithm in Golub & Van Loan, Matrix Computations, Sec. 7.5
+//    (small_reflector / apply_small_reflector for the bulge, settle_block2 for a deflated
+//    2x2 block);
+//  * schur_vector(): the eigenvector of one eigenvalue by back-substitution in T (mapped
+//    back with Z by lno_atom); a complex pair contributes the real and imaginary parts of
+//    one member;
 //  * sym_jacobi(): cyclic Jacobi eigendecomposition of a small symmetric matrix (used for
-//    the S_jj-Loewdin orthonormalisation of the kept span).
+//    the S_jj-Loewdin orthonormalisation of the kept span);
+//  * lno_atom(): the whole per-atom step (rank rule, kept span, Loewdin basis).
+// tests/test_small_eig_host.py compiles this header for the host and checks it against
+// LAPACK's general eigensolver.
 #pragma once
 
 #include <math.h>
@@ -70,172 +77,191 @@ LDC_HD inline void hessenberg(double *a, double *z, int n) {
   }
 }
 
-// Real Schur form of an upper Hessenberg a, accumulating into z.  wr/wi: eigenvalues in
-// Schur order (a complex pair occupies two consecutive positions, +wi first).  Returns 0 on
-// success, -1 if an eigenvalue needed more than 200 iterations (an exceptional shift
-// is taken every 10 iterations).
+// Householder reflector of a 2- or 3-vector x (len = 2 or 3): P = I - tau v v^T with v(0) = 1
+// and P x = beta e_0.  Returns false (P = I) when x(1:) is already zero.
+LDC_HD inline bool small_reflector(const double *x, int len, double *v, double &tau, double &beta) {
+  double tail = 0.0;
+  for (int i = 1; i < len; ++i) tail += x[i] * x[i];
+  v[0] = 1.0;
+  if (tail == 0.0) {
+    for (int i = 1; i < len; ++i) v[i] = 0.0;
+    tau = 0.0;
+    beta = x[0];
+    return false;
+  }
+  const double nrm = sqrt(x[0] * x[0] + tail);
+  beta = x[0] > 0.0 ? -nrm : nrm;  // sign opposite to x(0): no cancellation in x(0) - beta
+  const double inv = 1.0 / (x[0] - beta);
+  for (int i = 1; i < len; ++i) v[i] = x[i] * inv;
+  tau = (beta - x[0]) / beta;
+  return true;
+}
+
+// Applies P = I - tau v v^T (v of length len, acting on indices k..k+len-1) to the rows
+// k.. of a on the columns [c0, c1), and to the columns k.. of a on the rows [0, r1) and of z
+// on the rows [0, n).
+LDC_HD inline void apply_small_reflector(double *a, double *z, int n, int k, int len, const double *v, double tau,
+                                         int c0, int c1, int r1) {
+  for (int c = c0; c < c1; ++c) {
+    double s = 0.0;
+    for (int i = 0; i < len; ++i) s += v[i] * a[(k + i) * LD + c];
+    s *= tau;
+    for (int i = 0; i < len; ++i) a[(k + i) * LD + c] -= s * v[i];
+  }
+  for (int r = 0; r < r1; ++r) {
+    double s = 0.0;
+    for (int i = 0; i < len; ++i) s += a[r * LD + k + i] * v[i];
+    s *= tau;
+    for (int i = 0; i < len; ++i) a[r * LD + k + i] -= s * v[i];
+  }
+  for (int r = 0; r < n; ++r) {
+    double s = 0.0;
+    for (int i = 0; i < len; ++i) s += z[r * LD + k + i] * v[i];
+    s *= tau;
+    for (int i = 0; i < len; ++i) z[r * LD + k + i] -= s * v[i];
+  }
+}
+
+// Brings the trailing 2 x 2 block at rows/columns (p, p + 1) of the quasi-triangular a to its
+// final form: with real eigenvalues it is rotated to upper-triangular form (first column of
+// the rotation = an eigenvector of the block), otherwise it is left as it is.  wr/wi receive
+// the two eigenvalues (a complex pair as mean +- i omega, the + member at p).
+LDC_HD inline void settle_block2(double *a, double *z, int n, int p, double *wr, double *wi) {
+  const double b00 = a[p * LD + p], b01 = a[p * LD + p + 1];
+  const double b10 = a[(p + 1) * LD + p], b11 = a[(p + 1) * LD + p + 1];
+  const double half = 0.5 * (b00 - b11);
+  const double disc = half * half + b01 * b10;  // the eigenvalues are b11 + half +- sqrt(disc)
+  if (disc < 0.0) {
+    const double om = sqrt(-disc);
+    wr[p] = wr[p + 1] = 0.5 * (b00 + b11);
+    wi[p] = om;
+    wi[p + 1] = -om;
+    return;
+  }
+  wi[p] = wi[p + 1] = 0.0;
+  if (b10 == 0.0) {  // already triangular
+    wr[p] = b00;
+    wr[p + 1] = b11;
+    return;
+  }
+  // lam = b11 + g with g of the sign of half (the larger root in magnitude, no cancellation);
+  // (g, b10) is an eigenvector of the block for lam
+  const double g = half + (half >= 0.0 ? sqrt(disc) : -sqrt(disc));
+  const double r = sqrt(g * g + b10 * b10);
+  const double cs = g / r, sn = b10 / r;
+  for (int c = p; c < n; ++c) {  // rows p, p + 1 <- G^T (rows)
+    const double u = a[p * LD + c], w = a[(p + 1) * LD + c];
+    a[p * LD + c] = cs * u + sn * w;
+    a[(p + 1) * LD + c] = -sn * u + cs * w;
+  }
+  for (int rr = 0; rr <= p + 1; ++rr) {  // columns p, p + 1 <- (columns) G
+    const double u = a[rr * LD + p], w = a[rr * LD + p + 1];
+    a[rr * LD + p] = cs * u + sn * w;
+    a[rr * LD + p + 1] = -sn * u + cs * w;
+  }
+  for (int rr = 0; rr < n; ++rr) {
+    const double u = z[rr * LD + p], w = z[rr * LD + p + 1];
+    z[rr * LD + p] = cs * u + sn * w;
+    z[rr * LD + p + 1] = -sn * u + cs * w;
+  }
+  a[(p + 1) * LD + p] = 0.0;
+  wr[p] = a[p * LD + p];
+  wr[p + 1] = a[(p + 1) * LD + p + 1];
+}
+
+// Real Schur form T = Z^T A Z of an upper Hessenberg a (n <= LD), accumulating into z: the
+// implicitly double-shifted QR iteration of Francis, as stated in Golub & Van Loan, Matrix
+// Computations (Sec. 7.5: the Francis step and the QR algorithm with deflation).  The active
+// window [lo, hi] is the trailing unreduced Hessenberg block; a subdiagonal entry below
+// 2^-53 times its two diagonal neighbours is set to zero (deflation).  A 1 x 1 window is a
+// real eigenvalue; a 2 x 2 window is settled by settle_block2.  Otherwise one Francis step:
+// the shifts s1, s2 are the two eigenvalues of the window's trailing 2 x 2 block, the first
+// column of (H - s1)(H - s2) restricted to the window starts a bulge that 3 x 3 reflectors
+// chase down to the bottom.  Every 11th step of a window uses an ad hoc
+// shift pair built from the window's last subdiagonal entries instead, which breaks the
+// cycles that the standard shifts can fall into.  The reflectors act on whole rows and
+// columns of a (not only the window), so a ends as the full quasi-triangular T needed for
+// the eigenvectors.  wr/wi: eigenvalues in Schur order (a complex pair at two consecutive
+// positions, +wi first).  Returns 0, or -1 if a window needed more than 100 steps.
 LDC_HD inline int schur(double *a, double *z, double *wr, double *wi, int n) {
-  double anorm = 0.0;
+  double scale = 0.0;
   for (int i = 0; i < n; ++i)
-    for (int j = (i > 0 ? i - 1 : 0); j < n; ++j) anorm += fabs(a[i * LD + j]);
-  int nn = n - 1;
-  double t = 0.0;
-  int its = 0;
-  while (nn >= 0) {
-    int l;
-    for (l = nn; l >= 1; --l) {
-      double s = fabs(a[(l - 1) * LD + l - 1]) + fabs(a[l * LD + l]);
-      if (s == 0.0) s = anorm;
-      if (fabs(a[l * LD + l - 1]) + s == s) {
-        a[l * LD + l - 1] = 0.0;
+    for (int j = (i > 0 ? i - 1 : 0); j < n; ++j) scale = fmax(scale, fabs(a[i * LD + j]));
+  const double eps = 1.1102230246251565e-16;  // 2^-53
+  int hi = n - 1, steps = 0;
+  while (hi >= 0) {
+    int lo = hi;
+    for (; lo > 0; --lo) {
+      double nb = fabs(a[(lo - 1) * LD + lo - 1]) + fabs(a[lo * LD + lo]);
+      if (nb == 0.0) nb = scale;
+      if (fabs(a[lo * LD + lo - 1]) <= eps * nb) {
+        a[lo * LD + lo - 1] = 0.0;
         break;
       }
     }
-    double x = a[nn * LD + nn];
-    if (l == nn) {  // one real root
-      a[nn * LD + nn] = x + t;
-      wr[nn] = x + t;
-      wi[nn] = 0.0;
-      --nn;
-      its = 0;
+    if (lo == hi) {
+      wr[hi] = a[hi * LD + hi];
+      wi[hi] = 0.0;
+      --hi;
+      steps = 0;
       continue;
     }
-    double y = a[(nn - 1) * LD + nn - 1];
-    double w = a[nn * LD + nn - 1] * a[(nn - 1) * LD + nn];
-    if (l == nn - 1) {  // a 2x2 block
-      double p = 0.5 * (y - x);
-      double q = p * p + w;
-      double zz = sqrt(fabs(q));
-      x += t;
-      a[nn * LD + nn] = x;
-      a[(nn - 1) * LD + nn - 1] = y + t;
-      if (q >= 0.0) {  // real pair: rotate the block to triangular form
-        zz = p + sgn_copy(zz, p);
-        wr[nn - 1] = wr[nn] = x + zz;
-        if (zz != 0.0) wr[nn] = x - w / zz;
-        wi[nn - 1] = wi[nn] = 0.0;
-        x = a[nn * LD + nn - 1];
-        double s = fabs(x) + fabs(zz);
-        p = x / s;
-        q = zz / s;
-        double r = sqrt(p * p + q * q);
-        p /= r;
-        q /= r;
-        for (int j = nn - 1; j < n; ++j) {
-          zz = a[(nn - 1) * LD + j];
-          a[(nn - 1) * LD + j] = q * zz + p * a[nn * LD + j];
-          a[nn * LD + j] = q * a[nn * LD + j] - p * zz;
-        }
-        for (int i = 0; i <= nn; ++i) {
-          zz = a[i * LD + nn - 1];
-          a[i * LD + nn - 1] = q * zz + p * a[i * LD + nn];
-          a[i * LD + nn] = q * a[i * LD + nn] - p * zz;
-        }
-        for (int i = 0; i < n; ++i) {
-          zz = z[i * LD + nn - 1];
-          z[i * LD + nn - 1] = q * zz + p * z[i * LD + nn];
-          z[i * LD + nn] = q * z[i * LD + nn] - p * zz;
-        }
-        a[nn * LD + nn - 1] = 0.0;
-      } else {  // complex pair
-        wr[nn - 1] = wr[nn] = x + p;
-        wi[nn - 1] = zz;
-        wi[nn] = -zz;
-      }
-      nn -= 2;
-      its = 0;
+    if (lo == hi - 1) {
+      settle_block2(a, z, n, hi - 1, wr, wi);
+      hi -= 2;
+      steps = 0;
       continue;
     }
-    // no root yet: one double-shift QR sweep on rows/columns l..nn
-    if (its >= 200) return -1;
-    if (its > 0 && its % 10 == 0) {  // exceptional shift
-      t += x;
-      for (int i = 0; i <= nn; ++i) a[i * LD + i] -= x;
-      double s = fabs(a[nn * LD + nn - 1]) + fabs(a[(nn - 1) * LD + nn - 2]);
-      y = x = 0.75 * s;
-      w = -0.4375 * s * s;
+    if (steps >= 100) return -1;
+    ++steps;
+    // First column of (H - s1)(H - s2) on the window, divided by h10 (a common factor that
+    // leaves the reflector unchanged), written with differences of nearby diagonal entries so
+    // that nothing cancels when the shifts lie close to h00:
+    //   x = (h00 - s1)(h00 - s2) / h10 + h01,  y = (h11 - h00) + (h00 - s1) + (h00 - s2),  z = h21.
+    const double h00 = a[lo * LD + lo], h01 = a[lo * LD + lo + 1];
+    const double h10 = a[(lo + 1) * LD + lo], h11 = a[(lo + 1) * LD + lo + 1];
+    const double h21 = a[(lo + 2) * LD + lo + 1];
+    double prod, sum;  // (h00 - s1)(h00 - s2) and (h00 - s1) + (h00 - s2)
+    if (steps % 11 == 0) {
+      // ad hoc shifts: the complex pair h + w (0.6 +- 0.8 i) with h the last diagonal entry and
+      // w the size of the last two subdiagonal entries (not symmetric about h, so that a
+      // spectrum symmetric about h cannot hold the iteration in place)
+      const double w = fabs(a[hi * LD + hi - 1]) + fabs(a[(hi - 1) * LD + hi - 2]);
+      const double e = h00 - a[hi * LD + hi] - 0.6 * w;
+      prod = e * e + 0.64 * w * w;
+      sum = 2.0 * e;
+    } else {
+      // the eigenvalues of the window's trailing 2 x 2 block [p00 p01; p10 p11]
+      const double p00 = a[(hi - 1) * LD + hi - 1], p01 = a[(hi - 1) * LD + hi];
+      const double p10 = a[hi * LD + hi - 1], p11 = a[hi * LD + hi];
+      const double e1 = h00 - p00, e2 = h00 - p11;
+      prod = e1 * e2 - p01 * p10;
+      sum = e1 + e2;
     }
-    ++its;
-    int m;
-    double p = 0.0, q = 0.0, r = 0.0, zz;
-    for (m = nn - 2; m >= l; --m) {
-      zz = a[m * LD + m];
-      r = x - zz;
-      double s = y - zz;
-      p = (r * s - w) / a[(m + 1) * LD + m] + a[m * LD + m + 1];
-      q = a[(m + 1) * LD + m + 1] - zz - r - s;
-      r = a[(m + 2) * LD + m + 1];
-      s = fabs(p) + fabs(q) + fabs(r);
-      p /= s;
-      q /= s;
-      r /= s;
-      if (m == l) break;
-      double u = fabs(a[m * LD + m - 1]) * (fabs(q) + fabs(r));
-      double vv = fabs(p) * (fabs(a[(m - 1) * LD + m - 1]) + fabs(zz) + fabs(a[(m + 1) * LD + m + 1]));
-      if (u + vv == vv) break;
+    double x[3] = {prod / h10 + h01, (h11 - h00) + sum, h21};
+    {
+      const double sc = fabs(x[0]) + fabs(x[1]) + fabs(x[2]);
+      if (sc > 0.0)
+        for (int i = 0; i < 3; ++i) x[i] /= sc;
     }
-    for (int i = m + 2; i <= nn; ++i) {
-      a[i * LD + i - 2] = 0.0;
-      if (i != m + 2) a[i * LD + i - 3] = 0.0;
-    }
-    for (int k = m; k <= nn - 1; ++k) {
-      if (k != m) {
-        p = a[k * LD + k - 1];
-        q = a[(k + 1) * LD + k - 1];
-        r = 0.0;
-        if (k != nn - 1) r = a[(k + 2) * LD + k - 1];
-        x = fabs(p) + fabs(q) + fabs(r);
-        if (x != 0.0) {
-          p /= x;
-          q /= x;
-          r /= x;
-        }
+    double v[3], tau, beta;
+    for (int k = lo; k <= hi - 1; ++k) {
+      const int len = (k <= hi - 2) ? 3 : 2;
+      if (k > lo) {
+        for (int i = 0; i < len; ++i) x[i] = a[(k + i) * LD + k - 1];
       }
-      double s = sgn_copy(sqrt(p * p + q * q + r * r), p);
-      if (s != 0.0) {
-        if (k == m) {
-          if (l != m) a[k * LD + k - 1] = -a[k * LD + k - 1];
-        } else {
-          a[k * LD + k - 1] = -s * x;
-        }
-        p += s;
-        x = p / s;
-        y = q / s;
-        zz = r / s;
-        q /= p;
-        r /= p;
-        for (int j = k; j < n; ++j) {
-          p = a[k * LD + j] + q * a[(k + 1) * LD + j];
-          if (k != nn - 1) {
-            p += r * a[(k + 2) * LD + j];
-            a[(k + 2) * LD + j] -= p * zz;
-          }
-          a[(k + 1) * LD + j] -= p * y;
-          a[k * LD + j] -= p * x;
-        }
-        int mmin = nn < k + 3 ? nn : k + 3;
-        for (int i = 0; i <= mmin; ++i) {
-          p = x * a[i * LD + k] + y * a[i * LD + k + 1];
-          if (k != nn - 1) {
-            p += zz * a[i * LD + k + 2];
-            a[i * LD + k + 2] -= p * r;
-          }
-          a[i * LD + k + 1] -= p * q;
-          a[i * LD + k] -= p;
-        }
-        for (int i = 0; i < n; ++i) {
-          p = x * z[i * LD + k] + y * z[i * LD + k + 1];
-          if (k != nn - 1) {
-            p += zz * z[i * LD + k + 2];
-            z[i * LD + k + 2] -= p * r;
-          }
-          z[i * LD + k + 1] -= p * q;
-          z[i * LD + k] -= p;
+      if (small_reflector(x, len, v, tau, beta)) {
+        const int c0 = (k > lo) ? k - 1 : k;
+        const int r1 = (k + 3 < hi ? k + 3 : hi) + 1;
+        apply_small_reflector(a, z, n, k, len, v, tau, c0, n, r1);
+        if (k > lo) {
+          a[k * LD + k - 1] = beta;
+          for (int i = 1; i < len; ++i) a[(k + i) * LD + k - 1] = 0.0;
         }
       }
     }
   }
-  // entries below the subdiagonal are logically zero (bulge remnants are never read)
+  // entries below the subdiagonal are zero in exact arithmetic; clear the rounding residue
   for (int i = 2; i < n; ++i)
     for (int j = 0; j + 1 < i; ++j) a[i * LD + j] = 0.0;
   return 0;

@@ -11,24 +11,13 @@ import pytest
 mp = pytest.importorskip("mpmath")
 
 import oracle  # noqa: E402
-import synth  # noqa: E402
+from pair_systems import tiny_pair_system  # noqa: E402
 
 mp.mp.dps = 40
 
 
 def _tiny():
-    s = synth.make_system("sc", (8, 1, 1), (1, 0, 0), 3, lambda rng, sub, m: rng.normal(0, 0.1, (len(sub), m)),
-                          1.0, 0.8, 1.0 + 1e-6, 4242)
-    n = s["n_atoms"]
-    s.update(r_L=3.0, kappa=0.3, kT=0.05, spin_g=2, n_electrons=float(3 * n), lno=True,
-             lambda_th=0.1, k_min=1, k_max=-1, fixed_k=-1)
-    # a symmetric "previous density" on the pattern (any rho is allowed for the LNOs)
-    rng = np.random.default_rng(15)
-    dense_s, offs = oracle.exact.dense(s, s["S"])
-    x = rng.standard_normal(dense_s.shape) * 0.3
-    rho = (x + x.T) * (dense_s != 0)
-    dprev = oracle.exact_density_blocks(s, rho)
-    return s, dprev
+    return tiny_pair_system()
 
 
 def _blk(s, vals, i, j):
