@@ -32,8 +32,9 @@ HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
 
 
 def stage_work(dims):
-    """Algorithmic FP64 flops of the matrix-core stages for clusters of dimension d (LAPACK
-    counts: Cholesky d^3/3, standard form d^3, reduction to band form 4 d^3 / 3)."""
+    """Algorithmic FP64 flops of the matrix-core stages for clusters of dimension d, by the
+    per-cluster LAPACK counts of the operation each stage performs: Cholesky d^3/3, standard
+    form d^3, reduction to band form 4 d^3 / 3 (the whole tridiagonalization's count)."""
     d = dims.astype(np.float64)
     return {
         "potrf": float(np.sum(d ** 3 / 3.0)),
@@ -42,11 +43,37 @@ def stage_work(dims):
     }
 
 
-def sb2st_bytes(dims, b=32):
-    """Bytes the band-to-tridiagonal chase must move: every step of every sweep reads and writes
-    its window once (the lower triangle of the len x len diagonal block and the nr x len block
-    below it) and writes its reflector (len doubles).  Sweep s, step j: r0 = s + 1 + j b,
-    len = min(b, d - r0), nr = min(b, d - r0 - len), steps while r0 <= d - 2."""
+def executed_flops(dims, n_orb, b=32):
+    """FP64 flops this design executes in the eigensolve (potrf .. stedc) per build: Cholesky
+    d^3/3; standard form with the triangular inverse d^3/3, P = L^-1 H_L d^3/3 and
+    A = P L^-T + L^-1 P^T 2 d^3/3; band reduction 4 d^3/3; bulge chasing 6 b d^2 (12 b^2 per
+    step, d^2 / 2b steps); the 2M tracked columns through Q2 and the merges 8 M d^2.  No
+    eigenvector matrix and no back-transform are formed (the O(d^3) part is 3 d^3)."""
+    d = dims.astype(np.float64)
+    m = np.asarray(n_orb, dtype=np.float64)
+    return float(np.sum(3.0 * d ** 3 + 6.0 * b * d ** 2 + 8.0 * m * d ** 2))
+
+
+def sb2st_min_bytes(dims, b=32):
+    """HBM bytes the band-to-tridiagonal step cannot avoid: the lower band (b + 1 diagonals)
+    read once, the bulge-chasing reflectors (n - 1 - s entries for sweep s) written once, the
+    diagonal and off-diagonal written once."""
+    total = 0.0
+    for n in np.unique(dims):
+        n = int(n)
+        cnt = int(np.sum(dims == n))
+        band = sum(min(b + 1, n - c) for c in range(n))
+        refl = sum(n - 1 - s for s in range(0, max(0, n - 2)))
+        total += cnt * 8.0 * (band + refl + 2 * n)
+    return total
+
+
+def sb2st_design_bytes(dims, b=32):
+    """Bytes this design's chase moves when every window goes through memory: every step of
+    every sweep reads and writes its window once (the lower triangle of the len x len diagonal
+    block and the nr x len block below it) and writes its reflector (len doubles).  Sweep s,
+    step j: r0 = s + 1 + j b, len = min(b, d - r0), nr = min(b, d - r0 - len), steps while
+    r0 <= d - 2."""
     total = 0.0
     for n in np.unique(dims):
         cnt = int(np.sum(dims == n))
@@ -116,8 +143,19 @@ def stored_traffic(kernel, workload):
     return float(b.group(1))
 
 
+def host_workers():
+    """Oracle pool size: the host cores this process may run on, at most 16 (the host share
+    that goes with one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
 def cpu_baseline(s, sample_n, seed=0):
-    """The CPU oracle on a sample of clusters of the same workload (test infrastructure)."""
+    """The CPU oracle on a sample of clusters of the same workload (test infrastructure): the
+    SCF benchmark's baseline (one build's cost, extrapolated from the sample)."""
     import oracle
     t_start = time.time()
     rng = np.random.default_rng(seed)
@@ -132,7 +170,7 @@ def cpu_baseline(s, sample_n, seed=0):
                 m = no[i]
                 sii = s["S"][off[b]: off[b] + m * m].reshape(m, m)
                 dprev[off[b]: off[b] + m * m] = (0.5 * np.linalg.inv(sii)).ravel()
-    workers = oracle.driver.default_workers()
+    workers = host_workers()
     r = oracle.density_build(s, dprev=dprev, mu=0.0, clusters=clusters, workers=workers)
     t = r["times"]
     per_cluster = t["solve"] / len(clusters)
@@ -141,6 +179,43 @@ def cpu_baseline(s, sample_n, seed=0):
             "sample": (f"{len(clusters)} of {s['n_atoms']} clusters of the same DC-LNO build (LNOs of all atoms, "
                        f"cluster eigensolves and density rows at a fixed mu) in a {workers}-process pool; "
                        f"{time.time() - t_start:.1f} s wall; build time extrapolated to all clusters: {est:.1f} s")}
+
+
+def oracle_builds(s, log):
+    """The oracle's own chain on the benchmark input (test infrastructure, the cpu_baseline
+    leg): its plain-DC build (untimed), then the DC-LNO build from that density, timed whole
+    (all clusters, bisection over all of them, every density row; no sampling)."""
+    import oracle
+    workers = host_workers()
+    t0 = time.time()
+    r0 = oracle.density_build(s, dprev=None, workers=workers)
+    t1 = time.time()
+    log(f"[bench] oracle plain-DC build: {t1 - t0:.1f} s on {workers} processes")
+    r1 = oracle.density_build(s, dprev=r0["D"], workers=workers)
+    t2 = time.time()
+    log(f"[bench] oracle DC-LNO build: {t2 - t1:.1f} s  mu={r1['mu']:.12f}  "
+        f"E_band/atom={r1['e_band'] / s['n_atoms']:.12f}")
+    base = {"value": round(s["n_atoms"] / (t2 - t1), 3), "unit": "atoms/s", "cores": workers, "kind": "oracle",
+            "sample": (f"the whole DC-LNO build of the same input ({s['n_atoms']} clusters: LNOs of every atom from "
+                       f"the oracle's own plain-DC density, every cluster eigensolve, the bisection over all of "
+                       f"them and every density row) in a {workers}-process pool: {t2 - t1:.1f} s wall; its "
+                       f"plain-DC build that seeds the LNOs took {t1 - t0:.1f} s and is not counted")}
+    return base, r0, r1
+
+
+def accuracy_vs_oracle(s, ref, D, mu, eb, ne, ranks):
+    """The timed build against the oracle's build of the same input (Eq. 13, 24 with 27):
+    band energy per atom, density rows element by element, chemical potential, electron
+    count (g Tr(D S) from the returned rows against N_e, and against the oracle's), ranks."""
+    n = s["n_atoms"]
+    return {"vs": "oracle DC-LNO build of the same input (its own plain-DC density for the LNOs)",
+            "dE_band_per_atom": abs(eb - ref["e_band"]) / n,
+            "max_dD": float(np.max(np.abs(D - ref["D"]))),
+            "dmu": abs(mu - ref["mu"]),
+            "dN_e_strict": abs(ne - s["n_electrons"]),
+            "dN_e_vs_oracle": abs(ne - ref["n_e"]),
+            "ranks_equal": bool(np.array_equal(np.asarray(ranks), np.asarray(ref["ranks"]))),
+            "e_band_per_atom": eb / n, "mu": mu}
 
 
 def scf_bench(s, plan, H0, S, rule, use_lno, args, log):
@@ -170,7 +245,8 @@ def scf_bench(s, plan, H0, S, rule, use_lno, args, log):
     stages, builds = plan.stage_times()
     per_stage = {k: v / max(1, builds) for k, v in stages.items()}
     # the SCF kernels alone (10 calls each, on the last step's buffers)
-    q0 = torch.as_tensor(scf.reference_populations(s["n_orb"], s["n_electrons"]), device=S.device)
+    q0 = torch.empty(s["n_atoms"], dtype=torch.float64, device=S.device)
+    plan.reference_populations(s["n_electrons"], q0)
     q_in, q_out, v = q0.clone(), torch.zeros_like(q0), torch.zeros_like(q0)
     D, H = torch.zeros_like(S), torch.empty_like(H0)
 
@@ -416,6 +492,9 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="batched form without running the tuner")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1809_05637_amd", "tune", "mi355x.json"),
+                    help="tuning cache of the batched form (read, and written by the tuner when it has no entry)")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--scf", type=int, default=0, metavar="K",
                     help="instead of the build benchmark: K timed steps of the toy SCF loop (LNOs regenerated "
@@ -452,11 +531,12 @@ def main():
     log(f"[bench] config {args.config} {s['name']}: {s['n_atoms']} atoms, {s['n_basis']} basis, "
         f"{len(s['col'])} blocks ({time.time() - t0:.1f} s)")
     dev = torch.device("cuda:0")
-    stream = torch.cuda.current_stream()
+    # a stream of its own (default priority): the batched form captures its builds there
+    stream = torch.cuda.Stream(device=dev)
+    torch.cuda.set_stream(stream)
     H = torch.from_numpy(s["H"]).to(dev)
     S = torch.from_numpy(s["S"]).to(dev)
-    Da = torch.zeros_like(S)
-    Db = torch.zeros_like(S)
+    torch.cuda.synchronize()
     t1 = time.time()
     plan = ldc.Plan.from_system(s, stream=stream)
     info = plan.info()
@@ -473,55 +553,94 @@ def main():
         print(json.dumps(scf_bench(s, plan, H, S, rule, use_lno, args, log)), flush=True)
         plan.close()
         return
-    # step 0: plain DC seeds the first LNOs
+    out = build_bench(s, args, log, H, S, plan, stream, rule, use_lno)
+    print(json.dumps(out), flush=True)
+
+
+def build_bench(s, args, log, H, S, plan, stream, rule, use_lno):
+    """The FP64 forms on the benchmark workload.  Step 0 (untimed) is plain DC; its density D0
+    is the previous density of every timed build, so that every timed build does the same work.
+    Eager form: ldc_lno + ldc_solve + ldc_density per step with per-stage HIP events.  Batched
+    form: one ldc_build per step, replayed from a HIP graph, size buckets and launch grids from
+    the tuning cache (ldc_tune fills it when it has no entry for this device and workload)."""
+    import torch
+    import paper_1809_05637_amd as ldc
+    Da, Db, Dc = torch.zeros_like(S), torch.zeros_like(S), torch.zeros_like(S)
     t2 = time.time()
     plan.lno(S, None)
     plan.solve(H, S)
     mu0, eb0, ne0 = plan.density(s["n_electrons"], s["kT"], Da)
     log(f"[bench] plain-DC build: {time.time() - t2:.2f} s  mu={mu0:.10f}  E_band/atom={eb0 / s['n_atoms']:.10f}")
-    cur, nxt = Da, Db
+    D0 = Da if use_lno else None
+    ranks = plan.lno(S, D0, want_ranks=True, **rule)
 
     def step():
-        nonlocal cur, nxt
-        plan.lno(S, cur if use_lno else None, want_ranks=False, **rule)
+        plan.lno(S, D0, want_ranks=False, **rule)
         plan.solve(H, S)
-        out = plan.density(s["n_electrons"], s["kT"], nxt)
-        cur, nxt = nxt, cur
-        return out
+        return plan.density(s["n_electrons"], s["kT"], Db)
 
     for w in range(args.warmup):
         tw = time.time()
         mu, eb, ne = step()
-        log(f"[bench] warmup {w}: {time.time() - tw:.3f} s  mu={mu:.10f}")
+        log(f"[bench] eager warmup {w}: {time.time() - tw:.3f} s  mu={mu:.10f}")
     plan.profile(True)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
-    tw0 = time.time()
     for k in range(args.steps):
         mu, eb, ne = step()
-        log(f"[bench] step {k}: mu={mu:.12f} E_band/atom={eb / s['n_atoms']:.12f} N_e(D)={ne:.9f}")
+        log(f"[bench] eager step {k}: mu={mu:.12f} E_band/atom={eb / s['n_atoms']:.12f} N_e(D)={ne:.9f}")
     ev1.record(stream)
     torch.cuda.synchronize()
-    wall = time.time() - tw0
-    ms_total = ev0.elapsed_time(ev1)
-    ms_step = ms_total / args.steps
+    ms_eager = ev0.elapsed_time(ev1) / args.steps
     stages, builds = plan.stage_times()
     dims = plan.cluster_dims()
+    plan.profile(False)
     per_stage = {k: v / max(1, builds) for k, v in stages.items()}
     log("[bench] stage ms/build: " + ", ".join(f"{k}={v:.2f}" for k, v in per_stage.items()))
-    log(f"[bench] dims: min {dims.min()} mean {dims.mean():.1f} max {dims.max()}; wall {wall / args.steps * 1e3:.1f} "
-        f"ms/step, events {ms_step:.1f} ms/step")
+    log(f"[bench] dims: min {dims.min()} mean {dims.mean():.1f} max {dims.max()}; eager {ms_eager:.1f} ms/build")
+    D_eager = Db.cpu().numpy()
+
+    # batched form: tuned buckets, one graph-replayed ldc_build per step
+    cache = args.tune_cache
+    bplan = ldc.Plan.from_system(s, stream=stream, batched=True, use_graph=True, tune_cache=cache)
+    bplan.build(H, S, None, s["n_electrons"], s["kT"], Dc)
+    bplan.build(H, S, D0, s["n_electrons"], s["kT"], Dc, **rule)
+    tune_ms = None
+    if bplan.info()["tuned"] != 2 and not args.no_tune:
+        tt = time.time()
+        tune_ms = bplan.tune(H, S, D0, s["n_electrons"], s["kT"], Dc, **rule)
+        log(f"[bench] tuned in {time.time() - tt:.1f} s: {tune_ms:.1f} ms/build, cache {cache}")
+    for w in range(max(1, args.warmup)):
+        bplan.build(H, S, D0, s["n_electrons"], s["kT"], Dc, **rule)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for k in range(args.steps):
+        mu_b, eb_b, ne_b = bplan.build(H, S, D0, s["n_electrons"], s["kT"], Dc, **rule)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    binfo = bplan.info()
+    buckets = bplan.buckets()
+    bplan.close()
+    D_gpu = Dc.cpu().numpy()
+    log(f"[bench] batched form: {ms_step:.1f} ms/build ({len(buckets)} buckets, launch choices "
+        f"{['default', 'tuned', 'cache'][binfo['tuned']]}, graph captures {binfo['graph_captures']}, "
+        f"replays {binfo['graph_replays']}); max |D_batched - D_eager| = {np.abs(D_gpu - D_eager).max():.3e}")
+
     work = stage_work(dims)
     dom = max(per_stage, key=per_stage.get)
     kern = dom + "_kernel"
     if dom == "sb2st":
-        alg = sb2st_bytes(dims)
+        alg = sb2st_min_bytes(dims)
         achieved = alg / (per_stage[dom] * 1e-3) / 1e9
-        roof = {"kernel": kern, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic(kern, s["name"]),
-                "ms_per_launch": round(per_stage[dom], 3), "algorithmic_bytes": alg}
+        roof = {"kernel": kern, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": stored_traffic(kern, s["name"]),
+                "ms_per_launch": round(per_stage[dom], 3), "algorithmic_bytes": alg,
+                "algorithmic": "lower band read once + reflectors, diagonal and off-diagonal written once",
+                "design_traffic": sb2st_design_bytes(dims),
+                "design_traffic_note": "every bulge window read and written once per step (this design's chase)"}
     elif dom in work:
         achieved = work[dom] / (per_stage[dom] * 1e-3) / 1e12
         roof = {"kernel": kern, "bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
@@ -531,10 +650,20 @@ def main():
     else:
         roof = {"kernel": kern, "bound": "alu", "achieved": None, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": None, "traffic": None, "ms_per_launch": round(per_stage[dom], 3)}
-    # the eigensolve as a whole (Cholesky .. tridiagonal eigenvectors of the tracked columns)
-    # against the FP64 matrix-core peak, 7 d^3 flops per cluster
+    roof["measured"] = "HIP events around the kernel on the plan's stream, eager builds of the same work"
+    # the eigensolve as a whole (Cholesky .. divide-and-conquer) against the FP64 peak: executed
+    # flops, and the tridiagonalization (band reduction + chase) against its LAPACK count
     eig_ms = sum(per_stage.get(k, 0.0) for k in ("potrf", "sygst", "sy2sb", "sb2st", "q2x", "stedc"))
-    eig_tf = float(np.sum(7.0 * dims.astype(np.float64) ** 3)) / (eig_ms * 1e-3) / 1e12 if eig_ms > 0 else None
+    ex = executed_flops(dims, np.asarray(s["n_orb"]))
+    tri_ms = per_stage.get("sy2sb", 0.0) + per_stage.get("sb2st", 0.0)
+    tri_fl = float(np.sum(4.0 * dims.astype(np.float64) ** 3 / 3.0))
+    eig = {"executed_flops": ex, "ms": round(eig_ms, 3),
+           "tflops": round(ex / (eig_ms * 1e-3) / 1e12, 3) if eig_ms > 0 else None,
+           "frac_fp64_peak": round(ex / (eig_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4) if eig_ms > 0 else None,
+           "tridiagonalization": {"flops_4d3_3": tri_fl, "ms": round(tri_ms, 3),
+                                  "frac_fp64_peak": round(tri_fl / (tri_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)
+                                  if tri_ms > 0 else None},
+           "lapack_equivalent_flops_7d3": float(np.sum(7.0 * dims.astype(np.float64) ** 3))}
     value = s["n_atoms"] / (ms_step * 1e-3)
     out = {
         "metric": "atoms/s per density-matrix build (FP64 form)",
@@ -551,20 +680,32 @@ def main():
         "data": "synthetic",
         "config": {"workload": s["name"] + "_dclno_fp64", "atoms": int(s["n_atoms"]), "basis": int(s["n_basis"]),
                    "clusters": int(s["n_atoms"]), "dim_min": int(dims.min()), "dim_mean": round(float(dims.mean()), 1),
-                   "dim_max": int(dims.max()), "kT": s["kT"], "form": "fp64"},
+                   "dim_max": int(dims.max()), "kT": s["kT"], "form": "fp64 batched (hipGraph replay, tuned buckets)",
+                   "lno_source": "plain-DC density of the same input (fixed for every timed build)"},
         "clusters_per_s": round(value, 2),
+        "forms": {
+            "fp64_batched": {"atoms_per_s": round(value, 2), "ms_per_build": round(ms_step, 3),
+                             "buckets": buckets, "launch_choices": ["default", "tuned", "cache"][binfo["tuned"]],
+                             "tune_ms": tune_ms, "graph_captures": binfo["graph_captures"],
+                             "graph_replays": binfo["graph_replays"]},
+            "fp64_eager": {"atoms_per_s": round(s["n_atoms"] / (ms_eager * 1e-3), 2),
+                           "ms_per_build": round(ms_eager, 3),
+                           "max_abs_diff_vs_batched": float(np.abs(D_gpu - D_eager).max())},
+        },
         "stage_ms": {k: round(v, 3) for k, v in per_stage.items()},
         "roofline": roof,
-        "eigensolve": {"flops_7d3": float(np.sum(7.0 * dims.astype(np.float64) ** 3)), "ms": round(eig_ms, 3),
-                       "tflops": round(eig_tf, 3) if eig_tf else None,
-                       "frac_fp64_peak": round(eig_tf / FP64_PEAK_TFLOPS, 4) if eig_tf else None},
-        "accuracy": {"n_e_from_D": ne, "n_electrons": s["n_electrons"], "mu": mu},
+        "eigensolve": eig,
+        "accuracy": {"n_e_from_D": ne_b, "n_electrons": s["n_electrons"], "mu": mu_b,
+                     "e_band_per_atom": eb_b / s["n_atoms"]},
     }
     plan.close()
     if not args.no_cpu_baseline:
-        log("[bench] cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(s, args.cpu_sample)
-    print(json.dumps(out), flush=True)
+        log("[bench] cpu baseline: the oracle's whole build of the same input ...")
+        base, ref0, ref1 = oracle_builds(s, log)
+        out["cpu_baseline"] = base
+        out["accuracy"] = accuracy_vs_oracle(s, ref1, D_gpu, mu_b, eb_b, ne_b, ranks)
+        log(f"[bench] accuracy: {out['accuracy']}")
+    return out
 
 
 if __name__ == "__main__":

@@ -20,10 +20,11 @@
  * its device workspaces (cluster matrices, LNO table, spectra, tracked projections).
  *
  * Ordering: every call is enqueued on the plan's HIP stream (set at creation or with
- * ldc_plan_set_stream) in call order.  Entry points that return host values (ranks_out,
- * mu_out, ...) synchronize that stream before returning.  Errors raised inside kernels
- * (non-positive Cholesky pivot, unconverged eigensolver, ...) are reported by the next
- * call that synchronizes; ldc_last_error then names the first failing cluster/atom.
+ * ldc_plan_set_stream) in call order.  ldc_lno (without ranks_out) and ldc_solve never wait
+ * for the device; entry points that return host values (ranks_out, mu_out, ...) synchronize
+ * that stream once, before returning.  Errors raised inside kernels (non-positive Cholesky
+ * pivot, unconverged eigensolver, ...) are reported by the next call that synchronizes;
+ * ldc_last_error then names the first failing cluster/atom.
  *
  * Errors: functions return ldc_status; nothing is thrown across the ABI.  After an error
  * the plan stays usable for new calls.
@@ -52,15 +53,29 @@ typedef enum {
   LDC_ERR_LIMIT = 9         /* a size exceeds a compiled limit (orbitals per atom, members) */
 } ldc_status;
 
-/* Plan options.  Zero-initialised fields take the defaults shown. */
+/* Plan options.  Zero-initialised fields take the defaults shown, except r_L (required) and
+ * kappa (0 is a valid buffer fraction: the short region is then F_i plus the shells needed to
+ * reach N_F; pass a negative kappa for the paper's 0.3). */
+typedef enum {
+  LDC_FP64 = 0,        /* every step in FP64 */
+  LDC_MIXED_FP32 = 1   /* precision form: FP32 storage and products where the method allows it
+                          (see ldc_build); Cholesky, tridiagonal eigensolve and mu in FP64 */
+} ldc_precision;
+
 typedef struct {
   double r_L;          /* cluster radius (same length unit as the positions); required > 0 */
-  double kappa;        /* buffer fraction of the short region, Sec. III (iii); default 0.3
-                          is used when kappa < 0 */
+  double kappa;        /* buffer fraction of the short region, Sec. III (iii); < 0 -> 0.3 */
   double dist_tol;     /* relative tolerance for sphere membership; 0 -> 1e-9 */
   double shell_tol;    /* relative tolerance grouping equal distances into shells; 0 -> 1e-8 */
   int spin_g;          /* spin factor g in N_e = g Tr(D S) (Eq. 13); 0 -> 2 */
   int workgroups;      /* persistent workgroups per per-cluster kernel; 0 -> 2 x CUs */
+  int prec;            /* ldc_precision; 0 -> LDC_FP64 */
+  int batched;         /* 1: size buckets with launch choices from the tuning cache (ldc_tune);
+                          0: one launch per stage over all clusters with the default grids */
+  int use_graph;       /* 1: ldc_build captures a whole build into a HIP graph on its first call
+                          and replays it while pointers and parameters stay the same */
+  const char *tune_cache;  /* path of the tuning cache (JSON) read when batched, written by
+                              ldc_tune; NULL: none.  The string must outlive the plan. */
 } ldc_options;
 
 /* LNO rank rule (Sec. II.B step (iii), Eq. 22): k_j = clamp(#{Re lambda >= lambda_th},
@@ -82,6 +97,11 @@ typedef struct {
   int max_dim_pao;         /* largest cluster dimension with PAOs everywhere (plain DC) */
   int lno_mode;            /* 1 after ldc_lno with a previous density, 0 for plain DC */
   size_t device_bytes;     /* device memory held by the plan */
+  long long blk_total;     /* doubles in one block-sparse matrix (the length of H, S and D) */
+  int n_buckets;           /* size buckets of the current mode */
+  int tuned;               /* launch choices: 0 defaults, 1 from ldc_tune, 2 from the cache */
+  int graph_captures;      /* builds captured into a HIP graph by ldc_build */
+  int graph_replays;       /* ldc_build calls that launched a captured graph */
 } ldc_plan_info;
 
 /* Build the per-geometry plan (Sec. III (i)-(iv)): cluster of every atom (all atoms within
@@ -97,6 +117,14 @@ ldc_status ldc_plan_create(ldc_plan_t *out, int n_atoms, const double *pos, cons
 ldc_status ldc_plan_destroy(ldc_plan_t plan);
 ldc_status ldc_plan_set_stream(ldc_plan_t plan, void *stream);
 ldc_status ldc_plan_query(ldc_plan_t plan, ldc_plan_info *info);
+
+/* The size buckets of the current mode (host arrays of n_buckets entries, any may be NULL):
+ * the range [begin, begin + count) of the processing order (clusters by plain-DC dimension,
+ * largest first), the largest dimension its clusters can have, and the launch grids of the
+ * eight bucketed stages (gather, Cholesky, standard form, band reduction, bulge chasing,
+ * second-stage transform, tridiagonal eigensolve, density rows; 0 = default), row-major
+ * n_buckets x 8. */
+ldc_status ldc_plan_buckets(ldc_plan_t plan, int *begin, int *count, int *dim_bound, int *grids);
 
 /* Host-only planner (no device work, no GPU needed): the members of every atom's cluster,
  * exactly as ldc_plan_create computes them, in the library's member order.
@@ -137,6 +165,33 @@ ldc_status ldc_solve(ldc_plan_t plan, const double *d_H, const double *d_S);
 ldc_status ldc_density(ldc_plan_t plan, double n_electrons, double kT, double *d_D_out, double *mu_out,
                        double *e_band_out, double *n_e_out);
 
+/* One whole density build (Sec. II.C (i)-(v)): ldc_lno from d_Dprev (NULL: plain DC) with
+ * the rank rule, ldc_solve and ldc_density, enqueued without host waits and synchronized once
+ * at the end (mu, e_band, n_e to the host).  The chemical-potential bisection runs as a fixed
+ * number of launches that stop advancing once converged, so the whole sequence is
+ * stream-ordered.  With opt.use_graph the sequence is captured into a HIP graph on the first
+ * call (on a plan whose stream is not the default stream; on the default stream the build runs
+ * eagerly) and replayed by later calls with the same pointers, rank-rule parameters, n_electrons,
+ * kT and bucket set-up (the fixed ranks themselves may change between calls); anything else
+ * re-captures.  With opt.batched every bucketed stage is launched once per size bucket with
+ * the bucket's tuned grid.  Same outputs and errors as ldc_density. */
+ldc_status ldc_build(ldc_plan_t plan, const double *d_H, const double *d_S, const double *d_Dprev,
+                     const ldc_rank_rule *rule, double n_electrons, double kT, double *d_D_out, double *mu_out,
+                     double *e_band_out, double *n_e_out);
+
+/* Autotuner of the batched form: for 1..4 size buckets (equal shares of the processing
+ * order, each still holding >= 2 x CUs clusters) it times every bucketed stage per bucket
+ * with 1, 2, 3 and 4 workgroups per CU (one whole build per candidate, HIP events around
+ * every launch), keeps the fastest grid of each (stage, bucket), times the combination
+ * (best of two whole builds), and keeps the bucket count with the fastest build.  The choice
+ * stays in the plan for this mode and, when opt.tune_cache is set, is written there keyed by
+ * device, HIP runtime version and workload (atom count, mode and the clusters' dimension
+ * bounds).  Runs 6 whole builds per bucket count tried with the given inputs (d_D_out is
+ * overwritten);
+ * best_ms_out (host, may be NULL) receives the tuned build time.  Synchronizes. */
+ldc_status ldc_tune(ldc_plan_t plan, const double *d_H, const double *d_S, const double *d_Dprev,
+                    const ldc_rank_rule *rule, double n_electrons, double kT, double *d_D_out, double *best_ms_out);
+
 /* Density rows at a given chemical potential (no bisection); otherwise as ldc_density. */
 ldc_status ldc_density_at(ldc_plan_t plan, double mu, double kT, double *d_D_out, double *e_band_out,
                           double *n_e_out);
@@ -175,6 +230,10 @@ ldc_status ldc_window_density(ldc_plan_t plan, double e_lo, double e_hi, double 
  * density rows d_D (row i of D comes from cluster i; for the full density matrix this is
  * g sum_{a in i} (D S)_aa).  Inputs in the layout of S. */
 ldc_status ldc_mulliken(ldc_plan_t plan, const double *d_D, const double *d_S, double *d_q);
+
+/* ldc_reference_populations: the neutral populations q0_i = N_e M_i / sum_j M_j of the toy
+ * loop (every atom at the system's filling) into the device array d_q0 (n_atoms). */
+ldc_status ldc_reference_populations(ldc_plan_t plan, double n_electrons, double *d_q0);
 
 /* ldc_potential: H_ij = H0_ij + (v_i + v_j)/2 S_ij on every pattern block (a uniform v shifts
  * every cluster eigenvalue by v).  d_H may be d_H0 (in place). */

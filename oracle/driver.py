@@ -57,6 +57,16 @@ def _map(fn, items, workers):
         return pool.map(fn, items, chunksize=max(1, len(items) // (8 * workers)))
 
 
+def _row_budget():
+    """Bytes of coefficient rows a build may keep between its two passes: a quarter of the
+    free host memory (at least 3 GB)."""
+    try:
+        import psutil
+        return max(3e9, 0.25 * float(psutil.virtual_memory().available))
+    except Exception:  # pragma: no cover
+        return 3e9
+
+
 def default_workers():
     return int(os.environ.get("LDC_ORACLE_WORKERS", min(16, os.cpu_count() or 1)))
 
@@ -95,7 +105,7 @@ def density_build(sysd, dprev=None, fixed_rank=None, mu=None, clusters=None, wor
         r = regions[i]
         est += 8 * 9 * (r.n_fna + 1) * 9 * len(r.members)
     est = est / max(1, min(len(idx), 8)) * len(idx)
-    keep_rows = est < 3e9
+    keep_rows = est < _row_budget()
     _G.update(sys=sysd, regions=regions, us=us, ranks=ranks, keep_rows=keep_rows and mu is None,
               mu=mu, kT=kT, energy=energy, window=window)
     res = dict(_map(_solve, idx, workers))

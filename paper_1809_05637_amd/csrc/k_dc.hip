@@ -526,15 +526,18 @@ __global__ void __launch_bounds__(256, 3) stedc_kernel(int n_clusters, const int
 }
 
 void launch_stedc(Plan &p) {
-  const size_t lds = (size_t)p.max_dim * DcLds::kBytesPerRow + DcLds::kFixedBytes;
+  const int dm = cur_dim(p);
+  const size_t lds = (size_t)dm * DcLds::kBytesPerRow + DcLds::kFixedBytes;
   // above 64 KB (clusters of more than about 940 rows) the dynamic LDS limit must be raised
   if (lds > 64 * 1024)
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(stedc_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
-  // three workgroups per CU (at most 168 VGPRs; the LDS of a 711-row cluster is 51 KB): more
-  // waves in flight for the latency-bound merges
-  hipLaunchKernelGGL(stedc_kernel, dim3(3 * p.n_cu), dim3(kWG), lds, p.stream, p.n_atoms, p.d_order, p.d_vec,
-                     p.d_vec_off, p.d_ivec, p.d_ivec_off, p.d_dmax, p.d_dim, p.d_n_orb, p.d_status, p.max_dim);
+  // default three workgroups per CU (at most 168 VGPRs; the LDS of a 711-row cluster is 51 KB):
+  // more waves in flight for the latency-bound merges
+  const int n = cur_count(p);
+  const int grid = std::max(1, std::min(stage_grid(p, kTStedc, 3 * p.n_cu), n));
+  hipLaunchKernelGGL(stedc_kernel, dim3(grid), dim3(kWG), lds, p.stream, n, cur_order(p), p.d_vec, p.d_vec_off,
+                     p.d_ivec, p.d_ivec_off, p.d_dmax, p.d_dim, p.d_n_orb, p.d_status, dm);
 }
 
 }  // namespace ldc

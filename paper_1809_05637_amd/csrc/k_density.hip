@@ -1,11 +1,14 @@
 // Common chemical potential and density rows (Sec. II.C (iv)-(v); Eq. 13, 16, 24, 27).
 //
 // N(mu) = g sum_i sum_mu f((eps_mu - mu)/kT) w_mu is evaluated by a grid of workgroups
-// (one partial per workgroup, fixed cluster assignment) and combined in order by a
-// one-workgroup kernel that also performs the bisection update, so every run takes the
-// same decisions.  One launch pair advances the bisection by kMuLevels halvings: the grid
-// evaluates N at every node of the next kMuLevels levels of the bisection tree (each node the
-// midpoint the halving rule would form on that path), and the combine walks the tree.  Density rows of atom i: with C = L^{-T} Q Z the cluster eigenvectors,
+// (one partial per workgroup, fixed cluster assignment) and combined in order by the last
+// workgroup to finish, which also performs the bisection update, so every run takes the same
+// decisions.  One launch advances the bisection by kMuLevels halvings: the grid evaluates N at
+// every node of the next kMuLevels levels of the bisection tree (each node the midpoint the
+// halving rule would form on that path), and the combine walks the tree.  The host enqueues a
+// fixed number of launches; those after convergence return at once.
+//
+// Density rows of atom i: with C = L^{-T} Q Z the cluster eigenvectors,
 //   rho^(i)(:, i) = C f C_i^T = L^{-T} Q Z (f o u),  u = Z^T Q^T L^{-1} E_i = C_i^T,
 // so only the tracked u, the merge records (Z y), the stored reflectors (Q r) and the
 // trailing rows of L (P = F_i placed last) are needed.
@@ -27,89 +30,26 @@ __device__ __noinline__ void density_q2_lds(const double *A, int n, double *Xs, 
 // state layout of Plan::d_mu
 enum { MU_LO = 0, MU_HI, MU_DONE, MU_IT, MU_SUMW, MU_NE, MU_KT, MU_G, MU_MU, MU_BAD };
 
-// the tree's node count and the per-workgroup partial stride (kMuLevels halvings per launch pair)
+// the tree's node count and the per-workgroup partial stride (kMuLevels halvings per launch)
 constexpr int kMuNodes = (1 << kMuLevels) - 1, kMuStride = 16;
 static_assert(kMuNodes < kMuStride, "tree partials fit the stride");
 
-__global__ void __launch_bounds__(256) mu_partial_kernel(int mode, int n_clusters, const double *__restrict__ vec,
-                                                         const long long *__restrict__ vec_off,
-                                                         const int *__restrict__ dmax, const int *__restrict__ dim,
-                                                         const double *__restrict__ state,
-                                                         double *__restrict__ partial) {
-  __shared__ double red[8];
-  if (mode == 1 && state[MU_DONE] != 0.0) return;
-  const double kT = state[MU_KT];
-  if (mode == 0) {
-    double a0 = 1e300, a1 = -1e300, a2 = 0.0;
-    for (int c = blockIdx.x; c < n_clusters; c += gridDim.x) {
-      const VecLayout vl = VecLayout::make(dmax[c]);
-      const double *lam = vec + vec_off[c] + vl.lam;
-      const double *w = vec + vec_off[c] + vl.w;
-      const int n = dim[c];
-      for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        a0 = fmin(a0, lam[i]);
-        a1 = fmax(a1, lam[i]);
-        a2 += w[i];
-      }
-    }
-    const double s = block_sum(a2, red);
-    const double mn = -block_max(-a0, red);
-    const double mx = block_max(a1, red);
-    if (threadIdx.x == 0) {
-      partial[blockIdx.x * kMuStride + 0] = mn;
-      partial[blockIdx.x * kMuStride + 1] = mx;
-      partial[blockIdx.x * kMuStride + 2] = s;
-    }
-    return;
-  }
-  // the tree's nodes in heap order: node k covers (nl, nh), its children 2k + 1 (hi = mid) and
-  // 2k + 2 (lo = mid), each evaluated at its midpoint
-  double nl[kMuNodes], nh[kMuNodes], m[kMuNodes], acc[kMuNodes];
-  nl[0] = state[MU_LO];
-  nh[0] = state[MU_HI];
-  m[0] = 0.5 * (nl[0] + nh[0]);
-#pragma unroll
-  for (int k = 1; k < kMuNodes; ++k) {
-    const int p = (k - 1) / 2;
-    nl[k] = (k == 2 * p + 1) ? nl[p] : m[p];
-    nh[k] = (k == 2 * p + 1) ? m[p] : nh[p];
-    m[k] = 0.5 * (nl[k] + nh[k]);
-  }
-#pragma unroll
-  for (int k = 0; k < kMuNodes; ++k) acc[k] = 0.0;
-  for (int c = blockIdx.x; c < n_clusters; c += gridDim.x) {
-    const VecLayout vl = VecLayout::make(dmax[c]);
-    const double *lam = vec + vec_off[c] + vl.lam;
-    const double *w = vec + vec_off[c] + vl.w;
-    const int n = dim[c];
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const double li = lam[i], wi = w[i];
-#pragma unroll
-      for (int k = 0; k < kMuNodes; ++k) acc[k] += fermi_fast((li - m[k]) / kT) * wi;
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < kMuNodes; ++k) {
-    const double s = block_sum(acc[k], red);
-    if (threadIdx.x == 0) partial[blockIdx.x * kMuStride + k] = s;
-  }
-}
-
-// Combines the per-workgroup partials in a fixed order (lane l adds partials l, l + 64, ...,
-// then a fixed DPP tree) and updates the bisection state; one wavefront, every lane takes the
-// same decisions and lane 0 writes the state.
-__global__ void __launch_bounds__(64) mu_finalize_kernel(int mode, int nparts, double *__restrict__ state,
-                                                         const double *__restrict__ partial, DevStatus *st) {
-  const int lane = threadIdx.x;
-  if (mode == 1 && state[MU_DONE] != 0.0) return;
+// Combine of the per-workgroup partials in a fixed order (lane l adds partials l, l + 64, ...,
+// then a fixed DPP tree) and the bisection update; one wavefront, every lane takes the same
+// decisions and lane 0 writes the state.  Runs in the last workgroup of mu_step_kernel to
+// finish; the partials are read with coherent loads after the device-scope fence that
+// follows that workgroup's ticket.
+__device__ void mu_combine(int mode, int nparts, double *__restrict__ state, const double *partial, DevStatus *st) {
+  const int lane = threadIdx.x & 63;
+  const volatile double *vp = partial;
   const double kT = state[MU_KT], g = state[MU_G], ne = state[MU_NE];
   double lo, hi;
   if (mode == 0) {
     double s = 0.0, mn = 1e300, mx = -1e300;
     for (int b = lane; b < nparts; b += 64) {
-      s += partial[b * kMuStride + 2];
-      mn = fmin(mn, partial[b * kMuStride + 0]);
-      mx = fmax(mx, partial[b * kMuStride + 1]);
+      s += vp[b * kMuStride + 2];
+      mn = fmin(mn, vp[b * kMuStride + 0]);
+      mx = fmax(mx, vp[b * kMuStride + 1]);
     }
     s = wave_sum(s);
     mn = -wave_max(-mn);
@@ -133,49 +73,129 @@ __global__ void __launch_bounds__(64) mu_finalize_kernel(int mode, int nparts, d
       state[MU_MU] = mid;
       if (hi - lo <= 4e-16 * fmax(1.0, fabs(mid))) state[MU_DONE] = 1.0;
     }
+    return;
+  }
+  // N at every node of the evaluated tree, then kMuLevels halvings down it, each with the
+  // stopping test
+  double sn[kMuNodes];
+#pragma unroll
+  for (int k = 0; k < kMuNodes; ++k) sn[k] = 0.0;
+  for (int b = lane; b < nparts; b += 64) {
+#pragma unroll
+    for (int k = 0; k < kMuNodes; ++k) sn[k] += vp[b * kMuStride + k];
+  }
+#pragma unroll
+  for (int k = 0; k < kMuNodes; ++k) sn[k] = wave_sum(sn[k]);
+  lo = state[MU_LO];
+  hi = state[MU_HI];
+  double it = state[MU_IT];
+  bool done = false;
+  int node = 0;
+  for (int level = 0; level < kMuLevels; ++level) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < kMuNodes; ++k) s = (k == node) ? sn[k] : s;
+    const double mid = 0.5 * (lo + hi);
+    if (g * s < ne) {
+      lo = mid;
+      node = 2 * node + 2;
+    } else {
+      hi = mid;
+      node = 2 * node + 1;
+    }
+    it += 1.0;
+    const double mid2 = 0.5 * (lo + hi);
+    if (hi - lo <= 4e-16 * fmax(1.0, fabs(mid2)) || it >= 200.0) {
+      done = true;
+      break;
+    }
+  }
+  if (lane == 0) {
+    state[MU_IT] = it;
+    if (done) state[MU_DONE] = 1.0;
+    state[MU_LO] = lo;
+    state[MU_HI] = hi;
+    state[MU_MU] = 0.5 * (lo + hi);
+  }
+}
+
+// One step of the bisection over all clusters (mode 1), or its set-up (mode 0: the spectrum's
+// range and the total weight).  Every workgroup forms its partial sums over a fixed set of
+// clusters; the last workgroup to finish (atomic ticket on counter, which it resets) combines
+// them.  Once the state says done, a launch returns at once, so the host can enqueue a fixed
+// number of steps (enough for the 200-halving limit) without waiting for the result.
+__global__ void __launch_bounds__(256) mu_step_kernel(int mode, int n_clusters, const double *__restrict__ vec,
+                                                      const long long *__restrict__ vec_off,
+                                                      const int *__restrict__ dmax, const int *__restrict__ dim,
+                                                      double *__restrict__ state, double *__restrict__ partial,
+                                                      int *__restrict__ counter, DevStatus *st) {
+  __shared__ double red[8];
+  __shared__ int last;
+  if (mode == 1 && state[MU_DONE] != 0.0) return;
+  const double kT = state[MU_KT];
+  if (mode == 0) {
+    double a0 = 1e300, a1 = -1e300, a2 = 0.0;
+    for (int c = blockIdx.x; c < n_clusters; c += gridDim.x) {
+      const VecLayout vl = VecLayout::make(dmax[c]);
+      const double *lam = vec + vec_off[c] + vl.lam;
+      const double *w = vec + vec_off[c] + vl.w;
+      const int n = dim[c];
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        a0 = fmin(a0, lam[i]);
+        a1 = fmax(a1, lam[i]);
+        a2 += w[i];
+      }
+    }
+    const double s = block_sum(a2, red);
+    const double mn = -block_max(-a0, red);
+    const double mx = block_max(a1, red);
+    if (threadIdx.x == 0) {
+      partial[blockIdx.x * kMuStride + 0] = mn;
+      partial[blockIdx.x * kMuStride + 1] = mx;
+      partial[blockIdx.x * kMuStride + 2] = s;
+    }
   } else {
-    // N at every node of the evaluated tree, then kMuLevels halvings down it, each with the
-    // stopping test
-    double sn[kMuNodes];
+    // the tree's nodes in heap order: node k covers (nl, nh), its children 2k + 1 (hi = mid)
+    // and 2k + 2 (lo = mid), each evaluated at its midpoint
+    double nl[kMuNodes], nh[kMuNodes], m[kMuNodes], acc[kMuNodes];
+    nl[0] = state[MU_LO];
+    nh[0] = state[MU_HI];
+    m[0] = 0.5 * (nl[0] + nh[0]);
 #pragma unroll
-    for (int k = 0; k < kMuNodes; ++k) sn[k] = 0.0;
-    for (int b = lane; b < nparts; b += 64) {
-#pragma unroll
-      for (int k = 0; k < kMuNodes; ++k) sn[k] += partial[b * kMuStride + k];
+    for (int k = 1; k < kMuNodes; ++k) {
+      const int p = (k - 1) / 2;
+      nl[k] = (k == 2 * p + 1) ? nl[p] : m[p];
+      nh[k] = (k == 2 * p + 1) ? m[p] : nh[p];
+      m[k] = 0.5 * (nl[k] + nh[k]);
     }
 #pragma unroll
-    for (int k = 0; k < kMuNodes; ++k) sn[k] = wave_sum(sn[k]);
-    lo = state[MU_LO];
-    hi = state[MU_HI];
-    double it = state[MU_IT];
-    bool done = false;
-    int node = 0;
-    for (int level = 0; level < kMuLevels; ++level) {
-      double s = 0.0;
+    for (int k = 0; k < kMuNodes; ++k) acc[k] = 0.0;
+    for (int c = blockIdx.x; c < n_clusters; c += gridDim.x) {
+      const VecLayout vl = VecLayout::make(dmax[c]);
+      const double *lam = vec + vec_off[c] + vl.lam;
+      const double *w = vec + vec_off[c] + vl.w;
+      const int n = dim[c];
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double li = lam[i], wi = w[i];
 #pragma unroll
-      for (int k = 0; k < kMuNodes; ++k) s = (k == node) ? sn[k] : s;
-      const double mid = 0.5 * (lo + hi);
-      if (g * s < ne) {
-        lo = mid;
-        node = 2 * node + 2;
-      } else {
-        hi = mid;
-        node = 2 * node + 1;
-      }
-      it += 1.0;
-      const double mid2 = 0.5 * (lo + hi);
-      if (hi - lo <= 4e-16 * fmax(1.0, fabs(mid2)) || it >= 200.0) {
-        done = true;
-        break;
+        for (int k = 0; k < kMuNodes; ++k) acc[k] += fermi_fast((li - m[k]) / kT) * wi;
       }
     }
-    if (lane == 0) {
-      state[MU_IT] = it;
-      if (done) state[MU_DONE] = 1.0;
-      state[MU_LO] = lo;
-      state[MU_HI] = hi;
-      state[MU_MU] = 0.5 * (lo + hi);
+#pragma unroll
+    for (int k = 0; k < kMuNodes; ++k) {
+      const double s = block_sum(acc[k], red);
+      if (threadIdx.x == 0) partial[blockIdx.x * kMuStride + k] = s;
     }
+  }
+  // ticket: the partial stores above are made visible before the increment
+  __threadfence();
+  if (threadIdx.x == 0) last = (atomicAdd(counter, 1) == (int)gridDim.x - 1);
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  if (threadIdx.x < 64) {
+    mu_combine(mode, gridDim.x, state, partial, st);
+    if (threadIdx.x == 0) atomicExch(counter, 0);
   }
 }
 
@@ -314,39 +334,72 @@ __global__ void sum_pairs_kernel(int n, const double *__restrict__ partial, doub
 
 void launch_mu_init(Plan &p, double kT) {
   (void)kT;
-  hipLaunchKernelGGL(mu_partial_kernel, dim3(p.workgroups), dim3(kWG), 0, p.stream, 0, p.n_atoms, p.d_vec,
-                     p.d_vec_off, p.d_dmax, p.d_dim, p.d_mu, p.d_partial);
-  hipLaunchKernelGGL(mu_finalize_kernel, dim3(1), dim3(64), 0, p.stream, 0, p.workgroups, p.d_mu, p.d_partial,
-                     p.d_status);
+  hipLaunchKernelGGL(mu_step_kernel, dim3(p.workgroups), dim3(kWG), 0, p.stream, 0, p.n_atoms, p.d_vec,
+                     p.d_vec_off, p.d_dmax, p.d_dim, p.d_mu, p.d_partial, p.d_counter, p.d_status);
 }
 
 void launch_mu_step(Plan &p, double, double, double) {
-  hipLaunchKernelGGL(mu_partial_kernel, dim3(p.workgroups), dim3(kWG), 0, p.stream, 1, p.n_atoms, p.d_vec,
-                     p.d_vec_off, p.d_dmax, p.d_dim, p.d_mu, p.d_partial);
-  hipLaunchKernelGGL(mu_finalize_kernel, dim3(1), dim3(64), 0, p.stream, 1, p.workgroups, p.d_mu, p.d_partial,
-                     p.d_status);
+  hipLaunchKernelGGL(mu_step_kernel, dim3(p.workgroups), dim3(kWG), 0, p.stream, 1, p.n_atoms, p.d_vec,
+                     p.d_vec_off, p.d_dmax, p.d_dim, p.d_mu, p.d_partial, p.d_counter, p.d_status);
 }
 
 void launch_density(Plan &p, int mode, double *d_D, const double *d_H, const double *d_S, double w_lo, double w_hi,
                     double w_kT) {
   double *cl_partial = p.d_partial + kMuStride * p.workgroups;
-  // the Q2 product runs in LDS when the n x M rows and three reflector runs of the largest
-  // cluster still let two workgroups share a CU (72 KB each besides the 6 KB of static LDS)
+  // the Q2 product runs in LDS when the n x M rows and three reflector runs of the bucket's
+  // largest cluster still let two workgroups share a CU (72 KB each besides the 6 KB of static
+  // LDS)
+  const int dm = cur_dim(p);
   const size_t base = sizeof(double) * kQapplyLds;
-  const size_t q2 = sizeof(double) * (size_t)p.max_dim * (size_t)(p.mmax + 3);
+  const size_t q2 = sizeof(double) * (size_t)dm * (size_t)(p.mmax + 3);
   int q2_lds = q2 <= 72 * 1024;
   if (q2_lds && q2 > 64 * 1024 &&
       hipFuncSetAttribute(reinterpret_cast<const void *>(density_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)q2) != hipSuccess)
     q2_lds = 0;
   const size_t lds = q2_lds ? std::max(base, q2) : base;
-  hipLaunchKernelGGL(density_kernel, dim3(p.workgroups), dim3(kWG), lds, p.stream, mode, w_lo, w_hi, w_kT, p.n_atoms,
-                     p.d_order, p.d_mat,
-                     p.d_mat_off, p.d_vec, p.d_vec_off, p.d_ivec, p.d_ivec_off, p.d_dmax, p.d_dim, p.d_n_orb,
+  const int n = cur_count(p);
+  const int grid = std::max(1, std::min(stage_grid(p, kTDensity, p.workgroups), n));
+  hipLaunchKernelGGL(density_kernel, dim3(grid), dim3(kWG), lds, p.stream, mode, w_lo, w_hi, w_kT, n, cur_order(p),
+                     p.d_mat, p.d_mat_off, p.d_vec, p.d_vec_off, p.d_ivec, p.d_ivec_off, p.d_dmax, p.d_dim, p.d_n_orb,
                      p.d_p_rows, p.d_mem_ptr, p.d_mem_atom, p.d_fna_ptr, p.d_fna_blk, p.d_blk_off, p.d_mu, d_H, d_S,
-                     d_D, cl_partial, q2_lds, p.max_dim);
+                     d_D, cl_partial, q2_lds, dm);
+}
+
+void launch_density_sums(Plan &p, int mode) {
+  double *cl_partial = p.d_partial + kMuStride * p.workgroups;
   hipLaunchKernelGGL(sum_pairs_kernel, dim3(1), dim3(kWG), 0, p.stream, p.n_atoms, cl_partial,
                      p.d_mu + (mode == kRowsWindow ? 20 : (mode == kRowsEnergy ? 18 : 16)));
+}
+
+// State of a density: fixed == 0 prepares a bisection (n_e, kT, g), fixed != 0 sets mu and
+// marks the bisection done.
+__global__ void state_init_kernel(double *state, double n_e, double kT, double g, int fixed, double mu) {
+  const int t = threadIdx.x;
+  if (t < 32) state[t] = 0.0;
+  __syncthreads();
+  if (t == 0) {
+    state[MU_NE] = n_e;
+    state[MU_KT] = kT;
+    state[MU_G] = g;
+    if (fixed) {
+      state[MU_DONE] = 1.0;
+      state[MU_MU] = mu;
+    }
+  }
+}
+
+void launch_state_init(Plan &p, double n_e, double kT, double g, int fixed, double mu) {
+  hipLaunchKernelGGL(state_init_kernel, dim3(1), dim3(64), 0, p.stream, p.d_mu, n_e, kT, g, fixed, mu);
+}
+
+__global__ void fill_int_kernel(int *d, int n, int v) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) d[i] = v;
+}
+
+void launch_fill_int(Plan &p, int *d, int n, int v) {
+  const int blocks = std::max(1, std::min(256, (n + 255) / 256));
+  hipLaunchKernelGGL(fill_int_kernel, dim3(blocks), dim3(256), 0, p.stream, d, n, v);
 }
 
 }  // namespace ldc

@@ -84,6 +84,19 @@ __global__ void __launch_bounds__(256) scf_mix_kernel(int n_atoms, const double 
   }
 }
 
+// Neutral reference populations of the toy loop: q0_i = N_e M_i / sum_j M_j.
+__global__ void reference_populations_kernel(int n_atoms, const int *__restrict__ n_orb, double n_e, double n_basis,
+                                             double *__restrict__ q0) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_atoms; i += gridDim.x * blockDim.x)
+    q0[i] = n_e * (double)n_orb[i] / n_basis;
+}
+
+void launch_reference_populations(Plan &p, double n_electrons, double *d_q0) {
+  const int blocks = std::max(1, std::min(256, (p.n_atoms + 255) / 256));
+  hipLaunchKernelGGL(reference_populations_kernel, dim3(blocks), dim3(256), 0, p.stream, p.n_atoms, p.d_n_orb,
+                     n_electrons, (double)p.n_basis, d_q0);
+}
+
 void launch_mulliken(Plan &p, const double *d_D, const double *d_S, double *d_q, double g) {
   const int wgs = std::max(1, std::min(p.workgroups * 4, (p.n_atoms + 3) / 4));
   hipLaunchKernelGGL(mulliken_kernel, dim3(wgs), dim3(kWG), 0, p.stream, p.n_atoms, p.d_row_elem, d_D, d_S, g, d_q);

@@ -481,25 +481,35 @@ __global__ void __launch_bounds__(256, 2) sygst_kernel(int n_clusters, const int
 }
 
 // ---------------------------------------------------------------------------------------
+void launch_lno_blocks(Plan &p, const double *d_H, const double *d_S) {
+  hipLaunchKernelGGL(lno_blocks_kernel, dim3(std::min(p.n_atoms, 8 * p.n_cu)), dim3(kWG), 0, p.stream, p.n_atoms,
+                     p.d_row_ptr, p.d_col, p.d_n_orb, p.d_blk_off, p.d_rank, p.d_U, d_H, d_S, p.d_lno_blk,
+                     p.blk_total);
+}
+
 void launch_gather(Plan &p, const double *d_H, const double *d_S) {
-  if (p.lno_mode)
-    hipLaunchKernelGGL(lno_blocks_kernel, dim3(std::min(p.n_atoms, 8 * p.n_cu)), dim3(kWG), 0, p.stream, p.n_atoms,
-                       p.d_row_ptr, p.d_col, p.d_n_orb, p.d_blk_off, p.d_rank, p.d_U, d_H, d_S, p.d_lno_blk,
-                       p.blk_total);
-  // four workgroups per CU: the dense pass is bound by memory traffic, not by registers or LDS
-  hipLaunchKernelGGL(gather_kernel, dim3(4 * p.n_cu), dim3(kWG), sizeof(unsigned short) * p.max_dim, p.stream, p.n_atoms, p.d_order, p.d_mem_ptr,
-                     p.d_mem_atom, p.d_mem_long, p.d_pair_ptr, p.d_pair_ab, p.d_pair_blk, p.d_n_orb, p.d_blk_off, d_H,
-                     d_S, p.lno_mode, p.d_rank, p.d_lno_blk, p.blk_total, p.d_mat, p.d_mat_off, p.d_dmax, p.d_dim);
+  // default four workgroups per CU: the dense pass is bound by memory traffic, not by
+  // registers or LDS
+  const int n = cur_count(p);
+  const int grid = std::max(1, std::min(stage_grid(p, kTGather, 4 * p.n_cu), n));
+  hipLaunchKernelGGL(gather_kernel, dim3(grid), dim3(kWG), sizeof(unsigned short) * cur_dim(p), p.stream, n,
+                     cur_order(p), p.d_mem_ptr, p.d_mem_atom, p.d_mem_long, p.d_pair_ptr, p.d_pair_ab, p.d_pair_blk,
+                     p.d_n_orb, p.d_blk_off, d_H, d_S, p.lno_mode, p.d_rank, p.d_lno_blk, p.blk_total, p.d_mat,
+                     p.d_mat_off, p.d_dmax, p.d_dim);
 }
 
 void launch_potrf(Plan &p) {
-  hipLaunchKernelGGL(potrf_kernel, dim3(p.workgroups), dim3(kWG), 0, p.stream, p.n_atoms, p.d_order, p.d_mat,
-                     p.d_mat_off, p.d_dmax, p.d_dim, p.d_status);
+  const int n = cur_count(p);
+  const int grid = std::max(1, std::min(stage_grid(p, kTPotrf, p.workgroups), n));
+  hipLaunchKernelGGL(potrf_kernel, dim3(grid), dim3(kWG), 0, p.stream, n, cur_order(p), p.d_mat, p.d_mat_off, p.d_dmax,
+                     p.d_dim, p.d_status);
 }
 
 void launch_sygst(Plan &p) {
-  hipLaunchKernelGGL(sygst_kernel, dim3(p.workgroups), dim3(kWG), 0, p.stream, p.n_atoms, p.d_order, p.d_mat,
-                     p.d_mat_off, p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb);
+  const int n = cur_count(p);
+  const int grid = std::max(1, std::min(stage_grid(p, kTSygst, p.workgroups), n));
+  hipLaunchKernelGGL(sygst_kernel, dim3(grid), dim3(kWG), 0, p.stream, n, cur_order(p), p.d_mat, p.d_mat_off,
+                     p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb);
 }
 
 }  // namespace ldc

@@ -599,36 +599,42 @@ __global__ void __launch_bounds__(256, 2) q2x_kernel(int n_clusters, const int *
 
 // ---------------------------------------------------------------------------------------
 void launch_sy2sb(Plan &p) {
-  const size_t lds =
-      sizeof(double) * std::max({(size_t)LEAF * p.max_dim, (size_t)kGemmLds, (size_t)kGemmLdsTall, (size_t)kQapplyLds, (size_t)kAtbLds});
-  hipLaunchKernelGGL(sy2sb_kernel, dim3(p.workgroups), dim3(kWG), lds, p.stream, p.n_atoms, p.d_order, p.d_mat,
-                     p.d_mat_off, p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb);
+  const size_t lds = sizeof(double) * std::max({(size_t)LEAF * cur_dim(p), (size_t)kGemmLds, (size_t)kGemmLdsTall,
+                                                (size_t)kQapplyLds, (size_t)kAtbLds});
+  const int n = cur_count(p);
+  const int grid = std::max(1, std::min(stage_grid(p, kTSy2sb, p.workgroups), n));
+  hipLaunchKernelGGL(sy2sb_kernel, dim3(grid), dim3(kWG), lds, p.stream, n, cur_order(p), p.d_mat, p.d_mat_off,
+                     p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb);
 }
 
 void launch_sb2st(Plan &p) {
-  // two workgroups per compute unit: more clusters in flight push the bands out of the caches
-  // (measured with four waves per workgroup: 1, 1.5, 2 and 4 per CU give 190, 154, 133 and
-  // 149 ms on the 3920-atom slab; eight waves at 2 per CU: 122 ms)
-  const int wgs = std::max(1, std::min(p.workgroups, p.n_atoms));
-  hipLaunchKernelGGL(sb2st_kernel, dim3(wgs), dim3(64 * kChaseWaves), 0, p.stream, p.n_atoms, p.d_order, p.d_mat, p.d_mat_off,
-                     p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim);
+  // default two workgroups per compute unit: more clusters in flight push the bands out of the
+  // caches (measured with four waves per workgroup: 1, 1.5, 2 and 4 per CU give 190, 154, 133
+  // and 149 ms on the 3920-atom slab; eight waves at 2 per CU: 122 ms)
+  const int n = cur_count(p);
+  const int grid = std::max(1, std::min(stage_grid(p, kTSb2st, p.workgroups), n));
+  hipLaunchKernelGGL(sb2st_kernel, dim3(grid), dim3(64 * kChaseWaves), 0, p.stream, n, cur_order(p), p.d_mat,
+                     p.d_mat_off, p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim);
 }
 
 void launch_q2x(Plan &p) {
-  const size_t lds = sizeof(double) * (size_t)p.max_dim * (size_t)(p.mmax + 3);
+  const int dm = cur_dim(p);
+  const size_t lds = sizeof(double) * (size_t)dm * (size_t)(p.mmax + 3);
   int dev = 0, lds_max = 0;
   const bool fits = hipGetDevice(&dev) == hipSuccess &&
                     hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
                     lds <= (size_t)lds_max &&
                     hipFuncSetAttribute(reinterpret_cast<const void *>(q2x_lds_kernel),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess;
+  const int n = cur_count(p);
   if (fits) {
-    const int wgs = std::max(1, std::min(2 * p.n_cu, 2 * p.n_atoms));
-    hipLaunchKernelGGL(q2x_lds_kernel, dim3(wgs), dim3(kWG), lds, p.stream, p.n_atoms, p.d_order, p.d_mat,
-                       p.d_mat_off, p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb, p.max_dim);
+    const int grid = std::max(1, std::min(stage_grid(p, kTQ2x, 2 * p.n_cu), 2 * n));
+    hipLaunchKernelGGL(q2x_lds_kernel, dim3(grid), dim3(kWG), lds, p.stream, n, cur_order(p), p.d_mat, p.d_mat_off,
+                       p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb, dm);
   } else {
-    hipLaunchKernelGGL(q2x_kernel, dim3(p.workgroups), dim3(kWG), 0, p.stream, p.n_atoms, p.d_order, p.d_mat,
-                       p.d_mat_off, p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb);
+    const int grid = std::max(1, std::min(stage_grid(p, kTQ2x, p.workgroups), n));
+    hipLaunchKernelGGL(q2x_kernel, dim3(grid), dim3(kWG), 0, p.stream, n, cur_order(p), p.d_mat, p.d_mat_off, p.d_vec,
+                       p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb);
   }
 }
 

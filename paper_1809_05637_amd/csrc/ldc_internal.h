@@ -34,6 +34,33 @@ struct DcLayout {
   }
 };
 
+// Stages whose launch is chosen per size bucket (grid of the persistent launch).
+enum TunedStage { kTGather = 0, kTPotrf, kTSygst, kTSy2sb, kTSb2st, kTQ2x, kTStedc, kTDensity, kNumTuned };
+
+// A size bucket: a contiguous range of the processing order (clusters sorted by dimension,
+// largest first), the largest dimension its clusters can have in the current mode (LDS sizes
+// and strides of the bucket's launches follow it), and the launch grid of every tuned stage
+// (0: the stage's default).
+struct Bucket {
+  int begin = 0, count = 0;
+  int dim_bound = 0;
+  int grid[kNumTuned] = {};
+};
+
+// Key of a captured build: the graph is replayed only for the same pointers and parameters.
+struct BuildKey {
+  const void *H = nullptr, *S = nullptr, *Dprev = nullptr, *Dout = nullptr;
+  double lambda_th = 0.0, n_e = 0.0, kT = 0.0;
+  int k_min = 0, k_max = 0, has_fixed = 0, prec = 0;
+  long long bucket_sig = 0;
+  hipStream_t stream = nullptr;
+  bool operator==(const BuildKey &o) const {
+    return H == o.H && S == o.S && Dprev == o.Dprev && Dout == o.Dout && lambda_th == o.lambda_th &&
+           n_e == o.n_e && kT == o.kT && k_min == o.k_min && k_max == o.k_max && has_fixed == o.has_fixed &&
+           prec == o.prec && bucket_sig == o.bucket_sig && stream == o.stream;
+  }
+};
+
 struct Plan {
   int n_atoms = 0, nnzb = 0, n_basis = 0, mmax = 0;
   ldc_options opt{};
@@ -96,6 +123,27 @@ struct Plan {
   double stage_ms[LDC_NUM_STAGES] = {};
   int prof_builds = 0;
 
+  // size buckets of the current mode and the one being launched (launchers read their range,
+  // dimension bound and grid from it)
+  std::vector<Bucket> buckets;
+  std::vector<int> dim_bound;       // per cluster: largest dimension in the current mode
+  int bucket_mode = -1;             // the bound the buckets were made for (-1: none yet)
+  std::string bucket_wkey;          // workload key of the current bounds
+  const Bucket *cur = nullptr;
+  // tuning: per (stage, bucket) HIP events around the bucket's launch
+  int tuning = 0;
+  std::vector<hipEvent_t> tune_ev;  // 2 per (stage, bucket)
+  std::string tune_source;          // where the current launch choices came from
+
+  // pinned host staging (fixed ranks in, state and status out) and the captured build
+  int *h_fixed = nullptr;
+  double *h_out = nullptr;          // 32 state doubles, then the status word
+  hipEvent_t ev_fixed = nullptr;    // the last copy out of h_fixed
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  BuildKey graph_key;
+  int graph_builds = 0, graph_captures = 0;
+
   const double *last_H = nullptr, *last_S = nullptr;
   int solved = 0;
   int has_density = 0;              // a density was built since the last ldc_solve
@@ -155,9 +203,20 @@ struct IvecLayout {
 // host planner
 ldc_status build_regions(Plan &p, const double *pos, const double *cell, const int *periodic);
 
+// launch range of the current bucket (the whole processing order when no bucket is set)
+inline const int *cur_order(const Plan &p) { return p.cur ? p.d_order + p.cur->begin : p.d_order; }
+inline int cur_count(const Plan &p) { return p.cur ? p.cur->count : p.n_atoms; }
+inline int cur_dim(const Plan &p) { return p.cur ? p.cur->dim_bound : p.max_dim; }
+inline int stage_grid(const Plan &p, int stage, int dflt) {
+  const int g = p.cur ? p.cur->grid[stage] : 0;
+  return g > 0 ? g : dflt;
+}
+
 // kernel launchers (each enqueues on p.stream)
 void launch_lambda(Plan &p, const double *d_S, const double *d_D);
 void launch_lno_eig(Plan &p, const double *d_S, double lambda_th, int k_min, int k_max);
+// LNO-contracted pattern blocks (Eq. 26), once per ldc_solve in LNO mode
+void launch_lno_blocks(Plan &p, const double *d_H, const double *d_S);
 void launch_gather(Plan &p, const double *d_H, const double *d_S);
 void launch_potrf(Plan &p);
 void launch_sygst(Plan &p);
@@ -165,8 +224,10 @@ void launch_sy2sb(Plan &p);
 void launch_sb2st(Plan &p);
 void launch_q2x(Plan &p);
 void launch_stedc(Plan &p);
-// halvings of the chemical-potential bisection per launch pair (a tree of 2^k - 1 points)
-constexpr int kMuLevels = 2;
+// halvings of the chemical-potential bisection per launch (a tree of 2^k - 1 points), and the
+// number of launches that covers the 200-halving limit
+constexpr int kMuLevels = 4;
+constexpr int kMuLaunches = (200 + kMuLevels - 1) / kMuLevels;
 void launch_mu_init(Plan &p, double kT);
 void launch_mu_step(Plan &p, double n_electrons, double kT, double g);
 void launch_mu_fixed(Plan &p, double mu);
@@ -176,9 +237,17 @@ void launch_mu_fixed(Plan &p, double mu);
 enum { kRowsDensity = 0, kRowsEnergy = 1, kRowsWindow = 2 };
 void launch_density(Plan &p, int mode, double *d_D, const double *d_H, const double *d_S, double w_lo = 0.0,
                     double w_hi = 0.0, double w_kT = 1.0);
+// sums of the rows' traces with H and S over all clusters into the state slots of the mode
+void launch_density_sums(Plan &p, int mode);
+// state set-up of a density (n_e, kT, g; mu_fixed >= ... with fixed != 0: no bisection)
+void launch_state_init(Plan &p, double n_e, double kT, double g, int fixed, double mu);
+// every entry of an int array set to v
+void launch_fill_int(Plan &p, int *d, int n, int v);
 // toy SCF loop: Mulliken populations, potential on H0, linear mixing (residual to d_res[0])
 void launch_mulliken(Plan &p, const double *d_D, const double *d_S, double *d_q, double g);
 void launch_potential(Plan &p, const double *d_H0, const double *d_S, const double *d_v, double *d_H);
+// q0_i = N_e M_i / sum_j M_j
+void launch_reference_populations(Plan &p, double n_electrons, double *d_q0);
 void launch_scf_mix(Plan &p, const double *d_q_out, double *d_q_in, const double *d_q0, double U, double alpha,
                     double *d_v, double *d_res);
 

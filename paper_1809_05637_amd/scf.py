@@ -11,22 +11,19 @@ from __future__ import annotations
 import numpy as np
 
 
-def reference_populations(n_orb, n_electrons):
-    """q0_i = N_e M_i / sum_j M_j (neutral atoms at the system's filling), host array."""
-    m = np.asarray(n_orb, dtype=np.float64)
-    return float(n_electrons) * m / float(m.sum())
-
-
 def scf_loop(plan, H0, S, n_electrons, kT, U, alpha, steps, q0=None, lno=True, lambda_th=0.1, k_min=1, k_max=-1,
              fixed_rank=None, D0=None, keep=False, on_step=None):
     """Runs ``steps`` SCF steps on the plan's stream.  H0, S (and D0): device tensors in the
     block layout.  Returns one record per step: residual, mu, e_band, n_e (and, with keep=True,
-    host copies of q_in, q_out and D).  on_step(k, record) is called after every step."""
+    host copies of q_in, q_out and D).  on_step(k, record) is called after every step.  q0 (host
+    array) defaults to the library's neutral reference populations (ldc_reference_populations)."""
     import torch
     dev = S.device
     if q0 is None:
-        q0 = reference_populations(plan.n_orb, n_electrons)
-    q0_d = torch.as_tensor(np.asarray(q0, dtype=np.float64), device=dev)
+        q0_d = torch.empty(plan.n_atoms, dtype=torch.float64, device=dev)
+        plan.reference_populations(n_electrons, q0_d)   # neutral atoms at the system's filling
+    else:
+        q0_d = torch.as_tensor(np.asarray(q0, dtype=np.float64), device=dev)
     q_in = q0_d.clone()
     q_out = torch.zeros_like(q0_d)
     v = torch.zeros_like(q0_d)

@@ -58,6 +58,12 @@ def test_regions_match_oracle_config1():
     _check_regions(synth.load_config(1))
 
 
+def test_regions_match_oracle_config2():
+    """The benchmark workload (3920-atom metallic slab: free surfaces, vacancies, uneven
+    clusters)."""
+    _check_regions(synth.load_config(2))
+
+
 def test_regions_paper_counts():
     """The library planner on the Sec. IV.C diamond example: 465 = 275 short + 190 long."""
     ldc = _lib()

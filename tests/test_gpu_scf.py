@@ -117,7 +117,11 @@ def test_scf_full_size_kernels_and_sum_rule():
     assert abs(last["q_out"].sum() - s["n_electrons"]) < 1e-8 * s["n_electrons"]
     assert abs(last["n_e"] - s["n_electrons"]) < 1e-8 * s["n_electrons"]
     # the potential of the next step from the mixed populations
-    q0 = scf.reference_populations(s["n_orb"], s["n_electrons"])
+    q0_d = torch.empty(s["n_atoms"], dtype=torch.float64, device=H0.device)
+    plan.reference_populations(s["n_electrons"], q0_d)
+    torch.cuda.synchronize()
+    q0 = q0_d.cpu().numpy()
+    assert np.abs(q0 - oracle.reference_populations(s)).max() <= 1e-14 * s["n_electrons"]
     q_mixed = last["q_in"] + 0.3 * (last["q_out"] - last["q_in"])
     v = 0.2 * (q_mixed - q0)
     H = torch.empty_like(H0)
