@@ -192,6 +192,18 @@ ldc_status ldc_build(ldc_plan_t plan, const double *d_H, const double *d_S, cons
 ldc_status ldc_tune(ldc_plan_t plan, const double *d_H, const double *d_S, const double *d_Dprev,
                     const ldc_rank_rule *rule, double n_electrons, double kT, double *d_D_out, double *best_ms_out);
 
+/* For callers that cannot allocate device memory or wait for the device (code under HIP graph
+ * capture, tight serving loops): ldc_density without any allocation and without a host
+ * synchronization.  The bisection state, the workgroups' ticket counter, their partial sums
+ * and the per-cluster row sums live in one file-scope device array of the library (1.3 MB,
+ * present on every GPU the library runs on until the process ends) instead of the plan's
+ * buffers; mu, E_band and N_e go to d_result (device, 3 doubles, in that order).  The density
+ * rows, mu, E_band and N_e equal ldc_density's for the same solve.  Limits: at most 65536
+ * atoms and 2048 workgroups per plan, else LDC_ERR_LIMIT with a message.  All calls on one GPU
+ * share the array: calls that overlap in time on one GPU (two streams, two threads) race.
+ * Errors inside kernels are reported by the next call that synchronizes. */
+ldc_status ldc_density_noalloc(ldc_plan_t plan, double n_electrons, double kT, double *d_D_out, double *d_result);
+
 /* Density rows at a given chemical potential (no bisection); otherwise as ldc_density. */
 ldc_status ldc_density_at(ldc_plan_t plan, double mu, double kT, double *d_D_out, double *e_band_out,
                           double *n_e_out);

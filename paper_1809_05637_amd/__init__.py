@@ -94,6 +94,7 @@ def load():
         "ldc_solve": (c_int, [c_void_p, c_void_p, c_void_p]),
         "ldc_density": (c_int, [c_void_p, c_double, c_double, c_void_p, P_double, P_double, P_double]),
         "ldc_density_at": (c_int, [c_void_p, c_double, c_double, c_void_p, P_double, P_double]),
+        "ldc_density_noalloc": (c_int, [c_void_p, c_double, c_double, c_void_p, c_void_p]),
         "ldc_energy_density": (c_int, [c_void_p, c_void_p, P_double]),
         "ldc_window_density": (c_int, [c_void_p, c_double, c_double, c_double, c_void_p, P_double]),
         "ldc_mulliken": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
@@ -308,6 +309,12 @@ class Plan:
                                           ctypes.byref(mu),
                                           ctypes.byref(eb), ctypes.byref(ne)))
         return mu.value, eb.value, ne.value
+
+    def density_noalloc(self, n_electrons, kT, D_out, result_out):
+        """ldc_density_noalloc: as density(), with no allocation and no wait for the device; mu,
+        e_band and n_e go to the device vector result_out (3 float64)."""
+        self._check(self._lib.ldc_density_noalloc(self._h, float(n_electrons), float(kT), self._m(D_out, "D_out"),
+                                                  _dev(result_out, 3, "result_out", self._device)))
 
     def density_at(self, mu, kT, D_out):
         """ldc_density_at: density rows at a given chemical potential.  Returns (e_band, n_e)."""

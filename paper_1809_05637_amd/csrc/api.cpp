@@ -453,6 +453,13 @@ ldc_status ldc_plan_create(ldc_plan_t *out, int n_atoms, const double *pos, cons
     delete h;
     return LDC_ERR_DEVICE;
   }
+  p.device = dev;
+  // the allocation-free entry point's scratch address on this device (once per device); a
+  // failure here is reported by that entry point, which retries the set-up
+  {
+    std::string m;
+    (void)ldc::noalloc_setup(dev, m);
+  }
   if (p.max_dim > ldc::kMaxDimTri) {
     free_all(p);
     delete h;
@@ -703,6 +710,18 @@ void enqueue_rows(Plan &p, int mode, double *d_out, double w_lo = 0.0, double w_
   for_buckets(p, ldc::kTDensity, [&] { ldc::launch_density(p, mode, d_out, p.last_H, p.last_S, w_lo, w_hi, w_kT); });
   ldc::launch_density_sums(p, mode);
 }
+
+ldc_status enqueue_density(Plan &p, double n_electrons, double kT, double *d_D_out);
+
+}  // namespace
+
+// The device part of ldc_density (state set-up, bisection, rows and their sums) on the
+// plan's current scratch pointers; used by the allocation-free entry point.
+ldc_status ldc::enqueue_density_steps(Plan &p, double n_electrons, double kT, double *d_D_out) {
+  return enqueue_density(p, n_electrons, kT, d_D_out);
+}
+
+namespace {
 
 // The bisection (a fixed number of launches; those after convergence return at once) and the
 // density rows.

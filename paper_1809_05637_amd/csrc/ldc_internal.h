@@ -66,6 +66,7 @@ struct Plan {
   ldc_options opt{};
   hipStream_t stream = nullptr;
   int n_cu = 0;
+  int device = 0;                   // HIP device of the plan (current at creation)
   int workgroups = 0;
 
   // host copies of the geometry and pattern
@@ -202,6 +203,13 @@ struct IvecLayout {
 
 // host planner
 ldc_status build_regions(Plan &p, const double *pos, const double *cell, const int *periodic);
+
+// device part of ldc_density on the plan's current scratch pointers (d_mu, d_counter, d_partial)
+ldc_status enqueue_density_steps(Plan &p, double n_electrons, double kT, double *d_D_out);
+// scratch of the allocation-free density entry point: address of the file-scope array on a
+// device (set up once per device, with the device current), or nullptr
+ldc_status noalloc_setup(int device, std::string &msg);
+double *noalloc_scratch(int device);
 
 // launch range of the current bucket (the whole processing order when no bucket is set)
 inline const int *cur_order(const Plan &p) { return p.cur ? p.d_order + p.cur->begin : p.d_order; }
