@@ -493,6 +493,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="batched form without running the tuner")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the precision form (mixed FP32)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1809_05637_amd", "tune", "mi355x.json"),
                     help="tuning cache of the batched form (read, and written by the tuner when it has no entry)")
     ap.add_argument("--quiet", action="store_true")
@@ -629,6 +630,45 @@ def build_bench(s, args, log, H, S, plan, stream, rule, use_lno):
         f"{['default', 'tuned', 'cache'][binfo['tuned']]}, graph captures {binfo['graph_captures']}, "
         f"replays {binfo['graph_replays']}); max |D_batched - D_eager| = {np.abs(D_gpu - D_eager).max():.3e}")
 
+    # precision form on the same input and the same previous density
+    mixed = None
+    if not args.no_mixed:
+        mplan = ldc.Plan.from_system(s, stream=stream, batched=True, use_graph=True, tune_cache=cache,
+                                     prec="mixed_fp32")
+        Dm = torch.zeros_like(S)
+        mplan.build(H, S, D0, s["n_electrons"], s["kT"], Dm, **rule)
+        if mplan.info()["tuned"] != 2 and not args.no_tune:
+            tt = time.time()
+            mt = mplan.tune(H, S, D0, s["n_electrons"], s["kT"], Dm, **rule)
+            log(f"[bench] mixed form tuned in {time.time() - tt:.1f} s: {mt:.1f} ms/build")
+        for w in range(max(1, args.warmup)):
+            mplan.build(H, S, D0, s["n_electrons"], s["kT"], Dm, **rule)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for k in range(args.steps):
+            mu_m, eb_m, ne_m = mplan.build(H, S, D0, s["n_electrons"], s["kT"], Dm, **rule)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_m = ev0.elapsed_time(ev1) / args.steps
+        ranks_m = mplan.lno(S, D0, want_ranks=True, **rule)
+        mplan.solve(H, S)
+        mplan.density(s["n_electrons"], s["kT"], Dm)
+        resid = bisection_residual(mplan, s, mu_m)
+        minfo = mplan.info()
+        mplan.close()
+        mixed = {"atoms_per_s": round(s["n_atoms"] / (ms_m * 1e-3), 2), "ms_per_build": round(ms_m, 3),
+                 "speedup_vs_fp64_batched": round(ms_step / ms_m, 4),
+                 "lowered": "H half of the gather and of the LNO contraction (FP32 values, FP32 arithmetic); "
+                            "standard-form products P = L^-1 H_L and A = P L^-T + L^-1 P^T on FP32 matrix cores "
+                            "with FP32 accumulation",
+                 "fp64": "S gather and contraction, Cholesky and inverse of L, band reduction, bulge chasing, "
+                         "divide-and-conquer, mu bisection, density rows",
+                 "launch_choices": ["default", "tuned", "cache"][minfo["tuned"]],
+                 "D": Dm.cpu().numpy(), "mu": mu_m, "e_band": eb_m, "n_e": ne_m, "ranks": ranks_m,
+                 "bisection_residual": resid}
+        log(f"[bench] mixed form: {ms_m:.1f} ms/build ({ms_step / ms_m:.3f}x the FP64 batched form); "
+            f"max |D_mixed - D_fp64| = {np.abs(mixed['D'] - D_gpu).max():.3e}; bisection residual {resid:.3e}")
+
     work = stage_work(dims)
     dom = max(per_stage, key=per_stage.get)
     kern = dom + "_kernel"
@@ -666,7 +706,7 @@ def build_bench(s, args, log, H, S, plan, stream, rule, use_lno):
            "lapack_equivalent_flops_7d3": float(np.sum(7.0 * dims.astype(np.float64) ** 3))}
     value = s["n_atoms"] / (ms_step * 1e-3)
     out = {
-        "metric": "atoms/s per density-matrix build (FP64 form)",
+        "metric": "atoms/s per density-matrix build (FP64 form; the mixed FP32 form under forms)",
         "value": round(value, 2),
         "unit": "atoms/s",
         "n_gpus": 1,
@@ -699,13 +739,35 @@ def build_bench(s, args, log, H, S, plan, stream, rule, use_lno):
                      "e_band_per_atom": eb_b / s["n_atoms"]},
     }
     plan.close()
+    if mixed is not None:
+        out["forms"]["mixed_fp32"] = {k: v for k, v in mixed.items() if k not in ("D", "mu", "e_band", "n_e", "ranks")}
+        out["forms"]["mixed_fp32"]["vs_fp64_batched"] = {
+            "max_dD": float(np.abs(mixed["D"] - D_gpu).max()),
+            "dE_band_per_atom": abs(mixed["e_band"] - eb_b) / s["n_atoms"], "dmu": abs(mixed["mu"] - mu_b)}
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline: the oracle's whole build of the same input ...")
         base, ref0, ref1 = oracle_builds(s, log)
         out["cpu_baseline"] = base
         out["accuracy"] = accuracy_vs_oracle(s, ref1, D_gpu, mu_b, eb_b, ne_b, ranks)
         log(f"[bench] accuracy: {out['accuracy']}")
+        if mixed is not None:
+            acc = accuracy_vs_oracle(s, ref1, mixed["D"], mixed["mu"], mixed["e_band"], mixed["n_e"], mixed["ranks"])
+            acc["dN_e_bisection_fp64_weights"] = mixed["bisection_residual"]
+            out["forms"]["mixed_fp32"]["accuracy"] = acc
+            log(f"[bench] mixed form accuracy: {acc}")
     return out
+
+
+def bisection_residual(plan, s, mu):
+    """|g sum_i sum_mu f((eps - mu)/kT) w_mu - N_e| from every cluster's FP64 spectrum and weights at
+    the build's mu (the electron count the bisection solves for; reading (ii) of the mixed form's
+    electron-count target)."""
+    g = float(s.get("spin_g", 2))
+    tot = 0.0
+    for i in range(s["n_atoms"]):
+        e, w = plan.cluster_spectrum(i)
+        tot += float(np.sum(0.5 * (1.0 - np.tanh(0.5 * (e - mu) / s["kT"])) * w))
+    return abs(g * tot - s["n_electrons"])
 
 
 if __name__ == "__main__":

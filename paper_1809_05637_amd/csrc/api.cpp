@@ -184,7 +184,7 @@ std::string workload_key(const Plan &p, int lno) {
     h *= 1099511628211ull;
   }
   char buf[96];
-  std::snprintf(buf, sizeof buf, "%d:%s:%016llx", p.n_atoms, lno ? "lno" : "pao", h);
+  std::snprintf(buf, sizeof buf, "%d:%s:%016llx:p%d", p.n_atoms, lno ? "lno" : "pao", h, p.opt.prec);
   return buf;
 }
 
@@ -384,7 +384,7 @@ ldc_status ldc_plan_create(ldc_plan_t *out, int n_atoms, const double *pos, cons
   if (!out) return LDC_ERR_ARG;
   *out = nullptr;
   if (n_atoms <= 0 || !pos || !cell || !periodic || !n_orb || nnzb <= 0 || !row_ptr || !col || !opt ||
-      !(opt->r_L > 0.0))
+      !(opt->r_L > 0.0) || (opt->prec != LDC_FP64 && opt->prec != LDC_MIXED_FP32))
     return LDC_ERR_ARG;
   ldc_plan_s *h = new (std::nothrow) ldc_plan_s();
   if (!h) return LDC_ERR_OOM;

@@ -18,6 +18,11 @@ constexpr int NB = 32;  // panel width of the blocked factorizations
 // row-major, v = 0: U_i^T X_ij (k_i x M_j), v = 1: X_ij U_j (M_i x k_j), v = 2: U_i^T X_ij U_j
 // (k_i x k_j), for x = 0: X = H, x = 1: X = S.  U_j is column-major M_j x k_j (ld M_j).
 // One workgroup per atom row i; each wave takes one block of the row at a time.
+// TH: arithmetic of the H contractions (double, or float in the precision form: the entries are
+// rounded to FP32 and accumulated in FP32; the results are stored as FP64 values).  The S
+// contractions are always FP64 (the cluster overlap stays exact, so that C^T S C = I and the
+// electron count g Tr(D S) keep FP64 accuracy).
+template <typename TH>
 __global__ void __launch_bounds__(256) lno_blocks_kernel(int n_atoms, const int *__restrict__ row_ptr,
                                                          const int *__restrict__ col, const int *__restrict__ n_orb,
                                                          const long long *__restrict__ blk_off,
@@ -48,33 +53,39 @@ __global__ void __launch_bounds__(256) lno_blocks_kernel(int n_atoms, const int 
         if (act)
           for (int e = lane; e < Mi * Mj; e += 64) xs[wave][e] = X[e];
         __syncthreads();
-        if (act) {
-          double *o0 = out + (long long)x * total + bo;            // U_i^T X
-          double *o1 = out + (long long)(2 + x) * total + bo;      // X U_j
-          for (int e = lane; e < Mi * kj; e += 64) {
-            const int r = e / kj, q = e % kj;
-            double a = 0.0;
-            for (int be = 0; be < Mj; ++be) a += xs[wave][r * Mj + be] * uj[wave][be + q * Mj];
-            xu[wave][e] = a;
-            o1[e] = a;
+        // the three products in the arithmetic of this matrix (type of the tag)
+        auto contract = [&](auto tag) {
+          using TC = decltype(tag);
+          if (act) {
+            double *o0 = out + (long long)x * total + bo;            // U_i^T X
+            double *o1 = out + (long long)(2 + x) * total + bo;      // X U_j
+            for (int e = lane; e < Mi * kj; e += 64) {
+              const int r = e / kj, q = e % kj;
+              TC a = 0;
+              for (int be = 0; be < Mj; ++be) a += (TC)xs[wave][r * Mj + be] * (TC)uj[wave][be + q * Mj];
+              xu[wave][e] = (double)a;
+              o1[e] = (double)a;
+            }
+            for (int e = lane; e < ki * Mj; e += 64) {
+              const int r = e / Mj, q = e % Mj;
+              TC a = 0;
+              for (int al = 0; al < Mi; ++al) a += (TC)ui[al + r * Mi] * (TC)xs[wave][al * Mj + q];
+              o0[e] = (double)a;
+            }
           }
-          for (int e = lane; e < ki * Mj; e += 64) {
-            const int r = e / Mj, q = e % Mj;
-            double a = 0.0;
-            for (int al = 0; al < Mi; ++al) a += ui[al + r * Mi] * xs[wave][al * Mj + q];
-            o0[e] = a;
+          __syncthreads();
+          if (act) {
+            double *o2 = out + (long long)(4 + x) * total + bo;      // U_i^T X U_j
+            for (int e = lane; e < ki * kj; e += 64) {
+              const int r = e / kj, q = e % kj;
+              TC a = 0;
+              for (int al = 0; al < Mi; ++al) a += (TC)ui[al + r * Mi] * (TC)xu[wave][al * kj + q];
+              o2[e] = (double)a;
+            }
           }
-        }
-        __syncthreads();
-        if (act) {
-          double *o2 = out + (long long)(4 + x) * total + bo;      // U_i^T X U_j
-          for (int e = lane; e < ki * kj; e += 64) {
-            const int r = e / kj, q = e % kj;
-            double a = 0.0;
-            for (int al = 0; al < Mi; ++al) a += ui[al + r * Mi] * xu[wave][al * kj + q];
-            o2[e] = a;
-          }
-        }
+        };
+        if (x == 0) contract(TH{});
+        else contract(double{});
       }
     }
   }
@@ -101,7 +112,7 @@ __global__ void __launch_bounds__(256) gather_kernel(int n_clusters, const int *
                                                      const double *__restrict__ lno_blk, long long total,
                                                      double *__restrict__ mat,
                                                      const long long *__restrict__ mat_off, const int *__restrict__ dmax,
-                                                     int *__restrict__ dim) {
+                                                     int *__restrict__ dim, int round32) {
   extern __shared__ unsigned short rowmem[];
   __shared__ int off[kMaxMembers + 1];
   __shared__ int dm[kMaxMembers];
@@ -168,6 +179,10 @@ __global__ void __launch_bounds__(256) gather_kernel(int n_clusters, const int *
             const int q = min(q0 + u, db - 1);
             hv[u] = bo >= 0 ? hb[src + (long long)q * da] : 0.0;
             sv[u] = (bo >= 0 && s_rows) ? sb[src + (long long)q * da] : 0.0;
+          }
+          if (round32) {  // precision form: the cluster Hamiltonian holds FP32 values (S stays FP64)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) hv[u] = (double)(float)hv[u];
           }
 #pragma unroll
           for (int u = 0; u < 4; ++u)
@@ -360,6 +375,9 @@ __global__ void __launch_bounds__(256, 2) potrf_kernel(int n_clusters, const int
 // All products are MFMA GEMMs.  The tracked
 // columns of the tridiagonal solver are set up here: X_u = L^{-1} E_i (the last M columns of
 // L^{-1}) and X_v = L^T E_i (the last M rows of L, taken before the inversion).
+// TP: compute type of the two products (double, or float in the precision form: FP32 matrix
+// cores with FP32 accumulation; the inverse of L stays FP64).
+template <typename TP>
 __global__ void __launch_bounds__(256, 2) sygst_kernel(int n_clusters, const int *__restrict__ order,
                                                     double *__restrict__ mat, const long long *__restrict__ mat_off,
                                                     double *__restrict__ vec, const long long *__restrict__ vec_off,
@@ -468,23 +486,28 @@ __global__ void __launch_bounds__(256, 2) sygst_kernel(int n_clusters, const int
     const int nblk2 = (n + GT - 1) / GT;
     for (int bj = nblk2 - 1; bj >= 0; --bj) {
       const int r0 = bj * GT, jb = min(GT, n - r0), r1 = r0 + jb;
-      wg_gemm<G_OVERWRITE | G_PLUS | G_B_LOWER, 64, 128>(H + r0, ld, L + r0, ld, H, ld, jb, r1, r1, gl, r0);
+      wg_gemm<G_OVERWRITE | G_PLUS | G_B_LOWER, 64, 128, TP>(H + r0, ld, L + r0, ld, H, ld, jb, r1, r1, gl, r0);
     }
     // 3. A = P L^{-T} + L^{-1} P^T in place, lower part: block row b of A from L^{-1} and P of
     //    rows b and of rows 0:r1, in one pass of both products per tile.
     for (int bj = nblk2 - 1; bj >= 0; --bj) {
       const int r0 = bj * GT, jb = min(GT, n - r0), r1 = r0 + jb;
-      wg_gemm<G_TRANS_B | G_OVERWRITE | G_PLUS | G_REV | G_DUAL, 64, 128>(H + r0, ld, L + r0, ld, H, ld, jb, r1, r1,
-                                                                           gl, -1, 0, H + r0, L);
+      wg_gemm<G_TRANS_B | G_OVERWRITE | G_PLUS | G_REV | G_DUAL, 64, 128, TP>(H + r0, ld, L + r0, ld, H, ld, jb, r1,
+                                                                               r1, gl, -1, 0, H + r0, L);
     }
   }
 }
 
 // ---------------------------------------------------------------------------------------
 void launch_lno_blocks(Plan &p, const double *d_H, const double *d_S) {
-  hipLaunchKernelGGL(lno_blocks_kernel, dim3(std::min(p.n_atoms, 8 * p.n_cu)), dim3(kWG), 0, p.stream, p.n_atoms,
-                     p.d_row_ptr, p.d_col, p.d_n_orb, p.d_blk_off, p.d_rank, p.d_U, d_H, d_S, p.d_lno_blk,
-                     p.blk_total);
+  if (p.opt.prec == LDC_MIXED_FP32)
+    hipLaunchKernelGGL(lno_blocks_kernel<float>, dim3(std::min(p.n_atoms, 8 * p.n_cu)), dim3(kWG), 0, p.stream,
+                       p.n_atoms, p.d_row_ptr, p.d_col, p.d_n_orb, p.d_blk_off, p.d_rank, p.d_U, d_H, d_S, p.d_lno_blk,
+                       p.blk_total);
+  else
+    hipLaunchKernelGGL(lno_blocks_kernel<double>, dim3(std::min(p.n_atoms, 8 * p.n_cu)), dim3(kWG), 0, p.stream,
+                       p.n_atoms, p.d_row_ptr, p.d_col, p.d_n_orb, p.d_blk_off, p.d_rank, p.d_U, d_H, d_S, p.d_lno_blk,
+                       p.blk_total);
 }
 
 void launch_gather(Plan &p, const double *d_H, const double *d_S) {
@@ -495,7 +518,7 @@ void launch_gather(Plan &p, const double *d_H, const double *d_S) {
   hipLaunchKernelGGL(gather_kernel, dim3(grid), dim3(kWG), sizeof(unsigned short) * cur_dim(p), p.stream, n,
                      cur_order(p), p.d_mem_ptr, p.d_mem_atom, p.d_mem_long, p.d_pair_ptr, p.d_pair_ab, p.d_pair_blk,
                      p.d_n_orb, p.d_blk_off, d_H, d_S, p.lno_mode, p.d_rank, p.d_lno_blk, p.blk_total, p.d_mat,
-                     p.d_mat_off, p.d_dmax, p.d_dim);
+                     p.d_mat_off, p.d_dmax, p.d_dim, p.opt.prec == LDC_MIXED_FP32 ? 1 : 0);
 }
 
 void launch_potrf(Plan &p) {
@@ -508,8 +531,12 @@ void launch_potrf(Plan &p) {
 void launch_sygst(Plan &p) {
   const int n = cur_count(p);
   const int grid = std::max(1, std::min(stage_grid(p, kTSygst, p.workgroups), n));
-  hipLaunchKernelGGL(sygst_kernel, dim3(grid), dim3(kWG), 0, p.stream, n, cur_order(p), p.d_mat, p.d_mat_off,
-                     p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb);
+  if (p.opt.prec == LDC_MIXED_FP32)
+    hipLaunchKernelGGL(sygst_kernel<float>, dim3(grid), dim3(kWG), 0, p.stream, n, cur_order(p), p.d_mat,
+                       p.d_mat_off, p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb);
+  else
+    hipLaunchKernelGGL(sygst_kernel<double>, dim3(grid), dim3(kWG), 0, p.stream, n, cur_order(p), p.d_mat,
+                       p.d_mat_off, p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb);
 }
 
 }  // namespace ldc

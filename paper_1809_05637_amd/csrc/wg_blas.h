@@ -18,6 +18,26 @@ constexpr int kGemmLdsTall = GK * (128 + 32 + 2 * GPAD);
 constexpr int kGemmLdsWide = GK / 2 * (64 + 128 + 2 * GPAD);
 
 typedef double ldc_double4 __attribute__((ext_vector_type(4)));
+typedef float ldc_float4 __attribute__((ext_vector_type(4)));
+
+// One 16 x 16 x 4 matrix-core product for the compute type of wg_gemm: FP64 (v_mfma_f64_16x16x4)
+// or FP32 with FP32 accumulation (v_mfma_f32_16x16x4).  The two lay out their 16 x 16 result
+// differently: output register r of lane l holds row l / 16 + 4 r (FP64) or 4 (l / 16) + r (FP32)
+// of the instruction's result, column l % 16.
+template <typename TC>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef ldc_double4 acc_t;
+  __device__ static acc_t step(double a, double b, acc_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static int row_of(int r, int lk) { return 4 * r + lk; }
+};
+template <>
+struct Mfma<float> {
+  typedef ldc_float4 acc_t;
+  __device__ static acc_t step(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row_of(int r, int lk) { return 4 * lk + r; }
+};
 
 // Operand layouts and options of wg_gemm (bit flags).
 enum : unsigned {
@@ -59,10 +79,15 @@ enum : unsigned {
 // C[r0 + l%16][c0 + 4 r + l/16].  The next K chunk of A and op(B) (after a tile's last
 // chunk: the next tile's first) is fetched into registers while the current one is multiplied;
 // with the last chunk C is fetched too (with the first under G_EARLY_C; not under G_LATE_C).
-template <unsigned F, int TM = GT, int TN = GT>
+//
+// TC: compute type.  double: FP64 products (the default).  float: the operands are rounded to
+// FP32 when staged and multiplied on the FP32 matrix cores with FP32 accumulation; C stays FP64
+// in memory (the FP32 product is added to it in FP64).
+template <unsigned F, int TM = GT, int TN = GT, typename TC = double>
 __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const double *B, int ldb, int m, int n, int k,
                         double *lds, int a_diag = -1, int b_rot = 0, const double *A2 = nullptr,
                         const double *B2 = nullptr) {
+  typedef typename Mfma<TC>::acc_t acc_t;
   constexpr bool TRANS_B = F & G_TRANS_B, LOWER = F & G_LOWER, A_RM = F & G_A_RM, B_RM = F & G_B_RM;
   constexpr bool OVERWRITE = F & G_OVERWRITE, PREFETCH_C = !(F & G_LATE_C), C_RM = F & G_C_RM;
   constexpr bool A_SYM = F & G_A_SYM, PLUS = F & G_PLUS, REV = F & G_REV, EARLY_C = F & G_EARLY_C;
@@ -74,10 +99,14 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
   constexpr int GR = TM / 32, GC = 4 / GR, BN = TN / (16 * GC), WN = 16 * BN;
   static_assert(TM % 32 == 0 && GR * GC == 4 && (BN == 2 || BN == 4) && WN * GC == TN, "tile shape");
   static_assert(!LOWER || TM == TN, "lower-triangle tiling needs square tiles");
-  constexpr int LSA = TM + GPAD, LSB = TN + GPAD;
+  // LDS row padding: one double, or 16 floats for FP32 staging (a 16-wide read of four
+  // consecutive K rows then falls into four disjoint quarters of the 64 banks)
+  constexpr int PAD = sizeof(TC) == 4 ? 16 : GPAD;
+  constexpr int LSA = TM + PAD, LSB = TN + PAD;
+  static_assert(sizeof(TC) == 8 || KC * (LSA + LSB) * 4 <= KC * (TM + TN + 2 * GPAD) * 8, "FP32 staging fits");
   constexpr int PERA = TM * KC / 256, PERB = TN * KC / 256;  // staged elements per thread
-  double *As = lds;                   // [KC][LSA]
-  double *Bs = lds + KC * LSA;        // [KC][LSB]
+  TC *As = reinterpret_cast<TC *>(lds);  // [KC][LSA]
+  TC *Bs = As + KC * LSA;                 // [KC][LSB]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave / GC, wc = wave % GC;
   const int li = lane & 15, lk = lane >> 4;
@@ -101,6 +130,8 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
     if (A_SYM) return (k0 >= r0 + TM) ? 1 : 0;
     return A_RM ? 1 : 0;
   };
+  // Fetched chunks stay in FP64 registers (the loads are in flight while the previous chunk is
+  // multiplied); they are rounded to the compute type only when staged in LDS.
   auto fetchA = [&](const double *Ap, int r0, int k0, int mode, double *ra) {
     const double *Asrc = DUAL ? Ap : A;
 #pragma unroll
@@ -142,14 +173,14 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
   auto stage = [&](int mode, const double *ra, const double *rb) {
     if (mode) {
 #pragma unroll
-      for (int q = 0; q < PERA; ++q) As[kk0 * LSA + ek + q * STEP_K] = ra[q];
+      for (int q = 0; q < PERA; ++q) As[kk0 * LSA + ek + q * STEP_K] = (TC)ra[q];
     } else {
 #pragma unroll
-      for (int q = 0; q < PERA; ++q) As[(kf + q * STEP_E) * LSA + ef] = ra[q];
+      for (int q = 0; q < PERA; ++q) As[(kf + q * STEP_E) * LSA + ef] = (TC)ra[q];
     }
 #pragma unroll
     for (int q = 0; q < PERB; ++q)
-      Bs[(b_k + (B_KFAST ? 0 : q * B_STEP)) * LSB + b_e + (B_KFAST ? q * B_STEP : 0)] = rb[q];
+      Bs[(b_k + (B_KFAST ? 0 : q * B_STEP)) * LSB + b_e + (B_KFAST ? q * B_STEP : 0)] = (TC)rb[q];
   };
   auto cidx = [&](int gr, int gc) { return C_RM ? gr * ldc + gc : gc * ldc + gr; };
   // tiles in row-major order (G_REV: reversed; G_LOWER: only tile row >= tile column); a
@@ -205,11 +236,11 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
     const int nxt = next_tile(tile + 1);
     const int r0n = (nxt >= 0) ? (tile_of(nxt) / nt) * TM : 0, c0n = (nxt >= 0) ? (tile_of(nxt) % nt) * TN : 0;
     const bool fetch_next = nxt >= 0 && k_stop(r0n, c0n) > k_beg(c0n);
-    ldc_double4 acc[2][BN];
+    acc_t acc[2][BN];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < BN; ++b) acc[a][b] = ldc_double4{0.0, 0.0, 0.0, 0.0};
+      for (int b = 0; b < BN; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
     double cold[2][BN][4];
     for (int k0 = kbeg; k0 < kend; k0 += KC) {
       __syncthreads();
@@ -235,14 +266,14 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
           for (int b = 0; b < BN; ++b)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-              const int gr = r0 + wr * 32 + a * 16 + li, gc = c0 + wc * WN + b * 16 + 4 * r + lk;
+              const int gr = r0 + wr * 32 + a * 16 + li, gc = c0 + wc * WN + b * 16 + Mfma<TC>::row_of(r, lk);
               cold[a][b][r] = (gr < m && gc < n) ? C[cidx(gr, gc)] : 0.0;
             }
       }
 #pragma unroll
       for (int s4 = 0; s4 < KC / 4; ++s4) {
         const int kra = (4 * s4 + lk) * LSA, krb = (4 * s4 + lk) * LSB;
-        double af[2], bf[BN];
+        TC af[2], bf[BN];
 #pragma unroll
         for (int a = 0; a < 2; ++a) af[a] = As[kra + wr * 32 + a * 16 + li];
 #pragma unroll
@@ -250,7 +281,7 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
-          for (int b = 0; b < BN; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[b], af[a], acc[a][b], 0, 0, 0);
+          for (int b = 0; b < BN; ++b) acc[a][b] = Mfma<TC>::step(bf[b], af[a], acc[a][b]);
       }
     }
     if (kend <= kbeg && fetch_next) {
@@ -268,9 +299,9 @@ __device__ void wg_gemm(double *C, int ldc, const double *A, int lda, const doub
       for (int b = 0; b < BN; ++b) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int gc = c0 + wc * WN + b * 16 + 4 * r + lk;
+          const int gc = c0 + wc * WN + b * 16 + Mfma<TC>::row_of(r, lk);
           if (gr < m && gc < n) {
-            const double v = PLUS ? acc[a][b][r] : -acc[a][b][r];
+            const double v = PLUS ? (double)acc[a][b][r] : -(double)acc[a][b][r];
             if (OVERWRITE) C[cidx(gr, gc)] = v;
             else if (PREFETCH_C) C[cidx(gr, gc)] = cold[a][b][r] + v;
             else C[cidx(gr, gc)] += v;

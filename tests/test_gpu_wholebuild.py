@@ -6,8 +6,9 @@ Both sides run their own chain on the same input: a plain-DC build, then the DC-
 whose LNOs come from that side's plain-DC density (Sec. II.C (i)-(v)).  The LNO ranks must be
 equal (integers decided in FP64 on both sides); the density rows must agree element by element
 within 1e-9 and the band energy within 1e-10 Ha/atom (Eq. 13, Eq. 24 with 27), for the plain-DC
-build and for the DC-LNO build.  The oracle's two whole builds take a few minutes of host time
-(a process pool over the host's cores)."""
+build and for the DC-LNO build.  The precision form (mixed FP32) runs the same DC-LNO build and
+must hold its bars (1e-6 Ha/atom, electron count within 1e-8).  The oracle's two whole builds take
+a few minutes of host time (a process pool over the host's cores)."""
 import numpy as np
 import pytest
 
@@ -73,3 +74,22 @@ def test_whole_build_fcc3920():
           f"dN_e={abs(ne1 - ref1['n_e']):.3e}", flush=True)
     assert e1 <= TOL_D and de1 <= TOL_E
     assert abs(ne1 - s["n_electrons"]) <= 1e-8
+    # the precision form on the same input and LNO source: band energy within 1e-6 Ha/atom of the
+    # oracle, the returned rows' electron count within 1e-8 of N_e
+    H, S = to_dev(s["H"]), to_dev(s["S"])
+    Dm, Dp = torch.zeros_like(S), to_dev(g0)
+    plan = ldc.Plan.from_system(s, stream=torch.cuda.current_stream(), prec="mixed_fp32")
+    try:
+        ranks_m = np.asarray(plan.lno(S, Dp, **rule))
+        plan.solve(H, S)
+        mu_m, eb_m, ne_m = plan.density(s["n_electrons"], s["kT"], Dm)
+        torch.cuda.synchronize()
+        gm = Dm.cpu().numpy()
+    finally:
+        plan.close()
+    em = float(np.abs(gm - ref1["D"]).max())
+    dem = abs(eb_m - ref1["e_band"]) / n
+    print(f"[whole] mixed FP32 form: max|dD|={em:.3e} dE_band/atom={dem:.3e} dmu={abs(mu_m - ref1['mu']):.3e} "
+          f"strict dN_e={abs(ne_m - s['n_electrons']):.3e}", flush=True)
+    assert np.array_equal(ranks_m, np.asarray(ref1["ranks"]))
+    assert dem <= 1e-6 and abs(ne_m - s["n_electrons"]) <= 1e-8 and em <= 1e-4
