@@ -1,5 +1,6 @@
 // Host planner: truncated cluster, first neighbours and short/long regions of every atom
-// (Sec. III, steps (i)-(iv)), plus the index tables the kernels read.
+// (Sec. III, steps (i)-(iv)), plus the index tables the kernels read.  The sphere search runs
+// over a cell list (O(N) for a fixed radius).
 //
 // Rules (the same readings the CPU oracle states):
 //  * distances are minimum-image distances along periodic axes of an orthorhombic cell;
@@ -41,21 +42,86 @@ ldc_status build_regions(Plan &p, const double *pos, const double *cell, const i
   p.max_members = 0;
   p.max_dim = 0;
 
+  // Cell list: along every axis cells of width >= the search radius (periodic axes: the cell
+  // length divided evenly; open axes: from the smallest coordinate), so every atom within the
+  // radius of i lies in i's cell or a neighbouring one.  Neighbour cells along an axis are
+  // deduplicated (a periodic axis with fewer than three cells is searched whole), and the
+  // distance test is the minimum-image test of every candidate, so the cluster is exactly
+  // {j : dist(i, j) <= r_L (1 + tol)} whatever the cell sizes.
+  const double rc = r_L + dtol;
+  int ncell[3];
+  double lo[3], width[3];
+  for (int ax = 0; ax < 3; ++ax) {
+    if (periodic[ax]) {
+      lo[ax] = 0.0;
+      ncell[ax] = std::max(1, (int)std::floor(len[ax] / rc));
+      width[ax] = len[ax] / ncell[ax];
+    } else {
+      double mn = pos[ax], mx = pos[ax];
+      for (int j = 1; j < n; ++j) {
+        mn = std::min(mn, pos[3 * j + ax]);
+        mx = std::max(mx, pos[3 * j + ax]);
+      }
+      lo[ax] = mn;
+      width[ax] = rc;
+      ncell[ax] = std::max(1, (int)std::floor((mx - mn) / rc) + 1);
+    }
+    ncell[ax] = std::min(ncell[ax], 1 << 10);
+  }
+  auto cell_of = [&](int j, int ax) {
+    double x = pos[3 * j + ax] - lo[ax];
+    if (periodic[ax]) x -= len[ax] * std::floor(x / len[ax]);
+    int c = (int)std::floor(x / width[ax]);
+    return std::max(0, std::min(ncell[ax] - 1, c));
+  };
+  const long long ntot = (long long)ncell[0] * ncell[1] * ncell[2];
+  std::vector<int> cell_start(ntot + 1, 0), cell_atoms(n);
+  std::vector<long long> atom_cell(n);
+  for (int j = 0; j < n; ++j) {
+    atom_cell[j] = ((long long)cell_of(j, 0) * ncell[1] + cell_of(j, 1)) * ncell[2] + cell_of(j, 2);
+    cell_start[atom_cell[j] + 1] += 1;
+  }
+  for (long long c = 0; c < ntot; ++c) cell_start[c + 1] += cell_start[c];
+  {
+    std::vector<int> fill(cell_start.begin(), cell_start.end() - 1);
+    for (int j = 0; j < n; ++j) cell_atoms[fill[atom_cell[j]]++] = j;
+  }
+  auto neighbours = [&](int c, int ax, int *out) {
+    int k = 0;
+    for (int o = -1; o <= 1; ++o) {
+      int cc = c + o;
+      if (periodic[ax]) cc = ((cc % ncell[ax]) + ncell[ax]) % ncell[ax];
+      else if (cc < 0 || cc >= ncell[ax]) continue;
+      bool dup = false;
+      for (int q = 0; q < k; ++q) dup |= (out[q] == cc);
+      if (!dup) out[k++] = cc;
+    }
+    return k;
+  };
+
   std::vector<std::pair<double, int>> cand;
   std::vector<int> stamp(n, -1), midx(n, -1);
   std::vector<char> is_fna(n, 0);
   for (int i = 0; i < n; ++i) {
     cand.clear();
-    for (int j = 0; j < n; ++j) {
-      double d2 = 0.0;
-      for (int ax = 0; ax < 3; ++ax) {
-        double dx = pos[3 * j + ax] - pos[3 * i + ax];
-        if (periodic[ax]) dx -= len[ax] * std::nearbyint(dx / len[ax]);
-        d2 += dx * dx;
-      }
-      double d = std::sqrt(d2);
-      if (d <= r_L + dtol) cand.emplace_back(d, j);
-    }
+    int nb[3][3], nn[3];
+    for (int ax = 0; ax < 3; ++ax) nn[ax] = neighbours(cell_of(i, ax), ax, nb[ax]);
+    for (int a = 0; a < nn[0]; ++a)
+      for (int b = 0; b < nn[1]; ++b)
+        for (int c3 = 0; c3 < nn[2]; ++c3) {
+          const long long cell = ((long long)nb[0][a] * ncell[1] + nb[1][b]) * ncell[2] + nb[2][c3];
+          for (int q = cell_start[cell]; q < cell_start[cell + 1]; ++q) {
+            const int j = cell_atoms[q];
+            double d2 = 0.0;
+            for (int ax = 0; ax < 3; ++ax) {
+              double dx = pos[3 * j + ax] - pos[3 * i + ax];
+              if (periodic[ax]) dx -= len[ax] * std::nearbyint(dx / len[ax]);
+              d2 += dx * dx;
+            }
+            double d = std::sqrt(d2);
+            if (d <= r_L + dtol) cand.emplace_back(d, j);
+          }
+        }
     std::sort(cand.begin(), cand.end());
     const int nc = (int)cand.size();
     if (nc > kMaxMembers) {
