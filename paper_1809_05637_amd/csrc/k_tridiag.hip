@@ -430,12 +430,10 @@ __device__ void bulge_step(double *__restrict__ Bd, double *__restrict__ A, int 
   }
   __builtin_amdgcn_wave_barrier();
   if (isRow) {
-    // both candidates at fixed offsets from two bases (no per-column address registers)
+    // one read per entry, its address selected: the lane's own row on and below the diagonal,
+    // column i of the parked rows above it
 #pragma unroll
-    for (int k = 0; k < b; ++k) {
-      const double lower = wt[i * TS + k], upper = wt[k * TS + i];
-      row[k] = (k <= i) ? lower : upper;
-    }
+    for (int k = 0; k < b; ++k) row[k] = wt[(k <= i) ? i * TS + k : k * TS + i];
   }
   double pdot = 0.0;
 #pragma unroll
@@ -447,16 +445,18 @@ __device__ void bulge_step(double *__restrict__ Bd, double *__restrict__ A, int 
   __builtin_amdgcn_wave_barrier();
   // v is read again from LDS below rather than held in 64 more registers
   asm volatile("" ::: "memory");
+  // one pass for both lane halves: D rows take D - v w^T - w v^T, R rows R - p v^T
+  {
+    const double ca = isRow ? v : 0.0, cb = isRow ? w : (isR ? p : 0.0);
+#pragma unroll
+    for (int k = 0; k < b; ++k) row[k] = fma(-cb, vs[k], fma(-ca, wsv[k], row[k]));
+  }
   if (isRow) {
-    double *own = sink + lane;
+    // the part above the diagonal goes to the lane's own slot of the sink (one base, the offset
+    // selected: no branch per column)
+    const unsigned own = (unsigned)(sink - Bd) + (unsigned)lane;
 #pragma unroll
-    for (int k = 0; k < b; ++k) {
-      const double val = row[k] - v * wsv[k] - w * vs[k];
-      *((k <= i) ? Bd + oW + (unsigned)k * LD1 : own) = val;
-    }
-  } else if (isR) {
-#pragma unroll
-    for (int k = 0; k < b; ++k) row[k] -= p * vs[k];
+    for (int k = 0; k < b; ++k) Bd[(k <= i) ? oW + (unsigned)k * LD1 : own] = row[k];
   }
   if (nr >= 2) {
     // (a) H_{j+1} from x = R(:, 0)
