@@ -18,9 +18,10 @@
 // (j = 0) or from the first column of the bulge that step j - 1 created; step j applies it
 // two-sidedly to the diagonal block and from the right to the band block below (which
 // creates the next bulge), then forms the next reflector from that block and applies it from
-// the left to the rest of the block.  Step j of sweep s + 1 never touches what steps >= j + 3
-// of sweep s touch, so at time t every sweep s with j = t - 3 s in range is advanced at once,
-// one wavefront per step.  The reflectors are kept in the strictly upper triangle of A
+// the left to the rest of the block.  Everything step j reads or writes lies in the columns
+// [r0, r0 + b) of the band (column s too for j = 0), so step j of sweep s + 1 (columns
+// [r0 + 1, r0 + 1 + b)) only needs steps j and j + 1 of sweep s, and at time t every sweep s with
+// j = t - 2 s in range is advanced at once, one wavefront per step.  The reflectors are kept in the strictly upper triangle of A
 // (sweep s in column n - 1 - s, rows j b..: tau first, then v(1:)); q2x_lds_kernel then
 // forms X <- Q2^T X, sweep by sweep.
 #include "wg_blas.h"
@@ -353,9 +354,62 @@ __global__ void __launch_bounds__(256, 2) sy2sb_kernel(int n_clusters, const int
 // Stage 2: bulge chasing (see the top of the file).
 __device__ inline int sweep_steps(int n, int s) { return (s > n - 3) ? 0 : (n - 3 - s) / kBand + 1; }
 
-// One bulge step (sweep s, step j) by one wavefront.  The reflector H_j = I - tau v v^T of the
-// rows [r0, r1), r0 = s + 1 + j b, r1 = min(r0 + b, n), is in the sweep's LDS slot (tau, then v
-// with v(0) = 1); step 0 first forms it from column s.  The step then
+// Per-lane select with a wave-uniform 64-bit lane mask: bit l set -> lane l takes b.  One
+// v_cndmask with the mask in an SGPR pair (the compiler would otherwise build the mask per lane
+// from compares).
+__device__ inline unsigned lane_select(unsigned long long mask, unsigned a, unsigned b) {
+  unsigned r;
+  asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(mask));
+  return r;
+}
+
+// A lane mask from its two halves, each put in a scalar register by an opaque move: folded into
+// one 64-bit scalar move, a mask that is not an inline constant had its high half read as zero
+// on gfx950 (measured: the lanes 32..63 of such a mask were off).
+__device__ inline unsigned long long lane_mask(unsigned lo, unsigned hi) {
+  asm volatile("" : "+s"(lo), "+s"(hi));
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ inline double band_load(__amdgpu_buffer_rsrc_t band, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(band, (int)voff, (int)soff, 0));
+}
+
+__device__ inline void band_store(__amdgpu_buffer_rsrc_t band, double x, unsigned voff, unsigned soff) {
+  using U2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(band, 0, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, x), band, (int)voff, (int)soff, 0);
+}
+
+// A byte offset past the end of every band array: a buffer store through it is dropped (the
+// hardware range check of a raw buffer view; loads past the end read zero).
+constexpr unsigned kBandOob = 0x80000000u;
+
+// The band array: entry (r, c), r >= c, at c kBandLd + r - c, read and written through a raw
+// buffer view of its n kBandLd doubles.  Rows past the matrix hold zeros (written when the band
+// is set up, and only zeros are stored there later).
+//
+// Loads of bulge step (s, j): element k of the lane's row (D rows on lanes 0..31, R rows on
+// lanes 32..63) sits at r0 kBandLd + k (kBandLd - 1) + lane, so one load per k serves both
+// halves, the lane offset in a register and the window in a scalar register.  D rows read their
+// part above the diagonal as it lies in memory (the tail of the previous column); rows past the
+// matrix, and on the last step of a sweep the columns past it, read zeros (the zero rows of the
+// array, or past its end).  x is B(s + 1 + lane mod 32, s), column s below its diagonal (used by
+// step 0 only).
+__device__ inline void chase_fetch(__amdgpu_buffer_rsrc_t band, double (&row)[kBand], double &x, int s, int j) {
+  constexpr unsigned LB = kBandLd, LD1 = kBandLd - 1;
+  const unsigned lane = threadIdx.x & 63u;
+  const unsigned vl = lane * 8u;
+  const unsigned base = __builtin_amdgcn_readfirstlane((unsigned)(s + 1 + j * kBand) * LB * 8u);
+  const unsigned cs = __builtin_amdgcn_readfirstlane((unsigned)s * LB * 8u);
+#pragma unroll
+  for (int k = 0; k < kBand; ++k) row[k] = band_load(band, vl + (unsigned)k * LD1 * 8u, base);
+  x = band_load(band, (1u + (lane & 31u)) * 8u, cs);
+}
+
+// One bulge step (sweep s, step j) by one wavefront, on the rows chase_fetch loaded.  The
+// reflector H_j = I - tau v v^T of the rows [r0, r1), r0 = s + 1 + j b, r1 = min(r0 + b, n), is
+// in the sweep's LDS slot (tau, then v with v(0) = 1); step 0 first forms it from column s.  The
+// step then
 //   (c) updates the diagonal block D = B(r0:r1, r0:r1) <- H_j D H_j and the block below it,
 //       R = B(r1:r2, r0:r1) <- R H_j, r2 = min(r1 + b, n) (this creates the bulge in R);
 //   (a) when r2 - r1 >= 2, forms H_{j+1} from the first column of R, which it reduces to
@@ -363,20 +417,18 @@ __device__ inline int sweep_steps(int n, int s) { return (s > n - 3) ? 0 : (n - 
 //   (b) applies H_{j+1} from the left to the other columns of R.
 // (a) and (b) belong to step j + 1 of the sweep; nothing else touches R between the two
 // steps, so they run here while R is still in registers and every step moves its window
-// through memory once.  Lanes 0..31 hold the rows of D, lanes 32..63 the rows of R; every
-// load and store is consecutive in the lane for a fixed column (coalesced).  Entry (r, c),
-// r >= c, of the band array is Bd[c * LB + r - c].  Offsets are unsigned 32-bit from the array
-// base; indices past the end are clamped on load and never stored (D lanes store the part of
-// their row above the diagonal to their own slot of sink, which keeps those stores free of
-// branches).  wsv: kBand doubles and wt: kBand x (kBand + 1) doubles of the wave's LDS; slot:
-// kBand + 1 doubles of the sweep; sink: 64 doubles.
-__device__ void bulge_step(double *__restrict__ Bd, double *__restrict__ A, int ld, int n, int s, int j,
-                           double *slot, double *wsv, double *wt, double *__restrict__ sink) {
+// through memory once.  The D rows take their part above the diagonal from the tile (wt:
+// kBand x (kBand + 1) doubles of the wave's LDS; wsv: kBand doubles; slot: kBand + 1 doubles of
+// the sweep).  Rows past the matrix hold zeros throughout (they read zeros, and v, w, p and v1
+// are zero on them).  D and R rows are stored together at the end, one store per k: the D
+// lanes above the diagonal or past the window are sent past the end of the buffer, R rows past
+// the matrix store their zeros.
+__device__ void bulge_step(__amdgpu_buffer_rsrc_t band, double (&row)[kBand], double x, double *__restrict__ A,
+                           int ld, int n, int s, int j, double *slot, double *wsv, double *wt) {
   constexpr int b = kBand, TS = kBand + 1;
   constexpr unsigned LB = kBandLd, LD1 = kBandLd - 1;
   // the lane index and (s, j) through opaque moves: keeps the compiler from hoisting the
-  // per-lane addresses of the fully unrolled loops below out of the time loop (they would
-  // not fit in registers at four waves per SIMD)
+  // per-lane addresses of the fully unrolled loops below out of the time loop
   int tx;
   asm volatile("v_mov_b32 %0, %1" : "=v"(tx) : "v"((int)threadIdx.x));
   s = __builtin_amdgcn_readfirstlane(s);
@@ -385,21 +437,15 @@ __device__ void bulge_step(double *__restrict__ Bd, double *__restrict__ A, int 
   const int lane = tx & 63;
   const bool lo = lane < 32;
   const int i = lo ? lane : lane - 32;
-  const int r0 = s + 1 + j * b, r1 = min(r0 + b, n), len = r1 - r0;
-  const int nr = min(b, n - r1);  // rows of R (0 on the last step of the sweep)
+  const int r0 = s + 1 + j * b, len = min(b, n - r0), r1 = r0 + len;
+  const int nr = min(b, n - r1);  // rows of R (0 on the last step of a sweep)
   const bool isRow = lo && i < len, isR = !lo && i < nr;
-  const unsigned ic = (unsigned)min(i, len - 1);
-  const unsigned oW = (unsigned)r0 * LB + ic;  // D(i, k) at oW + k LD1 for k <= i
-  const unsigned oR = (unsigned)r0 * LB + (unsigned)len + (unsigned)min(i, max(nr - 1, 0));  // R(i, k) at oR + k LD1
-  const unsigned o = lo ? oW : oR;
-  const unsigned oX = (j == 0) ? (unsigned)s * LB + 1u + ic : o;  // column s below its diagonal (step 0)
-  const double x = Bd[oX];
-  double row[b];
-#pragma unroll
-  for (int k = 0; k < b; ++k) row[k] = Bd[o + (unsigned)min(k, len - 1) * LD1];
+  const unsigned vl = (unsigned)lane * 8u;       // lane part of every byte offset
+  const unsigned base = (unsigned)r0 * LB * 8u;  // the step's window
   double *vs = slot + 1;
   double tau, v;
   if (j == 0) {
+    // reflector from x = B(s + 1 + i, s)
     const double sigma = wave_sum(isRow && i >= 1 ? x * x : 0.0);
     const double alpha = __shfl(x, 0, 64);
     double beta, sc;
@@ -413,32 +459,31 @@ __device__ void bulge_step(double *__restrict__ Bd, double *__restrict__ A, int 
       sc = 1.0 / (alpha - beta);
     }
     v = isRow ? (i == 0 ? 1.0 : x * sc) : 0.0;
-    if (isRow) {
-      Bd[oX] = (i == 0) ? beta : 0.0;
-      A[(long long)(n - 1 - s) * ld + i] = (i == 0) ? tau : v;
-    }
+    // column s: beta on the subdiagonal, zeros below (the D lanes past the matrix rewrite zeros)
+    band_store(band, (i == 0) ? beta : 0.0, lane_select(lane_mask(0xFFFFFFFFu, 0u), kBandOob, (unsigned)(1 + i) * 8u),
+               (unsigned)s * LB * 8u);
+    if (isRow) A[(long long)(n - 1 - s) * ld + i] = (i == 0) ? tau : v;
     if (lo) vs[i] = v;
   } else {
     tau = slot[0];
     v = isRow ? vs[i] : 0.0;
   }
   __builtin_amdgcn_wave_barrier();
-  // (c) the D lanes park their lower rows in the tile and read back full symmetric rows
+  // (c) the D lanes park their rows in the tile and read back full symmetric rows: entry k of
+  // row i is tile(max(i, k), min(i, k)), at 33 max + min = 32 max + i + k
   if (lo) {
 #pragma unroll
-    for (int k = 0; k < b; ++k) wt[i * TS + k] = isRow ? row[k] : 0.0;
+    for (int k = 0; k < b; ++k) wt[i * TS + k] = row[k];
   }
   __builtin_amdgcn_wave_barrier();
-  if (isRow) {
-    // one read per entry, its address selected: the lane's own row on and below the diagonal,
-    // column i of the parked rows above it
+  if (lo) {
 #pragma unroll
-    for (int k = 0; k < b; ++k) row[k] = wt[(k <= i) ? i * TS + k : k * TS + i];
+    for (int k = 0; k < b; ++k) row[k] = wt[32 * max(i, k) + i + k];
   }
-  double pdot = 0.0;
+  double pd[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int k = 0; k < b; ++k) pdot += row[k] * vs[k];
-  const double p = tau * pdot;
+  for (int k = 0; k < b; ++k) pd[k & 3] = fma(row[k], vs[k], pd[k & 3]);
+  const double p = tau * ((pd[0] + pd[1]) + (pd[2] + pd[3]));
   const double vp = wave_sum(isRow ? v * p : 0.0);
   const double w = p - 0.5 * tau * vp * v;
   if (lo) wsv[i] = isRow ? w : 0.0;
@@ -450,13 +495,6 @@ __device__ void bulge_step(double *__restrict__ Bd, double *__restrict__ A, int 
     const double ca = isRow ? v : 0.0, cb = isRow ? w : (isR ? p : 0.0);
 #pragma unroll
     for (int k = 0; k < b; ++k) row[k] = fma(-cb, vs[k], fma(-ca, wsv[k], row[k]));
-  }
-  if (isRow) {
-    // the part above the diagonal goes to the lane's own slot of the sink (one base, the offset
-    // selected: no branch per column)
-    const unsigned own = (unsigned)(sink - Bd) + (unsigned)lane;
-#pragma unroll
-    for (int k = 0; k < b; ++k) Bd[(k <= i) ? oW + (unsigned)k * LD1 : own] = row[k];
   }
   if (nr >= 2) {
     // (a) H_{j+1} from x = R(:, 0)
@@ -474,7 +512,7 @@ __device__ void bulge_step(double *__restrict__ Bd, double *__restrict__ A, int 
       sc = 1.0 / (alpha - beta);
     }
     const double v1 = isR ? (i == 0 ? 1.0 : x1 * sc) : 0.0;
-    row[0] = (i == 0) ? beta : 0.0;
+    if (!lo) row[0] = (i == 0) ? beta : 0.0;
     if (isR) A[(long long)(n - 1 - s) * ld + (j + 1) * b + i] = (i == 0) ? tau1 : v1;
     // the slot passes H_{j+1} to the next step (every read of H_j above comes first)
     __builtin_amdgcn_wave_barrier();
@@ -483,34 +521,38 @@ __device__ void bulge_step(double *__restrict__ Bd, double *__restrict__ A, int 
     // (b) R(:, 1:) <- H_{j+1} R(:, 1:), column dots through the tile
     if (!lo) {
 #pragma unroll
-      for (int c = 1; c < b; ++c) wt[i * TS + c] = isR ? v1 * row[c] : 0.0;
+      for (int c = 1; c < b; ++c) wt[i * TS + c] = v1 * row[c];
     }
     __builtin_amdgcn_wave_barrier();
     if (lo && i >= 1) {
-      double d = 0.0;
+      double dq[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int q = 0; q < b; ++q) d += wt[q * TS + i];
-      wsv[i] = tau1 * d;
+      for (int q = 0; q < b; ++q) dq[q & 3] += wt[q * TS + i];
+      wsv[i] = tau1 * ((dq[0] + dq[1]) + (dq[2] + dq[3]));
     }
     __builtin_amdgcn_wave_barrier();
-    if (isR) {
+    if (!lo) {
 #pragma unroll
       for (int c = 1; c < b; ++c) row[c] -= v1 * wsv[c];
     }
   }
-  if (isR) {
+  // D rows on and below the diagonal inside the window, and all R rows (past the last column
+  // the R offsets fall past the end of the array), one store per k
+  const unsigned in_win = len >= 32 ? 0xFFFFFFFFu : ((1u << len) - 1u);
 #pragma unroll
-    for (int k = 0; k < b; ++k) Bd[oR + (unsigned)k * LD1] = row[k];
+  for (int k = 0; k < b; ++k) {
+    const unsigned long long keep = lane_mask((0xFFFFFFFFu << k) & in_win, 0xFFFFFFFFu);
+    band_store(band, row[k], lane_select(keep, kBandOob, vl) + (unsigned)k * LD1 * 8u, base);
   }
 }
 
-// Sweeps in flight at one time step: at most ceil(steps / 3) <= 10 (n <= kMaxDimTri), so 16
+// Sweeps in flight at one time step: at most ceil(steps / 2) <= 15 (n <= kMaxDimTri), so 16
 // slots indexed by s mod 16 are never shared by two live sweeps.
 constexpr int kSweepSlots = 16;
-// Wavefronts per chase workgroup: at most about ten sweeps are in flight at a time step, and
-// more waves per cluster hide the latency of each step without adding clusters in flight.
+// Wavefronts per chase workgroup: about n / 64 sweeps are in flight at a time step, and more
+// waves per cluster hide the latency of each step without adding clusters in flight.
 constexpr int kChaseWaves = 8;
-static_assert(3 * kSweepSlots > (kMaxDimTri - 3) / kBand + 1, "sweep slots");
+static_assert(2 * kSweepSlots > (kMaxDimTri - 3) / kBand + 1, "sweep slots");
 
 __global__ void __launch_bounds__(64 * kChaseWaves, 4) sb2st_kernel(int n_clusters, const int *__restrict__ order,
                                                     double *__restrict__ mat, const long long *__restrict__ mat_off,
@@ -519,7 +561,9 @@ __global__ void __launch_bounds__(64 * kChaseWaves, 4) sb2st_kernel(int n_cluste
   __shared__ double wsv[kChaseWaves][kBand];
   __shared__ double wtile[kChaseWaves][kBand * (kBand + 1)];
   __shared__ double slots[kSweepSlots][kBand + 1];
-  const int tid = threadIdx.x, wave = tid >> 6, nthr = blockDim.x, nw = nthr >> 6;
+  // the wave index in a scalar register: the sweep numbers and band offsets derived from it are
+  // wave-uniform (buffer offsets in vector registers would need a loop over lanes)
+  const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), nthr = blockDim.x, nw = nthr >> 6;
   constexpr int LB = kBandLd;
   for (int sidx = blockIdx.x; sidx < n_clusters; sidx += gridDim.x) {
     const int c = order[sidx];
@@ -535,13 +579,18 @@ __global__ void __launch_bounds__(64 * kChaseWaves, 4) sb2st_kernel(int n_cluste
       Bd[e] = (d <= kBand && cc + d < n) ? A[(long long)cc * ld + cc + d] : 0.0;
     }
     __syncthreads();
-    const int tend = 3 * (n - 3);
+    // raw buffer view of the band array (word 3: the gfx9 buffer format for untyped access)
+    const __amdgpu_buffer_rsrc_t band = __builtin_amdgcn_make_buffer_rsrc(Bd, (short)0, n * LB * 8, 0x00020000);
+    // time step t advances every sweep s with j = t - 2 s in range; sweep s runs on wave s mod nw
+    const int tend = 2 * (n - 3);
     for (int t = 0; t <= tend; ++t) {
-      const int shi = min(t / 3, n - 3);
-      for (int s = shi - wave; s >= 0; s -= nw) {
-        const int j = t - 3 * s;
+      const int shi = min(t / 2, n - 3);
+      for (int s = shi >= wave ? wave + (shi - wave) / nw * nw : -1; s >= 0; s -= nw) {
+        const int j = t - 2 * s;
         if (j >= sweep_steps(n, s)) break;
-        bulge_step(Bd, A, ld, n, s, j, slots[s % kSweepSlots], wsv[wave], wtile[wave], cv + vl.kg);
+        double row[kBand], x;
+        chase_fetch(band, row, x, s, j);
+        bulge_step(band, row, x, A, ld, n, s, j, slots[s % kSweepSlots], wsv[wave], wtile[wave]);
       }
       __syncthreads();
     }
