@@ -196,7 +196,10 @@ std::string device_key() {
     return "unknown";
   }
   (void)hipRuntimeGetVersion(&rt);
-  std::string name = std::string(prop.gcnArchName) + " " + prop.name + " hip " + std::to_string(rt);
+  // the architecture, the compute-unit count and the runtime: the marketing name is left out (it
+  // reads empty under some tools, which would split one device into two keys)
+  std::string name = std::string(prop.gcnArchName) + " " + std::to_string(prop.multiProcessorCount) + " CUs hip " +
+                     std::to_string(rt);
   for (char &ch : name)
     if (ch == '"' || ch == '\\') ch = ' ';
   return name;
