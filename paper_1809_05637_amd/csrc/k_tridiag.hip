@@ -385,24 +385,32 @@ __device__ inline void band_store(__amdgpu_buffer_rsrc_t band, double x, unsigne
 constexpr unsigned kBandOob = 0x80000000u;
 
 // The band array: entry (r, c), r >= c, at c kBandLd + r - c, read and written through a raw
-// buffer view of its n kBandLd doubles.  Rows past the matrix hold zeros (written when the band
-// is set up, and only zeros are stored there later).
+// buffer view of its n kBandLd doubles (entries of rows past the matrix are zero and are neither
+// read nor written by the steps).
 //
 // Loads of bulge step (s, j): element k of the lane's row (D rows on lanes 0..31, R rows on
 // lanes 32..63) sits at r0 kBandLd + k (kBandLd - 1) + lane, so one load per k serves both
-// halves, the lane offset in a register and the window in a scalar register.  D rows read their
-// part above the diagonal as it lies in memory (the tail of the previous column); rows past the
-// matrix, and on the last step of a sweep the columns past it, read zeros (the zero rows of the
-// array, or past its end).  x is B(s + 1 + lane mod 32, s), column s below its diagonal (used by
-// step 0 only).
-__device__ inline void chase_fetch(__amdgpu_buffer_rsrc_t band, double (&row)[kBand], double &x, int s, int j) {
+// halves, the lane offset in a register and the window in a scalar register.  Only entries that
+// exist are fetched: D on and below the diagonal inside the window, R rows and columns inside the
+// matrix; the other lanes are sent past the end of the buffer and read zero (the D part above the
+// diagonal is taken from the tile later).  x is B(s + 1 + lane mod 32, s), column s below its
+// diagonal (used by step 0 only).
+__device__ inline void chase_fetch(__amdgpu_buffer_rsrc_t band, double (&row)[kBand], double &x, int n, int s,
+                                   int j) {
   constexpr unsigned LB = kBandLd, LD1 = kBandLd - 1;
   const unsigned lane = threadIdx.x & 63u;
   const unsigned vl = lane * 8u;
-  const unsigned base = __builtin_amdgcn_readfirstlane((unsigned)(s + 1 + j * kBand) * LB * 8u);
+  const int r0 = __builtin_amdgcn_readfirstlane(s + 1 + j * kBand);
+  const int len = min(kBand, n - r0), nr = max(0, min(kBand, n - r0 - len));
+  const unsigned in_win = len >= 32 ? 0xFFFFFFFFu : ((1u << len) - 1u);
+  const unsigned in_r = nr >= 32 ? 0xFFFFFFFFu : ((1u << nr) - 1u);
+  const unsigned base = (unsigned)r0 * LB * 8u;
   const unsigned cs = __builtin_amdgcn_readfirstlane((unsigned)s * LB * 8u);
 #pragma unroll
-  for (int k = 0; k < kBand; ++k) row[k] = band_load(band, vl + (unsigned)k * LD1 * 8u, base);
+  for (int k = 0; k < kBand; ++k) {
+    const unsigned long long keep = lane_mask((0xFFFFFFFFu << k) & in_win, k < len ? in_r : 0u);
+    row[k] = band_load(band, lane_select(keep, kBandOob, vl) + (unsigned)k * LD1 * 8u, base);
+  }
   x = band_load(band, (1u + (lane & 31u)) * 8u, cs);
 }
 
@@ -420,9 +428,8 @@ __device__ inline void chase_fetch(__amdgpu_buffer_rsrc_t band, double (&row)[kB
 // through memory once.  The D rows take their part above the diagonal from the tile (wt:
 // kBand x (kBand + 1) doubles of the wave's LDS; wsv: kBand doubles; slot: kBand + 1 doubles of
 // the sweep).  Rows past the matrix hold zeros throughout (they read zeros, and v, w, p and v1
-// are zero on them).  D and R rows are stored together at the end, one store per k: the D
-// lanes above the diagonal or past the window are sent past the end of the buffer, R rows past
-// the matrix store their zeros.
+// are zero on them).  D and R rows are stored together at the end, one store per k: the lanes
+// of entries above the diagonal or outside the matrix are sent past the end of the buffer.
 __device__ void bulge_step(__amdgpu_buffer_rsrc_t band, double (&row)[kBand], double x, double *__restrict__ A,
                            int ld, int n, int s, int j, double *slot, double *wsv, double *wt) {
   constexpr int b = kBand, TS = kBand + 1;
@@ -536,12 +543,13 @@ __device__ void bulge_step(__amdgpu_buffer_rsrc_t band, double (&row)[kBand], do
       for (int c = 1; c < b; ++c) row[c] -= v1 * wsv[c];
     }
   }
-  // D rows on and below the diagonal inside the window, and all R rows (past the last column
-  // the R offsets fall past the end of the array), one store per k
+  // D rows on and below the diagonal inside the window, and the R rows and columns inside the
+  // matrix, one store per k
   const unsigned in_win = len >= 32 ? 0xFFFFFFFFu : ((1u << len) - 1u);
+  const unsigned in_r = nr >= 32 ? 0xFFFFFFFFu : ((1u << max(nr, 0)) - 1u);
 #pragma unroll
   for (int k = 0; k < b; ++k) {
-    const unsigned long long keep = lane_mask((0xFFFFFFFFu << k) & in_win, 0xFFFFFFFFu);
+    const unsigned long long keep = lane_mask((0xFFFFFFFFu << k) & in_win, k < len ? in_r : 0u);
     band_store(band, row[k], lane_select(keep, kBandOob, vl) + (unsigned)k * LD1 * 8u, base);
   }
 }
@@ -572,7 +580,10 @@ __global__ void __launch_bounds__(64 * kChaseWaves, 4) sb2st_kernel(int n_cluste
     const VecLayout vl = VecLayout::make(dmax[c]);
     double *cv = vec + vec_off[c];
     double *dd = cv + vl.d, *ee = cv + vl.e;
-    double *Bd = cv + vl.vw;  // n x kBandLd (reuses the band-reduction workspace)
+    // n x kBandLd from the first 128-byte boundary of the band-reduction workspace (n kBandLd + 15
+    // <= 3 kBand dmax doubles)
+    double *Bd = cv + vl.vw;
+    Bd += (16 - (int)((reinterpret_cast<unsigned long long>(Bd) >> 3) & 15)) & 15;
     __syncthreads();
     for (long long e = tid; e < (long long)n * LB; e += nthr) {
       const int cc = (int)(e / LB), d = (int)(e % LB);
@@ -589,7 +600,7 @@ __global__ void __launch_bounds__(64 * kChaseWaves, 4) sb2st_kernel(int n_cluste
         const int j = t - 2 * s;
         if (j >= sweep_steps(n, s)) break;
         double row[kBand], x;
-        chase_fetch(band, row, x, s, j);
+        chase_fetch(band, row, x, n, s, j);
         bulge_step(band, row, x, A, ld, n, s, j, slots[s % kSweepSlots], wsv[wave], wtile[wave]);
       }
       __syncthreads();

@@ -155,9 +155,11 @@ struct Plan {
 
 // vector workspace offsets inside a cluster's double region (n = dimension bound)
 // Band width of the reduction to band form and the row stride of the band array used by
-// the bulge chasing (lower band plus bulge: 2 kBand + 1 diagonals, padded to even).
+// the bulge chasing (lower band plus bulge: 2 kBand + 1 diagonals, padded to 80 doubles, five
+// 128-byte cache lines, so that every column of the line-aligned array starts on a line).
 constexpr int kBand = 32;
-constexpr int kBandLd = 2 * kBand + 2;
+constexpr int kBandLd = 80;
+static_assert(kBandLd >= 2 * kBand + 1 && kBandLd % 16 == 0, "band array stride");
 // Largest reduced cluster dimension (the panel QR holds 8 columns of the panel in LDS and a
 // column in 15 registers per lane).
 constexpr int kMaxDimTri = 960;
@@ -178,12 +180,13 @@ struct VecLayout {
     v.y0 = o; o += (long long)n * kMaxOrb;
     v.y1 = o; o += (long long)n * kMaxOrb;
     // reduction to band form: [V | W] (n x 2 kBand, row-major), -V T (n x kBand, row-major),
-    // K and G (kBand x kBand each); the band array of the bulge chasing (n x kBandLd) reuses
-    // this space once the band form is complete
+    // K and G (kBand x kBand each); the band array of the bulge chasing (n x kBandLd, from the
+    // first 128-byte boundary) reuses this space once the band form is complete
     v.vw = o; o += (long long)n * 2 * kBand;
     v.vt = o; o += (long long)n * kBand;
     v.kg = o; o += 2LL * kBand * kBand;
     v.dc = o;
+    static_assert(3 * kBand >= kBandLd, "the band array fits the [V | W] and -V T space");
     return v;
   }
   __host__ __device__ static long long total(int n) {
