@@ -23,8 +23,8 @@ static_assert(4 * kMaxDimTri + (kMaxDimTri + 1) / 2 + kApplyChunk * kMaxOrb <= k
 
 // Q2 r with r in LDS, kept out of line: inlined into the density kernel it raises the register
 // pressure of the whole kernel and spills (44.8 vs 94 ms per build on the 3920-atom slab)
-__device__ __noinline__ void density_q2_lds(const double *A, int n, double *Xs, int nc, double *runs, int rstride) {
-  wg_apply_q2_lds(A, n, Xs, nc, runs, rstride, false);
+__device__ __noinline__ void density_q2_lds(const double *A, int n, double *Xs, int nc, double *runs) {
+  wg_apply_q2_lds(A, n, Xs, nc, runs, false);
 }
 
 // state layout of Plan::d_mu
@@ -252,10 +252,11 @@ __global__ void __launch_bounds__(256, 2) density_kernel(
     // panels (T factors stored by the band reduction)
     if (q2_lds && n >= 3) {
       __syncthreads();  // the merge staging in the same LDS is done
-      double *Xs = qlds, *runs = qlds + (long long)max_dim * M;
-      for (int e = tid; e < n * M; e += nthr) Xs[e] = r[(long long)(e / M) * kMaxOrb + e % M];
-      density_q2_lds(A, n, Xs, M, runs, max_dim);
-      for (int e = tid; e < n * M; e += nthr) r[(long long)(e / M) * kMaxOrb + e % M] = Xs[e];
+      const int P = q2_lds_stride(n);
+      double *Xs = qlds, *runs = qlds + (long long)M * P;
+      for (int e = tid; e < n * M; e += nthr) Xs[(long long)(e % M) * P + e / M] = r[(long long)(e / M) * kMaxOrb + e % M];
+      density_q2_lds(A, n, Xs, M, runs);
+      for (int e = tid; e < n * M; e += nthr) r[(long long)(e / M) * kMaxOrb + e % M] = Xs[(long long)(e % M) * P + e / M];
       __syncthreads();
     } else {
       wg_apply_q2(A, ld, n, r, kMaxOrb, M, false);
@@ -346,12 +347,12 @@ void launch_mu_step(Plan &p, double, double, double) {
 void launch_density(Plan &p, int mode, double *d_D, const double *d_H, const double *d_S, double w_lo, double w_hi,
                     double w_kT) {
   double *cl_partial = p.d_partial + kMuStride * p.workgroups;
-  // the Q2 product runs in LDS when the n x M rows and three reflector runs of the bucket's
-  // largest cluster still let two workgroups share a CU (72 KB each besides the 6 KB of static
-  // LDS)
+  // the Q2 product runs in LDS when the M padded columns and three reflector runs of the
+  // bucket's largest cluster still let two workgroups share a CU (72 KB each besides the 6 KB of
+  // static LDS)
   const int dm = cur_dim(p);
   const size_t base = sizeof(double) * kQapplyLds;
-  const size_t q2 = sizeof(double) * (size_t)dm * (size_t)(p.mmax + 3);
+  const size_t q2 = sizeof(double) * (size_t)q2_lds_stride(dm) * (size_t)(p.mmax + 3);
   int q2_lds = q2 <= 72 * 1024;
   if (q2_lds && q2 > 64 * 1024 &&
       hipFuncSetAttribute(reinterpret_cast<const void *>(density_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -631,13 +631,14 @@ __global__ void __launch_bounds__(256, 2) q2x_lds_kernel(int n_clusters, const i
     const double *A = mat + mat_off[c];
     const VecLayout vl = VecLayout::make(dmax[c]);
     double *X = vec + vec_off[c] + vl.G0 + half * nc;  // n x nc of the n x kTrack row-major block
-    double *Xs = q2l;                                  // n x nc
-    double *runs = q2l + (long long)max_dim * nc;      // 3 x max_dim
+    const int P = q2_lds_stride(n);
+    double *Xs = q2l;                                  // nc columns of P rows
+    double *runs = q2l + (long long)nc * P;            // 3 x P
     __syncthreads();
     if (n < 3) continue;
-    for (int e = tid; e < n * nc; e += nthr) Xs[e] = X[(e / nc) * kTrack + e % nc];
-    wg_apply_q2_lds(A, n, Xs, nc, runs, max_dim, true);
-    for (int e = tid; e < n * nc; e += nthr) X[(e / nc) * kTrack + e % nc] = Xs[e];
+    for (int e = tid; e < n * nc; e += nthr) Xs[(long long)(e % nc) * P + e / nc] = X[(e / nc) * kTrack + e % nc];
+    wg_apply_q2_lds(A, n, Xs, nc, runs, true);
+    for (int e = tid; e < n * nc; e += nthr) X[(e / nc) * kTrack + e % nc] = Xs[(long long)(e % nc) * P + e / nc];
   }
 }
 
@@ -679,7 +680,7 @@ void launch_sb2st(Plan &p) {
 
 void launch_q2x(Plan &p) {
   const int dm = cur_dim(p);
-  const size_t lds = sizeof(double) * (size_t)dm * (size_t)(p.mmax + 3);
+  const size_t lds = sizeof(double) * (size_t)q2_lds_stride(dm) * (size_t)(p.mmax + 3);
   int dev = 0, lds_max = 0;
   const bool fits = hipGetDevice(&dev) == hipSuccess &&
                     hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&

@@ -216,14 +216,22 @@ __device__ void wg_apply_q2(const double *__restrict__ A, int ld, int n, double 
   }
 }
 
-// The same product with X held in LDS (n >= 3; nc <= 16 columns, row-major with row stride nc):
-// the only global reads are the reflectors, one contiguous run per sweep (n - 1 - s doubles of
-// column n - 1 - s of A from row 0: per step tau, then v(1:len)), fetched two sweeps ahead into
-// registers and parked in a triple buffer of LDS (runs: 3 x rstride doubles, rstride >= n), one
-// barrier per sweep.  Groups of 16 lanes take one reflector each, lane q one column.  Q2^T runs
-// the sweeps forwards, Q2 backwards.  Starts with the run prefetch (so a fill of Xs needs no
-// barrier of its own before the call) and ends with a barrier.
-constexpr int kQ2Run = (kMaxDimTri + kWG - 1) / kWG;  // run elements per thread
+// The same product with X held in LDS (n >= 3; nc <= 16 columns, column-major: column q at
+// Xs + q P, P = q2_lds_stride(n)): the only global reads are the reflectors, one contiguous run
+// per sweep (n - 1 - s doubles of column n - 1 - s of A from row 0: per step tau, then v(1:len)),
+// fetched two sweeps ahead into registers and parked in a triple buffer of LDS (runs: 3 x P
+// doubles), one barrier per sweep.  Groups of 16 lanes take one reflector each, lane q one
+// column.  The rows n .. P - 1 of every column and the kBand entries past the end of every
+// parked run are zero, so every reflector, the last of a sweep too, runs over kBand rows with
+// no clamping or masking (its entries past the run are zero and its rows past n stay zero), and
+// every LDS offset is a lane base plus a constant.  Q2^T runs the sweeps forwards, Q2 backwards.
+// Zeroes the padding rows and starts with the run prefetch (so a fill of Xs needs no barrier of
+// its own before the call); ends with a barrier.
+constexpr int kQ2Run = (kMaxDimTri + kBand + kWG - 1) / kWG;  // run elements per thread
+
+// column stride of the LDS copy of X: at least n + kBand rows, odd (the columns of a group then
+// start in distinct banks)
+__host__ __device__ inline int q2_lds_stride(int n) { return (n + kBand) | 1; }
 
 __device__ inline void q2_fetch_run(double *nx, const double *A, int n, int s, int tid, int nthr) {
   // run of sweep s (clamped unconditional loads; a sweep outside 0..n-3 reads its nearest)
@@ -233,39 +241,46 @@ __device__ inline void q2_fetch_run(double *nx, const double *A, int n, int s, i
   for (int u = 0; u < kQ2Run; ++u) nx[u] = src[min(tid + u * nthr, len - 1)];
 }
 
-__device__ void wg_apply_q2_lds(const double *__restrict__ A, int n, double *Xs, int nc, double *runs, int rstride,
+__device__ void wg_apply_q2_lds(const double *__restrict__ A, int n, double *Xs, int nc, double *runs,
                                 bool transpose) {
   constexpr int b = kBand;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int grp = tid >> 4, q = tid & 15, ngrp = nthr >> 4;
+  const int P = q2_lds_stride(n);
   const int qc = min(q, nc - 1);
+  double *xcol = Xs + (long long)qc * P;
   const int nsw = n - 2;  // sweeps 0 .. n-3
   auto sweep = [&](int it) { return max(0, min(transpose ? it : nsw - 1 - it, n - 3)); };
+  // a parked run: its n - 1 - s entries, then kBand zeros
+  auto park = [&](double *dst, const double *nx, int it) {
+    const int nlen = n - 1 - sweep(it);
+#pragma unroll
+    for (int u = 0; u < kQ2Run; ++u) {
+      const int e = tid + u * nthr;
+      if (e < nlen + b) dst[e] = e < nlen ? nx[u] : 0.0;
+    }
+  };
+  for (int e = tid; e < nc * (P - n); e += nthr) Xs[(long long)(e / (P - n)) * P + n + e % (P - n)] = 0.0;
   double nx0[kQ2Run], nx1[kQ2Run];
   q2_fetch_run(nx0, A, n, sweep(0), tid, nthr);
   q2_fetch_run(nx1, A, n, sweep(1), tid, nthr);
-  const int len0 = n - 1 - sweep(0);
-#pragma unroll
-  for (int u = 0; u < kQ2Run; ++u)
-    if (tid + u * nthr < len0) runs[tid + u * nthr] = nx0[u];
+  park(runs, nx0, 0);
   __syncthreads();
   for (int it = 0; it < nsw; ++it) {
     const int s = sweep(it);
     // nx1 holds the run of the next sweep; fetch the one after
     q2_fetch_run(nx0, A, n, sweep(it + 2), tid, nthr);
-    const double *cur = runs + (it % 3) * rstride;
+    const double *cur = runs + (it % 3) * P;
     const int nst = (n - 3 - s) / b + 1;
     for (int j = grp; j < nst; j += ngrp) {
-      const int r0 = s + 1 + j * b, len = min(b, n - r0);
+      const int r0 = s + 1 + j * b;
       const double *vp = cur + j * b;
-      double *xp = Xs + (long long)r0 * nc + qc;
+      double *xp = xcol + r0;
       double vv[b], xv[b];
 #pragma unroll
       for (int i = 0; i < b; ++i) {
-        const int ii = min(i, len - 1);
-        const double t = vp[ii];
-        vv[i] = (i < len) ? t : 0.0;
-        xv[i] = xp[ii * nc];
+        vv[i] = vp[i];
+        xv[i] = xp[i];
       }
       const double tau = vv[0];
       vv[0] = 1.0;
@@ -275,15 +290,10 @@ __device__ void wg_apply_q2_lds(const double *__restrict__ A, int n, double *Xs,
       d *= tau;
       if (q < nc) {
 #pragma unroll
-        for (int i = 0; i < b; ++i)
-          if (i < len) xp[i * nc] = xv[i] - d * vv[i];
+        for (int i = 0; i < b; ++i) xp[i] = xv[i] - d * vv[i];
       }
     }
-    double *nxt = runs + ((it + 1) % 3) * rstride;
-    const int nlen = n - 1 - sweep(it + 1);
-#pragma unroll
-    for (int u = 0; u < kQ2Run; ++u)
-      if (tid + u * nthr < nlen) nxt[tid + u * nthr] = nx1[u];
+    park(runs + ((it + 1) % 3) * P, nx1, it + 1);
 #pragma unroll
     for (int u = 0; u < kQ2Run; ++u) nx1[u] = nx0[u];
     __syncthreads();
