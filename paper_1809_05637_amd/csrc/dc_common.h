@@ -114,13 +114,26 @@ __device__ inline double *dc_apply_nc(int n, int ny, DcWs ws, double *ya, double
 #pragma unroll
       for (int cc = 0; cc < NC; ++cc) acc[cc] = 0.0;
       const int rlo = qb - qb % span, rhi = min(n, ((min(qb + nthr, n) - 1) / span + 1) * span);
+      // each chunk of y rows is fetched into registers while the previous one is used
+      constexpr int PER = (kApplyChunk * kMaxOrb + 255) / 256;
+      double pre[PER];
+      auto fetch_chunk = [&](int c0) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+          const int e = tid + u * nthr, r = e / ny, cc = e % ny;
+          pre[u] = (e < kApplyChunk * ny && c0 + r < n) ? yb[(long long)(c0 + r) * kMaxOrb + cc] : 0.0;
+        }
+      };
+      if (rlo < rhi) fetch_chunk(rlo);
       for (int c0 = rlo; c0 < rhi; c0 += kApplyChunk) {
         __syncthreads();
-        for (int e = tid; e < kApplyChunk * ny; e += nthr) {
-          const int r = e / ny, cc = e % ny;
-          sy[r * kMaxOrb + cc] = (c0 + r < n) ? yb[(long long)(c0 + r) * kMaxOrb + cc] : 0.0;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+          const int e = tid + u * nthr;
+          if (e < kApplyChunk * ny) sy[(e / ny) * kMaxOrb + e % ny] = pre[u];
         }
         __syncthreads();
+        if (c0 + kApplyChunk < rhi) fetch_chunk(c0 + kApplyChunk);
         if (kept) {
           const int ta = max(c0, lo), tb = min(c0 + kApplyChunk, lo + kp);
           for (int t = ta; t < tb; ++t) {
