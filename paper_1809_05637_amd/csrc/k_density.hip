@@ -17,14 +17,19 @@
 
 namespace ldc {
 
-// the product Z y stages its data in the compact-WY LDS area
-static_assert(4 * kMaxDimTri + (kMaxDimTri + 1) / 2 + kApplyChunk * kMaxOrb <= kQapplyLds,
-              "dc_apply staging must fit the compact-WY LDS area");
+// dynamic LDS besides the Q2 product's: the staging of the product Z y and the partial
+// products of Q1 r
+constexpr int kDensityLds = std::max(4 * kMaxDimTri + (kMaxDimTri + 1) / 2 + kApplyChunk * kMaxOrb, kQ1Lds);
 
 // Q2 r with r in LDS, kept out of line: inlined into the density kernel it raises the register
 // pressure of the whole kernel and spills (44.8 vs 94 ms per build on the 3920-atom slab)
 __device__ __noinline__ void density_q2_lds(const double *A, int n, double *Xs, int nc, double *runs) {
   wg_apply_q2_lds(A, n, Xs, nc, runs, false);
+}
+
+// Q1 r, kept out of line for the same reason: it holds r in registers
+__device__ __noinline__ void density_q1(const double *A, int n, const double *Tq, double *r, int M, double *lds) {
+  wg_apply_q1(A, n, Tq, r, M, lds);
 }
 
 // state layout of Plan::d_mu
@@ -235,7 +240,6 @@ __global__ void __launch_bounds__(256, 2) density_kernel(
     ws.dci = ivec + ivec_off[c];
     const double *A = mat + mat_off[c];
     const double *L = A + (long long)dmax[c] * dmax[c];
-    const double *tt = cv + vl.tau;
     double *ya = cv + vl.y0, *yb = cv + vl.y1;
     __syncthreads();
     // y = w o u with the mode's weights w
@@ -261,7 +265,7 @@ __global__ void __launch_bounds__(256, 2) density_kernel(
     } else {
       wg_apply_q2(A, ld, n, r, kMaxOrb, M, false);
     }
-    wg_apply_q(A, ld, n, tt, cv + vl.u, false, r, kMaxOrb, M, false, qlds, kBand);
+    density_q1(A, n, cv + vl.u, r, M, qlds);
     // x_P = L_PP^{-T} r_P = ((L^{-1})_PP)^T r_P (P = the last p rows; the S slot holds L^{-1}):
     // x(g) = sum_{t >= g} Linv(t, g) r(t), written to the other buffer
     const int b0 = n - p;
@@ -351,7 +355,7 @@ void launch_density(Plan &p, int mode, double *d_D, const double *d_H, const dou
   // bucket's largest cluster still let two workgroups share a CU (72 KB each besides the 6 KB of
   // static LDS)
   const int dm = cur_dim(p);
-  const size_t base = sizeof(double) * kQapplyLds;
+  const size_t base = sizeof(double) * kDensityLds;
   const size_t q2 = sizeof(double) * (size_t)q2_lds_stride(dm) * (size_t)(p.mmax + 3);
   int q2_lds = q2 <= 72 * 1024;
   if (q2_lds && q2 > 64 * 1024 &&

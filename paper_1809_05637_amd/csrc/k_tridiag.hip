@@ -314,7 +314,7 @@ __device__ __noinline__ void band_panel(double *__restrict__ A, int ld, int n, i
 
 // ---------------------------------------------------------------------------------------
 // Stage 1: reduction to band form (see the top of the file).  Dynamic LDS: max(LEAF * nmax,
-// kGemmLds, kGemmLdsTall, kQapplyLds, kAtbLds) doubles.
+// kGemmLds, kGemmLdsTall, kAtbLds) doubles.
 __global__ void __launch_bounds__(256, 2) sy2sb_kernel(int n_clusters, const int *__restrict__ order,
                                                        double *__restrict__ mat, const long long *__restrict__ mat_off,
                                                        double *__restrict__ vec, const long long *__restrict__ vec_off,
@@ -661,7 +661,7 @@ __global__ void __launch_bounds__(256, 2) q2x_kernel(int n_clusters, const int *
 // ---------------------------------------------------------------------------------------
 void launch_sy2sb(Plan &p) {
   const size_t lds = sizeof(double) * std::max({(size_t)LEAF * cur_dim(p), (size_t)kGemmLds, (size_t)kGemmLdsTall,
-                                                (size_t)kQapplyLds, (size_t)kAtbLds});
+                                                (size_t)kAtbLds});
   const int n = cur_count(p);
   const int grid = std::max(1, std::min(stage_grid(p, kTSy2sb, p.workgroups), n));
   hipLaunchKernelGGL(sy2sb_kernel, dim3(grid), dim3(kWG), lds, p.stream, n, cur_order(p), p.d_mat, p.d_mat_off,

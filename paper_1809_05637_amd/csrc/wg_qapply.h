@@ -1,178 +1,199 @@
-// Products with an orthogonal factor Q = H_0 H_1 ... H_{n-1-sh} stored as Householder
-// reflectors below a band of width sh: H_k = I - tau_k v_k v_k^T, v_k(0:k+sh) = 0,
-// v_k(k+sh) = 1, v_k(k+sh+1:) stored in A(k+sh+1:, k) (column-major, leading dimension ld).
-// sh = 1 is the one-stage tridiagonalization, sh = b the reduction to band form.  Reflectors
-// are grouped in panels of QP columns; a panel's product is I - V T V^T with T upper
-// triangular (compact WY form): T(a,a) = tau_a, T(0:a, a) = -tau_a T(0:a, 0:a) (V(:, 0:a)^T v_a).
+// Products with the orthogonal factors of the two-stage tridiagonalization, Q = Q1 Q2.
+//
+// Q1 (reduction to band form, b = kBand): H_0 H_1 ... H_{n-1-b}, H_k = I - tau_k v_k v_k^T,
+// v_k(0:k+b) = 0, v_k(k+b) = 1, v_k(k+b+1:) stored in A(k+b+1:, k) (column-major, leading
+// dimension n).  The reflectors come in panels of b, panel p = reflectors 32 p .. 32 p + 31,
+// whose product is I - V T V^T (compact WY) with T upper triangular, stored row-major by the
+// band reduction, one b x b block per panel.
 #pragma once
 
 #include "dev_common.h"
+#include "wg_blas.h"
 
 namespace ldc {
 
-constexpr int QP = 32;      // reflectors per panel
-constexpr int QCH = 32;     // rows of V staged in LDS per step
-constexpr int QXC = 32;     // largest number of columns of X
-constexpr int QS = QP + 1;  // LDS row stride
+constexpr int kQ1Slots = (kMaxDimTri + 63) / 64;  // 16-row chunks of X per wave
+constexpr int kQ1Lds = 2 * 4 * 512;                // two buffers of the four waves' partial Y
 
-// LDS (doubles) needed by wg_apply_q.
-constexpr int kQapplyLds = QCH * QS + 3 * QP * QS + QCH * (QXC + 1);
-
-// X (n rows, ncol <= QXC columns, row-major with row stride ldx) <- Q^T X (transpose) or
-// Q X.  With make_T the panels' T factors are formed and stored in Tq (QP*QP per panel,
-// row-major); otherwise the stored ones are used.  Whole workgroup (256 threads); lds:
-// kQapplyLds.
-__device__ void wg_apply_q(const double *__restrict__ A, int ld, int n, const double *__restrict__ tau, double *Tq,
-                           bool make_T, double *X, int ldx, int ncol, bool transpose, double *lds, int sh = 1) {
-  const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, wave = tid >> 6;
-  double *Vc = lds;              // [QCH][QS]
-  double *G = Vc + QCH * QS;     // [QP][QS]  V^T V
-  double *T = G + QP * QS;       // [QP][QS]
-  double *Y = T + QP * QS;       // [QP][QS]  V^T X, then T' V^T X
-  double *Xc = Y + QP * QS;      // [QCH][QXC+1] rows of X
-  constexpr int NACC = (QP * QP + QP * QXC) / 256;  // entries per thread (8)
-  constexpr int NST = QCH * QP / 256;               // staged V (and X) entries per thread (4)
-  static_assert(QCH * QXC <= NST * 256, "X staging");
-  const int nref = n - sh;                          // reflectors 0..n-1-sh
-  const int npan = nref > 0 ? (nref + QP - 1) / QP : 0;
-  for (int pi = 0; pi < npan; ++pi) {
-    const int p = transpose ? pi : (npan - 1 - pi);
-    const int p0 = p * QP, nbp = min(QP, nref - p0);
-    const int nG = make_T ? QP * QP : 0;
-    const int nE = nG + QP * ncol;
-    // Staging of QCH rows from r0: V entry e = tid + 256 u at (row e % QCH, reflector e / QCH),
-    // X entry e at (row e / ncol, column e % ncol).  Loads are clamped into range and
-    // unconditional (the next chunk is fetched while the current one is used); values outside
-    // the reflectors or past row n are masked.
-    auto fetch = [&](int r0, double *rv, double *rx) {
-#pragma unroll
-      for (int u = 0; u < NST; ++u) {
-        const int e = tid + u * nthr, rr = e % QCH, t = e / QCH;
-        const int r = r0 + rr, k = p0 + t;
-        const double a = A[(long long)min(k, p0 + nbp - 1) * ld + min(r, n - 1)];
-        const bool in = t < nbp && r < n;
-        rv[u] = (in && r > k + sh) ? a : ((in && r == k + sh) ? 1.0 : 0.0);
-        const int xr = r0 + e / ncol, xq = e % ncol;
-        const double x = X[(long long)min(xr, n - 1) * ldx + xq];
-        rx[u] = (e < QCH * ncol && xr < n) ? x : 0.0;
-      }
-    };
-    auto stage = [&](const double *rv, const double *rx) {
-#pragma unroll
-      for (int u = 0; u < NST; ++u) {
-        const int e = tid + u * nthr;
-        Vc[(e % QCH) * QS + e / QCH] = rv[u];
-        if (e < QCH * ncol) Xc[(e / ncol) * (QXC + 1) + e % ncol] = rx[u];
-      }
-    };
-    double rv[NST], rx[NST];
-    double acc[NACC];
-#pragma unroll
-    for (int q = 0; q < NACC; ++q) acc[q] = 0.0;
-    fetch(p0 + sh, rv, rx);
-    for (int r0 = p0 + sh; r0 < n; r0 += QCH) {
-      __syncthreads();
-      stage(rv, rx);
-      __syncthreads();
-      if (r0 + QCH < n) fetch(r0 + QCH, rv, rx);
-      // whole chunks (rows past n are staged as zeros): fixed trip counts keep the LDS reads
-      // in flight together
-#pragma unroll
-      for (int q = 0; q < NACC; ++q) {
-        const int e = tid + q * 256;
-        if (e < nE) {
-          double s = 0.0;
-          if (e < nG) {
-            const int a = e / QP, b = e % QP;
-            if (a < b) {
-#pragma unroll 8
-              for (int rr = 0; rr < QCH; ++rr) s += Vc[rr * QS + a] * Vc[rr * QS + b];
-            }
-          } else {
-            const int a = (e - nG) / ncol, qq = (e - nG) % ncol;
-#pragma unroll 8
-            for (int rr = 0; rr < QCH; ++rr) s += Vc[rr * QS + a] * Xc[rr * (QXC + 1) + qq];
-          }
-          acc[q] += s;
-        }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < NACC; ++q) {
-      const int e = tid + q * 256;
-      if (e < nE) {
-        if (e < nG) G[(e / QP) * QS + e % QP] = acc[q];
-        else Y[((e - nG) / ncol) * QS + (e - nG) % ncol] = acc[q];
-      }
-    }
-    // the first chunk of the second pass is fetched while T and T'Y are formed
-    fetch(p0 + sh, rv, rx);
-    __syncthreads();
-    double *Tp = Tq + (long long)p * QP * QP;
-    if (make_T) {
-      // lane a of wave 0 forms row a of T: T(a, i) = -tau_i sum_{b=a}^{i-1} T(a, b) G(b, i)
-      if (wave == 0 && lane < QP) {
-        const int a = lane;
-        for (int i = 0; i < QP; ++i) {
-          double t;
-          if (i >= nbp || i < a) t = 0.0;
-          else if (i == a) t = tau[p0 + i];
-          else {
-            double sacc = 0.0;
-            for (int b = a; b < i; ++b) sacc += T[a * QS + b] * G[b * QS + i];
-            t = -tau[p0 + i] * sacc;
-          }
-          T[a * QS + i] = t;
-          Tp[a * QP + i] = t;
-        }
-      }
-    } else {
-      for (int e = tid; e < QP * QP; e += nthr) T[(e / QP) * QS + e % QP] = Tp[e];
-    }
-    __syncthreads();
-    // Y <- T^T Y (transpose) or T Y
-    double z[(QP * QXC) / 256];
-#pragma unroll
-    for (int q = 0; q < (QP * QXC) / 256; ++q) {
-      const int e = tid + q * 256;
-      double s = 0.0;
-      if (e < QP * ncol) {
-        const int a = e / ncol, qq = e % ncol;
-        if (transpose) {
-          for (int b = 0; b <= a; ++b) s += T[b * QS + a] * Y[b * QS + qq];
-        } else {
-          for (int b = a; b < QP; ++b) s += T[a * QS + b] * Y[b * QS + qq];
-        }
-      }
-      z[q] = s;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < (QP * QXC) / 256; ++q) {
-      const int e = tid + q * 256;
-      if (e < QP * ncol) Y[(e / ncol) * QS + e % ncol] = z[q];
-    }
-    // X(r, :) <- X(r, :) - V(r, :) Y, V and X staged in LDS by chunks of QCH rows
-    for (int r0 = p0 + sh; r0 < n; r0 += QCH) {
-      __syncthreads();
-      stage(rv, rx);
-      __syncthreads();
-      if (r0 + QCH < n) fetch(r0 + QCH, rv, rx);
-      const int rmax = min(QCH, n - r0);
-      for (int e = tid; e < rmax * ncol; e += nthr) {
-        const int rr = e / ncol, q = e % ncol;
-        double s = 0.0;
-#pragma unroll 8
-        for (int t = 0; t < QP; ++t) s += Vc[rr * QS + t] * Y[t * QS + q];
-        X[(long long)(r0 + rr) * ldx + q] = Xc[rr * (QXC + 1) + q] - s;
-      }
-    }
-    __syncthreads();
-  }
+// 8-byte load and store through a raw buffer view: byte offset voff (per lane) + soff (wave-
+// uniform); a load at or past the view's size reads zero and a store there is dropped.
+__device__ inline double view_load(__amdgpu_buffer_rsrc_t v, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(v, (int)voff, (int)soff, 0));
+}
+__device__ inline void view_store(__amdgpu_buffer_rsrc_t v, double x, unsigned voff, unsigned soff) {
+  using U2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(v, 0, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, x), v, (int)voff, (int)soff, 0);
 }
 
-// X (n rows, ncol <= 32 columns, row-major, row stride ldx) <- Q2^T X (transpose) or Q2 X for
-// the bulge-chasing reflectors of the band-to-tridiagonal step: sweep s holds the reflectors
+// A pointer that is the same in every lane, moved to scalar registers.
+template <typename T>
+__device__ inline T *uniform_ptr(T *p) {
+  const unsigned long long u = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u), hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+  return reinterpret_cast<T *>(((unsigned long long)hi << 32) | lo);
+}
+
+// X (n rows, M <= kMaxOrb columns, row-major with row stride kMaxOrb) <- Q1 X on the FP64
+// matrix cores, panel by panel from the last:  Y = V^T X,  Y <- T Y,  X <- X - V Y.
+// X stays in registers for the whole product: 16-row chunk c belongs to wave c mod 4 and is
+// held in the result layout of v_mfma_f64_16x16x4 (register r of lane l: X(16 c + l/16 + 4 r,
+// l % 16)).  The K steps of every product are ordered so that each operand already sits in
+// the register the instruction takes: step r of V^T X runs over the chunk's rows l/16 + 4 r
+// (its B operand is register r of the chunk), the steps of T Y and of V Y over the reflectors
+// 16 h + l/16 + 4 r (B operand: register r of block h of Y).  Rows below 2 b + 32 p are not
+// touched by panel p, and rows 0 .. b - 1 by none.  The reflectors are read from A straight
+// into the A operands (buffer loads: a lane offset and a wave-uniform one), the next chunk's
+// while the current one is multiplied; entries that are not stored (above and on the unit
+// diagonal, past row n, past the last reflector) are formed only in the panel's first two
+// chunks, the chunk that holds row n - 1 and a short last panel.  The waves' partial Y meet in
+// LDS (two buffers, so one barrier per panel), and every wave forms T Y itself in the same
+// order.  Whole workgroup (4 waves); lds: kQ1Lds doubles; ends with a barrier.
+__device__ void wg_apply_q1(const double *__restrict__ A, int n, const double *__restrict__ Tq, double *X, int M,
+                            double *lds) {
+  static_assert(kBand == 32 && kMaxOrb == 16, "panels of two 16-wide blocks, X one 16-wide block");
+  // the arguments are wave-uniform (out of line they arrive in vector registers)
+  A = uniform_ptr(A);
+  Tq = uniform_ptr(Tq);
+  X = uniform_ptr(X);
+  n = __builtin_amdgcn_readfirstlane(n);
+  M = __builtin_amdgcn_readfirstlane(M);
+  const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nref = n - kBand;
+  if (nref <= 0) return;
+  const int nch = (n + 15) >> 4, npan = (nref + 31) >> 5;
+  const unsigned n8 = 8u * (unsigned)n;
+  const __amdgpu_buffer_rsrc_t av = __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(A), (short)0, (int)(n8 * n), 0x00020000);
+  const __amdgpu_buffer_rsrc_t xv = __builtin_amdgcn_make_buffer_rsrc(X, (short)0, (int)(n8 * kMaxOrb), 0x00020000);
+  // X rows past n read zero (view size), columns M.. are sent past the view
+  const unsigned xo = li < M ? 8u * (unsigned)(kMaxOrb * lg + li) : 0x80000000u;
+  ldc_double4 x[kQ1Slots];
+#pragma unroll
+  for (int j = 0; j < kQ1Slots; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) x[j][r] = view_load(xv, xo + 512u * r, 128u * 16u * (4 * j + wave));
+  // lane offsets of the two operand layouts: V(row0 + lg + 4 r, 16 h + li) and
+  // V(row0 + li, 16 h + lg + 4 r)
+  const unsigned o1 = 8u * (unsigned)(li * n + lg), o2 = 8u * (unsigned)(lg * n + li);
+  for (int p = npan - 1; p >= 0; --p) {
+    const int nbp = min(32, nref - 32 * p), cf = 2 * p + 2;
+    const unsigned vb0 = 32u * p * n8;  // column 32 p
+    // the wave's chunks of the panel, c = 4 j + wave in [cf, nch)
+    const int jlo = (cf - wave + 3) >> 2, jhi = (nch - 1 - wave) >> 2;
+    // entries of the operand blocks that are not stored: t is the row offset from the panel's
+    // first row (32 p + b) minus the reflector index
+    // (rl = rows of the chunk inside the matrix, made opaque so that the compares are formed
+    // here rather than hoisted out of the panel loop for every chunk)
+    auto mask1 = [&](double (&v)[8], int c) {
+      if (c < cf + 2 || 16 * c + 16 > n || nbp < 32) {
+        int rl = n - 16 * c;
+        asm volatile("" : "+s"(rl));
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int t = 16 * (c - cf - h) + 4 * r + lg - li;
+            const bool in = li + 16 * h < nbp;
+            v[4 * h + r] = (in && t > 0 && lg + 4 * r < rl) ? v[4 * h + r] : ((in && t == 0) ? 1.0 : 0.0);
+          }
+      }
+    };
+    auto mask2 = [&](double (&v)[8], int c) {
+      if (c < cf + 2 || 16 * c + 16 > n || nbp < 32) {
+        int rl = n - 16 * c;
+        asm volatile("" : "+s"(rl));
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int t = 16 * (c - cf - h) - 4 * r + li - lg;
+            const bool in = lg + 4 * r + 16 * h < nbp;
+            v[4 * h + r] = (in && t > 0 && li < rl) ? v[4 * h + r] : ((in && t == 0) ? 1.0 : 0.0);
+          }
+      }
+    };
+    auto load1 = [&](double (&v)[8], int c) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[4 * h + r] = view_load(av, o1 + 32u * r, vb0 + 16u * h * n8 + 128u * c);
+    };
+    auto load2 = [&](double (&v)[8], int c) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[4 * h + r] = view_load(av, o2, vb0 + (16u * h + 4u * r) * n8 + 128u * c);
+    };
+    // Y = V^T X, two 16-row blocks
+    ldc_double4 y0 = {0.0, 0.0, 0.0, 0.0}, y1 = {0.0, 0.0, 0.0, 0.0};
+    double va[8], vb[8] = {};
+    if (jlo <= jhi) load1(va, 4 * jlo + wave);
+#pragma unroll
+    for (int j = 0; j < kQ1Slots; ++j) {
+      if (j >= jlo && j <= jhi) {
+        const int c = 4 * j + wave;
+        if (j < jhi) load1(vb, c + 4);
+        mask1(va, c);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          y0 = __builtin_amdgcn_mfma_f64_16x16x4f64(va[r], x[j][r], y0, 0, 0, 0);
+          y1 = __builtin_amdgcn_mfma_f64_16x16x4f64(va[4 + r], x[j][r], y1, 0, 0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) va[u] = vb[u];
+      }
+    }
+    // T operands (T(16 g + li, 16 h + lg + 4 r); the block g = 1, h = 0 is zero)
+    const double *Tp = Tq + (long long)p * 1024;
+    double ta[8], tb[4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) ta[4 * h + r] = Tp[li * 32 + 16 * h + lg + 4 * r];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) tb[r] = Tp[(16 + li) * 32 + 16 + lg + 4 * r];
+    double *Yb = lds + (p & 1) * 2048;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      Yb[wave * 512 + r * 64 + lane] = y0[r];
+      Yb[wave * 512 + (4 + r) * 64 + lane] = y1[r];
+    }
+    __syncthreads();
+    // Y summed over the waves in a fixed order, then T Y: z0 = rows 0..15, z1 = rows 16..31
+    ldc_double4 z0 = {0.0, 0.0, 0.0, 0.0}, z1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double ys = ((Yb[u * 64 + lane] + Yb[512 + u * 64 + lane]) + Yb[1024 + u * 64 + lane]) + Yb[1536 + u * 64 + lane];
+      z0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ta[u], ys, z0, 0, 0, 0);
+      if (u >= 4) z1 = __builtin_amdgcn_mfma_f64_16x16x4f64(tb[u - 4], ys, z1, 0, 0, 0);
+    }
+    // X <- X - V (T Y)
+    if (jlo <= jhi) load2(va, 4 * jlo + wave);
+#pragma unroll
+    for (int j = 0; j < kQ1Slots; ++j) {
+      if (j >= jlo && j <= jhi) {
+        const int c = 4 * j + wave;
+        if (j < jhi) load2(vb, c + 4);
+        mask2(va, c);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(va[r], -z0[r], x[j], 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(va[4 + r], -z1[r], x[j], 0, 0, 0);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) va[u] = vb[u];
+      }
+    }
+  }
+  // rows past n and columns M.. are dropped by the view
+#pragma unroll
+  for (int j = 0; j < kQ1Slots; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) view_store(xv, x[j][r], xo + 512u * r, 128u * 16u * (4 * j + wave));
+  __syncthreads();
+}
+
+// Q2, band to tridiagonal by bulge chasing.  X (n rows, ncol <= 32 columns, row-major, row stride
+// ldx) <- Q2^T X (transpose) or Q2 X for the bulge-chasing reflectors of the band-to-tridiagonal step: sweep s holds the reflectors
 // of rows [s + 1 + j b, s + 1 + j b + len), len = min(b, n - r0), b = kBand, stored in
 // column n - 1 - s of A above the diagonal at rows j b.. (tau first, then v(1:len)); the
 // steps of one sweep act on disjoint rows, so each sweep is one parallel step (16 or 32 lanes
