@@ -15,6 +15,7 @@
 // which feed the z vectors), and stores per merge what a later product Z y needs: the sort
 // permutation, the rotations, the secular-equation data and the output order.
 #include "dc_common.h"
+#include "wg_blas.h"
 
 #include <type_traits>
 
@@ -23,72 +24,117 @@ namespace ldc {
 constexpr double kEps = 2.220446049250313e-16;
 
 // Root t (0-based) of 1/rho + sum_j z_j^2/(d_j - lambda) = 0 for ascending poles d (k of
-// them).  Returns the origin pole o and tau with lambda = d_o + tau.
-__device__ void secular_root(const double *__restrict__ d, const double *__restrict__ z, int k, double rho, int t,
-                             int *o_out, double *tau_out) {
-  const double rinv = 1.0 / rho;
-  int o;
-  double a, b;
-  if (t < k - 1) {
-    const double delta = d[t + 1] - d[t];
-    const double dt = d[t];
-    double g = rinv;
-    for (int j = 0; j < k; ++j) g += z[j] * z[j] * rcp_nr((d[j] - dt) - 0.5 * delta);
-    if (g >= 0.0) {
+// them), given the squares z2 of the z entries, as lambda = d_o + tau with o the nearer pole.
+// An interior root starts from the midpoint of its two poles, whose sums also decide the
+// nearer pole; the last root from the middle of (d_k, d_k + rho |z|^2].  Each pass evaluates
+// the sums once and takes one safeguarded rational ("middle way") step; the root is done when
+// the equation holds to its rounding error, the bracket has closed, or the step has become a
+// rounding-level change of tau.  The passes of one root are a fixed sequence, whichever lane
+// runs them and whatever it ran before.
+struct SecularRoot {
+  const double *d, *z2;
+  int k, t, o, it;
+  bool start;  // the next pass is the one at the midpoint (d0 = d_t)
+  double rinv, rho, a, b, tau, d0;
+
+  __device__ void begin(const double *dk, const double *z2k, int kk, double rh, int tt) {
+    d = dk;
+    z2 = z2k;
+    k = kk;
+    t = tt;
+    rho = rh;
+    rinv = 1.0 / rh;
+    it = 0;
+    if (t < k - 1) {
+      start = true;
       o = t;
-      a = 0.0;
-      b = 0.5 * delta;
+      d0 = d[t];
+      tau = 0.5 * (d[t + 1] - d[t]);
+      a = b = 0.0;
     } else {
-      o = t + 1;
-      a = -0.5 * delta;
-      b = 0.0;
+      start = false;
+      o = t;
+      d0 = d[t];
+      double zz = 0.0;
+      for (int j = 0; j < k; ++j) zz += z2[j];
+      a = 0.0;
+      b = rho * zz * (1.0 + 8.0 * kEps);  // the last root lies in (d_k, d_k + rho |z|^2]
+      tau = 0.5 * (a + b);
     }
-  } else {
-    o = t;
-    double zz = 0.0;
-    for (int j = 0; j < k; ++j) zz += z[j] * z[j];
-    a = 0.0;
-    b = rho * zz * (1.0 + 8.0 * kEps);  // the last root lies in (d_k, d_k + rho |z|^2]
   }
-  const double dorig = d[o];
-  double tau = 0.5 * (a + b);
-  // sum of z_j^2 / (d_j - lambda) and of its derivative over [j0, j1), four independent
-  // partial sums (the terms' latency chains overlap)
-  auto sums = [&](int j0, int j1, double &sv, double &dv) {
-    double s4[4] = {0.0, 0.0, 0.0, 0.0}, d4[4] = {0.0, 0.0, 0.0, 0.0};
-    int j = j0;
-    for (; j + 4 <= j1; j += 4) {
+
+  // psi = sum_{j <= t} z_j^2 / (d_j - lambda), phi = sum_{j > t} (the same), and their
+  // derivatives, d_j - lambda = (d_j - d0) - tau, in one loop over all j: with lambda strictly
+  // between d_t and d_t+1 (the last root: above d_k) the terms of j <= t are exactly the
+  // negative ones, so every lane of a merge runs the same j whatever its root.  Two partial
+  // sums each; four terms formed stage by stage (their chains in flight together; the
+  // reciprocal and its two Newton steps as in rcp_nr).
+  __device__ void sums(double &psi, double &dpsi, double &phi, double &dphi) const {
+    double sn[2] = {0.0, 0.0}, sp[2] = {0.0, 0.0}, dn[2] = {0.0, 0.0}, dpv[2] = {0.0, 0.0};
+    auto add = [&](int h, double term, double r) {
+      const double tn = fmin(term, 0.0), tp = fmax(term, 0.0);
+      sn[h] += tn;
+      sp[h] += tp;
+      dn[h] = fma(tn, r, dn[h]);
+      dpv[h] = fma(tp, r, dpv[h]);
+    };
+    int j = 0;
+    for (; j + 4 <= k; j += 4) {
+      double x[4], r[4], e[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const double r = rcp_nr((d[j + u] - dorig) - tau);
-        const double term = z[j + u] * z[j + u] * r;
-        s4[u] += term;
-        d4[u] += term * r;
-      }
+      for (int u = 0; u < 4; ++u) x[u] = (d[j + u] - d0) - tau;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) r[u] = __builtin_amdgcn_rcp(x[u]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) e[u] = fma(-x[u], r[u], 1.0);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) r[u] = fma(r[u], e[u], r[u]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) e[u] = fma(-x[u], r[u], 1.0);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) r[u] = fma(r[u], e[u], r[u]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) add(u & 1, z2[j + u] * r[u], r[u]);
     }
-    for (; j < j1; ++j) {
-      const double r = rcp_nr((d[j] - dorig) - tau);
-      const double term = z[j] * z[j] * r;
-      s4[0] += term;
-      d4[0] += term * r;
+    for (; j < k; ++j) {
+      const double r = rcp_nr((d[j] - d0) - tau);
+      add(0, z2[j] * r, r);
     }
-    sv = (s4[0] + s4[1]) + (s4[2] + s4[3]);
-    dv = (d4[0] + d4[1]) + (d4[2] + d4[3]);
-  };
-  for (int it = 0; it < 100; ++it) {
+    psi = sn[0] + sn[1];
+    phi = sp[0] + sp[1];
+    dpsi = dn[0] + dn[1];
+    dphi = dpv[0] + dpv[1];
+  }
+
+  // one pass; true when the root is done (o and tau final)
+  __device__ bool pass() {
     double psi, dpsi, phi, dphi;
-    sums(0, t + 1, psi, dpsi);
-    sums(t + 1, k, phi, dphi);
+    sums(psi, dpsi, phi, dphi);
+    if (start) {  // at the midpoint: the sign decides the nearer pole and the bracket
+      start = false;
+      const double half = tau;
+      if (rinv + psi + phi >= 0.0) {  // the root lies in (d_t, midpoint]
+        o = t;
+        a = 0.0;
+        b = half;
+      } else {
+        o = t + 1;
+        a = -half;
+        b = 0.0;
+        tau = a;
+      }
+      d0 = d[o];
+    }
     const double g = rinv + psi + phi;
     const double err = 8.0 * (fabs(psi) + fabs(phi) + rinv) + fabs(tau) * (dpsi + dphi);
     if (g < 0.0) a = tau;
     else b = tau;
-    if (fabs(g) <= kEps * err || (b - a) <= 2.0 * kEps * fmax(fabs(a), fabs(b))) break;
-    const double dl = (d[t] - dorig) - tau;
-    double eta;
+    if (fabs(g) <= kEps * err || (b - a) <= 2.0 * kEps * fmax(fabs(a), fabs(b))) return true;
+    const double dl = (d[t] - d0) - tau;
+    double eta = 0.0;
     bool ok = true;
     if (t < k - 1) {
-      const double dr = (d[t + 1] - dorig) - tau;
+      const double dr = (d[t + 1] - d0) - tau;
       const double cc = g - dl * dpsi - dr * dphi;
       const double aa = (dl + dr) * g - dl * dr * (dpsi + dphi);
       const double bb = dl * dr * g;
@@ -108,11 +154,11 @@ __device__ void secular_root(const double *__restrict__ d, const double *__restr
     }
     double tn = ok ? tau + eta : 0.5 * (a + b);
     if (!(tn > a && tn < b)) tn = 0.5 * (a + b);
+    const bool done = fabs(tn - tau) <= 2.0 * kEps * fabs(tn);
     tau = tn;
+    return done || ++it >= 100;
   }
-  *o_out = o;
-  *tau_out = tau;
-}
+};
 
 // Total order on doubles (IEEE order for numbers; NaNs at the ends): sorting and ranking by
 // this key gives a permutation whatever the data.
@@ -153,6 +199,7 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
                            DcLds S, DevStatus *st, int cid) {
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int Fc = nx, Lc = nx + 1, nt = nx + 2;
+  __shared__ int qnext;  // the secular roots' work queue
   double *lam = ws.lam, *G0 = ws.G0, *G1 = ws.G1;
   for (int i = tid; i < n; i += nthr) {
     double di = dd[i];
@@ -238,9 +285,15 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
       }
       rho *= zn2;
       const double tol = 8.0 * kEps * fmax(dmaxabs, zmax);
+      // the pending entry pj (the last one not deflated) is kept in registers with its z and
+      // pole, so the chain from one j to the next is only the pair test; the test
+      // |(d_j - d_pj) c s| <= tol of the rotation (c, s) = (z_j, -z_pj) / r, r^2 = z_pj^2 + z_j^2,
+      // is taken as |(d_j - d_pj) z_j z_pj| <= tol r^2, and the rotation is formed only when
+      // the pair deflates
       int kp = 0, nd = 0, nrot = 0, pj = -1;
+      double zp = 0.0, dp = 0.0;
       for (int j = 0; j < k; ++j) {
-        const double zj = zs[j];
+        const double zj = zs[j], dj = Ds[j];
         if (rho * fabs(zj) <= tol) {
           R.kpos[hi - 1 - nd] = j;
           S.kpos[hi - 1 - nd] = j;
@@ -249,14 +302,14 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
         }
         if (pj < 0) {
           pj = j;
+          zp = zj;
+          dp = dj;
           continue;
         }
-        double s_ = zs[pj], c_ = zj;
-        const double tau = hypot(c_, s_);
-        const double tdiff = Ds[j] - Ds[pj];
-        c_ /= tau;
-        s_ = -s_ / tau;
-        if (fabs(tdiff * c_ * s_) <= tol) {
+        const double tdiff = dj - dp;
+        if (fabs(tdiff * zj * zp) <= tol * (zp * zp + zj * zj)) {
+          const double tau = hypot(zj, zp);
+          const double c_ = zj / tau, s_ = -zp / tau;
           zs[j] = tau;
           zs[pj] = 0.0;
           R.ra[lo + nrot] = pj;
@@ -264,17 +317,21 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
           R.rc[lo + nrot] = c_;
           R.rs[lo + nrot] = s_;
           ++nrot;
-          const double dp = Ds[pj], dj = Ds[j];
           const double t1 = dp * c_ * c_ + dj * s_ * s_;
-          Ds[j] = dp * s_ * s_ + dj * c_ * c_;
+          const double dn = dp * s_ * s_ + dj * c_ * c_;
+          Ds[j] = dn;
           Ds[pj] = t1;
           R.kpos[hi - 1 - nd] = pj;
           S.kpos[hi - 1 - nd] = pj;
           ++nd;
+          zp = tau;
+          dp = dn;
         } else {
           R.kpos[lo + kp] = pj;
           S.kpos[lo + kp] = pj;
           ++kp;
+          zp = zj;
+          dp = dj;
         }
         pj = j;
       }
@@ -286,22 +343,49 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
       R.cnt[lo] = kp;
       R.cnt[lo + 1] = nrot;
       ws.rhov[lo] = rho;
+      // kept poles and z in order; S.zt[lo + t] takes z^2 for the secular solver (position
+      // kpos[t] >= t, so no entry of zs is overwritten before it is read)
       for (int t = 0; t < kp; ++t) {
         const int pos = S.kpos[lo + t];
         const double dv = Ds[pos], zv = zs[pos];
         R.dK[lo + t] = dv;
         S.d[lo + t] = dv;
         S.z[lo + t] = zv;
+        S.zt[lo + t] = zv * zv;
       }
       for (int t = 0; t < k; ++t) S.jinv[lo + S.kpos[lo + t]] = t;
     }
     __syncthreads();
-    // Phase A3: G1 = rows of G0 in sorted order
-    for (long long e = tid; e < (long long)n * nt; e += nthr) {
-      const int q = (int)(e / nt), cc = (int)(e % nt);
-      const int lo = q - q % span;
-      if (R.cnt[lo] < 0) continue;
-      G1[(long long)q * kTrack + cc] = G0[(long long)(lo + R.perm[q]) * kTrack + cc];
+    // Phase A3: G1 = rows of G0 in sorted order; 32 lanes per row (lane c: columns c and
+    // c + 32), eight rows per thread in flight
+    {
+      const int cq = tid & 31, rstep = nthr >> 5;
+      for (int q0 = tid >> 5; q0 < n; q0 += 8 * rstep) {
+        int src[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int q = q0 + u * rstep;
+          src[u] = -1;
+          if (q < n) {
+            const int lo = q & ~(span - 1);
+            if (R.cnt[lo] >= 0) src[u] = lo + R.perm[q];
+          }
+        }
+        double v0[8], v1[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const double *g = G0 + (long long)max(src[u], 0) * kTrack;
+          v0[u] = g[cq];
+          v1[u] = cq + 32 < kTrack ? g[min(cq + 32, kTrack - 1)] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (src[u] < 0) continue;
+          double *o = G1 + (long long)(q0 + u * rstep) * kTrack;
+          if (cq < nt) o[cq] = v0[u];
+          if (cq + 32 < nt) o[cq + 32] = v1[u];
+        }
+      }
     }
     __syncthreads();
     // Phase A4: deflation rotations, one thread per (merge, column)
@@ -321,19 +405,39 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
       }
     }
     __syncthreads();
-    // Phase B: secular roots
-    for (int q = tid; q < n; q += nthr) {
-      const int lo = q - q % span;
-      const int kp = R.cnt[lo];
-      const int t = q - lo;
-      if (kp < 0 || t >= kp) continue;
-      int o;
-      double tau;
-      secular_root(S.d + lo, S.z + lo, kp, ws.rhov[lo], t, &o, &tau);
-      R.orig[lo + t] = o;
-      R.tau[lo + t] = tau;
-      S.orig[lo + t] = o;
-      S.tau[lo + t] = tau;
+    // Phase B: secular roots.  Every lane works through the roots of the level from a shared
+    // queue: a lane whose root is done stores it and takes the next one at once, so the few
+    // slow roots of a wave do not hold its other lanes idle.
+    {
+      if (tid == 0) qnext = nthr;
+      __syncthreads();
+      auto is_root = [&](int q) {
+        const int lo = q & ~(span - 1), kp = R.cnt[lo];
+        return kp >= 0 && q - lo < kp;
+      };
+      auto next_root = [&](int q) {
+        while (q < n && !is_root(q)) q = atomicAdd(&qnext, 1);
+        return q;
+      };
+      SecularRoot sr;
+      int q = next_root(tid);
+      if (q < n) {
+        const int lo = q & ~(span - 1);
+        sr.begin(S.d + lo, S.zt + lo, R.cnt[lo], ws.rhov[lo], q - lo);
+      }
+      while (__any(q < n)) {
+        if (q < n && sr.pass()) {
+          R.orig[q] = sr.o;
+          R.tau[q] = sr.tau;
+          S.orig[q] = sr.o;
+          S.tau[q] = sr.tau;
+          q = next_root(atomicAdd(&qnext, 1));
+          if (q < n) {
+            const int lo2 = q & ~(span - 1);
+            sr.begin(S.d + lo2, S.zt + lo2, R.cnt[lo2], ws.rhov[lo2], q - lo2);
+          }
+        }
+      }
     }
     __syncthreads();
     // Phase C: Loewner z
@@ -347,12 +451,36 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
       const double *tu = S.tau + lo;
       const double dj = dK[j];
       const double rho = ws.rhov[lo];
-      double prod = -((dj - dK[org[j]]) - tu[j]) / rho;
-      for (int i = 0; i < kp; ++i) {
+      // four partial products over i = u mod 4, the factors of four i formed stage by stage
+      // (their chains in flight together); the factor of i = j is one
+      double p4[4] = {1.0, 1.0, 1.0, 1.0};
+      int i = 0;
+      for (; i + 4 <= kp; i += 4) {
+        double num[4], x[4], r[4], e[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          num[u] = (dj - dK[org[i + u]]) - tu[i + u];
+          x[u] = dj - dK[i + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) r[u] = __builtin_amdgcn_rcp(x[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) e[u] = fma(-x[u], r[u], 1.0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) r[u] = fma(r[u], e[u], r[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) e[u] = fma(-x[u], r[u], 1.0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) r[u] = fma(r[u], e[u], r[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) p4[u] *= (i + u == j) ? 1.0 : num[u] * r[u];
+      }
+      for (; i < kp; ++i) {
         if (i == j) continue;
         const double num = (dj - dK[org[i]]) - tu[i];
-        prod *= num * rcp_nr(dj - dK[i]);
+        p4[0] *= num * rcp_nr(dj - dK[i]);
       }
+      const double prod = (-((dj - dK[org[j]]) - tu[j]) / rho) * ((p4[0] * p4[1]) * (p4[2] * p4[3]));
       const double ztj = copysign(sqrt(fmax(prod, 0.0)), S.z[lo + j]);
       R.zt[lo + j] = ztj;
       S.zt[lo + j] = ztj;
@@ -366,12 +494,34 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
       if (kp < 0 || t >= kp) continue;
       const double *dK = S.d + lo, *zt = S.zt + lo;
       const double dorig = dK[S.orig[lo + t]], tau = S.tau[lo + t];
-      double s2 = 0.0;
-      for (int j = 0; j < kp; ++j) {
-        const double u = zt[j] * rcp_nr((dK[j] - dorig) - tau);
-        s2 += u * u;
+      // four partial sums, the terms of four j formed stage by stage
+      double s4[4] = {0.0, 0.0, 0.0, 0.0};
+      int j = 0;
+      for (; j + 4 <= kp; j += 4) {
+        double x[4], r[4], e[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = (dK[j + u] - dorig) - tau;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) r[u] = __builtin_amdgcn_rcp(x[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) e[u] = fma(-x[u], r[u], 1.0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) r[u] = fma(r[u], e[u], r[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) e[u] = fma(-x[u], r[u], 1.0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) r[u] = fma(r[u], e[u], r[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double v = zt[j + u] * r[u];
+          s4[u] += v * v;
+        }
       }
-      const double nv = sqrt(s2);
+      for (; j < kp; ++j) {
+        const double v = zt[j] * rcp_nr((dK[j] - dorig) - tau);
+        s4[0] += v * v;
+      }
+      const double nv = sqrt((s4[0] + s4[1]) + (s4[2] + s4[3]));
       R.nrm[lo + t] = nv;
       S.nrm[lo + t] = nv;
     }
@@ -491,8 +641,129 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
         }
       }
     };
-    if (nt <= 20) transform(std::integral_constant<int, 20>{});
-    else transform(std::integral_constant<int, kTrack>{});
+    // Merges of 64 rows or more on the FP64 matrix cores.  Each wave takes 64 output rows of one
+    // merge as four 16-row tiles t; step s covers the staged rows pp = lo + 4 s + l/16: lane l
+    // forms the weight u(q, pp) of row q = q0 + 16 t + l % 16 of every tile (the A operands)
+    // and reads the 16-column blocks of G1 row pp (B operands, lane l: column 16 c + l % 16)
+    // straight from memory, so the waves need no barrier.  Register r of the tile's result then
+    // holds row q0 + 16 t + l/16 + 4 r.  The NL columns past the last full block are summed on
+    // the vector units per lane and added over the four lane groups at the end.  Rows that are
+    // not kept take zero weights (pole 0, shift -1e300, scale 0: every weight is an exact zero)
+    // and are copies of their own G1 row.
+    auto transform_mfma = [&](auto ntl_c, auto nl_c) {
+      constexpr int NTL = decltype(ntl_c)::value, NL = decltype(nl_c)::value;
+      const int lane = tid & 63, li = lane & 15, lg = lane >> 4;
+      const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+      for (int q0 = 64 * wave; q0 < n; q0 += nthr) {
+        const int lo = q0 - q0 % span, hi = min(lo + span, n);
+        const int kp = R.cnt[lo];
+        if (kp < 0) continue;
+        double dor[4], tu[4], ni[4];
+        unsigned long long keptm[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int q = q0 + 16 * t + li;
+          const int e = q < n ? R.oo[q] : kp;
+          const bool kq = e < kp;
+          dor[t] = kq ? S.d[lo + S.orig[lo + e]] : 0.0;
+          tu[t] = kq ? S.tau[lo + e] : -1e300;
+          ni[t] = kq ? 1.0 / S.nrm[lo + e] : 0.0;
+          keptm[t] = __ballot(kq);
+        }
+        ldc_double4 acc[4][NTL];
+        double pl[4][NL];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+#pragma unroll
+          for (int c = 0; c < NTL; ++c) acc[t][c] = ldc_double4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int c = 0; c < NL; ++c) pl[t][c] = 0.0;
+        }
+        // one step: the data of staged row pp (fetched two steps ahead), then its weights and
+        // products; rows past the merge (the tail step only) take zero weights
+        struct Row {
+          double D, z, gb[NTL], gl[NL];
+        };
+        auto fetch = [&](Row &b, int pp) {
+          const int pr = min(pp, hi - 1);
+          b.D = S.Ds[pr];
+          b.z = S.z[pr];
+          const double *g = G1 + (long long)pr * kTrack;
+#pragma unroll
+          for (int c = 0; c < NTL; ++c) b.gb[c] = g[16 * c + li];
+#pragma unroll
+          for (int c = 0; c < NL; ++c) b.gl[c] = g[16 * NTL + c];
+        };
+        auto step = [&](const Row &b, bool in) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const double w0 = b.z * rcp_nr((b.D - dor[t]) - tu[t]) * ni[t];
+            const double w = in ? w0 : 0.0;
+#pragma unroll
+            for (int c = 0; c < NTL; ++c) acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(w, b.gb[c], acc[t][c], 0, 0, 0);
+#pragma unroll
+            for (int c = 0; c < NL; ++c) pl[t][c] += w * b.gl[c];
+          }
+        };
+        const int pend = lo + ((hi - lo) & ~3);
+        Row b0, b1;
+        fetch(b0, lo + lg);
+        fetch(b1, lo + 4 + lg);
+        for (int p0 = lo; p0 < pend; p0 += 4) {
+          const Row cur = b0;
+          b0 = b1;
+          fetch(b1, p0 + 8 + lg);
+          step(cur, true);
+        }
+        if (pend < hi) step(b0, pend + lg < hi);
+        // results: kept rows of the blocks, then the remaining columns (lane l: row q0 + l,
+        // tile l/16), then the copies
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int q = q0 + 16 * t + lg + 4 * r;
+            if (q < n && ((keptm[t] >> (lg + 4 * r)) & 1ull)) {
+#pragma unroll
+              for (int c = 0; c < NTL; ++c)
+                if (16 * c + li < nt) G0[(long long)q * kTrack + 16 * c + li] = acc[t][c][r];
+            }
+          }
+        double own[NL];
+#pragma unroll
+        for (int c = 0; c < NL; ++c) own[c] = 0.0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int c = 0; c < NL; ++c) {
+            double v = pl[t][c];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            if (lg == t) own[c] = v;
+          }
+        const int q = q0 + lane;
+        if (q < n) {
+          const int e = R.oo[q];
+          if (e < kp) {
+#pragma unroll
+            for (int c = 0; c < NL; ++c)
+              if (16 * NTL + c < nt) G0[(long long)q * kTrack + 16 * NTL + c] = own[c];
+          } else {
+            const double *g = G1 + (long long)(lo + S.kpos[lo + e]) * kTrack;
+            for (int cc = 0; cc < nt; ++cc) G0[(long long)q * kTrack + cc] = g[cc];
+          }
+        }
+      }
+    };
+    if (span >= 64) {
+      __syncthreads();  // the staged poles and weights are complete
+      if (nt <= 20) transform_mfma(std::integral_constant<int, 1>{}, std::integral_constant<int, 4>{});
+      else transform_mfma(std::integral_constant<int, 2>{}, std::integral_constant<int, kTrack - 32>{});
+    } else if (nt <= 20) {
+      transform(std::integral_constant<int, 20>{});
+    } else {
+      transform(std::integral_constant<int, kTrack>{});
+    }
     __syncthreads();
   }
 }
