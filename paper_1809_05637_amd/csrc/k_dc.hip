@@ -170,11 +170,9 @@ __device__ inline long long dc_key(double x) {
 // LDS copies of the current level's merge data (n entries each), read many times by the
 // secular solver, the Loewner formula, the norms, the output ranking and the row transform.
 struct DcLds {
-  double *d, *z, *zt, *tau, *nrm, *Ds, *g;
+  double *d, *z, *zt, *tau, *nrm, *Ds;
   int *orig, *kpos, *jinv;
   static constexpr int kBytesPerRow = 6 * sizeof(double) + 3 * sizeof(int);
-  static constexpr int kChunk = 32;  // rows of G1 staged per step of the row transform
-  static constexpr int kFixedBytes = kChunk * kTrack * sizeof(double);
 };
 
 __device__ inline DcLds dc_lds(void *base, int nmax) {
@@ -186,8 +184,7 @@ __device__ inline DcLds dc_lds(void *base, int nmax) {
   L.tau = b + 3 * nmax;
   L.nrm = b + 4 * nmax;
   L.Ds = b + 5 * nmax;
-  L.g = b + 6 * nmax;  // kChunk x kTrack
-  L.orig = reinterpret_cast<int *>(b + 6 * nmax + DcLds::kChunk * kTrack);
+  L.orig = reinterpret_cast<int *>(b + 6 * nmax);
   L.kpos = L.orig + nmax;
   L.jinv = L.kpos + nmax;
   return L;
@@ -556,11 +553,10 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
     __syncthreads();
     // Phase E: transformed rows, written in output order.  Output row q (merge [lo, lo+k),
     // element e = oo[q]) is sum_j u(e, j) G1(lo + kpos[j]) over the kept j (e < kp), or its own
-    // row G1(lo + kpos[e]) (deflated e).  One output row per thread and pass; G1 is staged
-    // through LDS kChunk rows at a time.  A staged row p carries its pole and Loewner z in
-    // S.Ds[p] and S.z[p] (the merge data of row p's j = jinv[p]; a deflated row has z = 0 and a
-    // far pole, so its weight is exactly zero), so the threads of one merge read the same LDS
-    // entries in step (broadcast) and, when merges span whole chunks, run a fixed 32-row loop.
+    // row G1(lo + kpos[e]) (deflated e).  Row p of G1 carries its pole and Loewner z in S.Ds[p]
+    // and S.z[p] (the merge data of row p's j = jinv[p]; a deflated row has z = 0 and a far
+    // pole, so its weight is exactly zero), so every output row of a merge sums over all the
+    // merge's rows p in order.
     for (int pp = tid; pp < n; pp += nthr) {
       const int lo = pp - pp % span;
       const int kp = R.cnt[lo];
@@ -570,75 +566,38 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
       S.Ds[pp] = kj ? S.d[lo + j] : 1e300;
       S.z[pp] = kj ? S.zt[lo + j] : 0.0;
     }
-    // the columns are summed unguarded up to a compile-time count NT >= nt (entries past nt are
-    // never stored): a guard per column would serialize the LDS reads
-    auto transform = [&](auto ntc) {
+    // Merges of fewer than 64 rows: one output row per thread, the rows of its merge read
+    // straight from memory (the threads of a merge load the same row together) and summed in
+    // order; the columns are summed unguarded up to a compile-time count NT >= nt (entries past
+    // nt are never stored).
+    auto transform_small = [&](auto ntc) {
       constexpr int NT = decltype(ntc)::value;
-      for (int qb = 0; qb < n; qb += nthr) {
-        constexpr int CH = DcLds::kChunk;
-        const int q = qb + tid;
-        int lo = 0, hi = 0, kp = -1, e = 0;
-        double dorig = 0.0, tau = 0.0, ninv = 0.0;
-        if (q < n) {
-          lo = q - q % span;
-          hi = min(lo + span, n);
-          kp = R.cnt[lo];
-          if (kp >= 0) {
-            e = R.oo[q];
-            if (e < kp) {
-              dorig = S.d[lo + S.orig[lo + e]];
-              tau = S.tau[lo + e];
-              ninv = 1.0 / S.nrm[lo + e];
-            }
-          }
+      for (int q = tid; q < n; q += nthr) {
+        const int lo = q & ~(span - 1);
+        const int kp = R.cnt[lo];
+        if (kp < 0) continue;
+        const int hi = min(lo + span, n);
+        const int e = R.oo[q];
+        double *out = G0 + (long long)q * kTrack;
+        if (e >= kp) {
+          const double *g = G1 + (long long)(lo + S.kpos[lo + e]) * kTrack;
+          for (int cc = 0; cc < nt; ++cc) out[cc] = g[cc];
+          continue;
         }
-        const bool kept = q < n && kp >= 0 && e < kp;
+        const double dorig = S.d[lo + S.orig[lo + e]], tau = S.tau[lo + e], ninv = 1.0 / S.nrm[lo + e];
         double acc[NT];
 #pragma unroll
         for (int cc = 0; cc < NT; ++cc) acc[cc] = 0.0;
-        // the rows any thread of this pass needs: [first merge start, last merge end)
-        const int rlo = qb - qb % span, rhi = min(n, ((min(qb + nthr, n) - 1) / span + 1) * span);
-        for (int c0 = rlo; c0 < rhi; c0 += CH) {
-          __syncthreads();
-          for (int t = tid; t < CH * nt; t += nthr) {
-            const int r = t / nt, cc = t % nt;
-            S.g[r * kTrack + cc] = (c0 + r < n) ? G1[(long long)(c0 + r) * kTrack + cc] : 0.0;
-          }
-          __syncthreads();
-          if (!kept || c0 + CH <= lo || c0 >= hi) continue;
-          if (span >= CH) {
-            // the chunk lies inside this merge (merges start at multiples of span >= CH); rows
-            // past the end of the matrix are masked
-#pragma unroll 4
-            for (int r = 0; r < CH; ++r) {
-              const int pp = min(c0 + r, n - 1);
-              const double w0 = S.z[pp] * rcp_nr((S.Ds[pp] - dorig) - tau) * ninv;
-              const double w = (c0 + r < hi) ? w0 : 0.0;
-              const double *g = S.g + r * kTrack;
+#pragma unroll 2
+        for (int pp = lo; pp < hi; ++pp) {
+          const double w = S.z[pp] * rcp_nr((S.Ds[pp] - dorig) - tau) * ninv;
+          const double *g = G1 + (long long)pp * kTrack;
 #pragma unroll
-              for (int cc = 0; cc < NT; ++cc) acc[cc] += w * g[cc];
-            }
-          } else {
-            const int pa = max(c0, lo), pb = min(c0 + CH, hi);
-            for (int pp = pa; pp < pb; ++pp) {
-              const double w = S.z[pp] * rcp_nr((S.Ds[pp] - dorig) - tau) * ninv;
-              const double *g = S.g + (pp - c0) * kTrack;
-#pragma unroll
-              for (int cc = 0; cc < NT; ++cc) acc[cc] += w * g[cc];
-            }
-          }
+          for (int cc = 0; cc < NT; ++cc) acc[cc] += w * g[cc];
         }
-        if (q < n && kp >= 0) {
-          if (!kept) {
-            const double *g = G1 + (long long)(lo + S.kpos[lo + e]) * kTrack;
 #pragma unroll
-            for (int cc = 0; cc < NT; ++cc)
-              if (cc < nt) acc[cc] = g[cc];
-          }
-#pragma unroll
-          for (int cc = 0; cc < NT; ++cc)
-            if (cc < nt) G0[(long long)q * kTrack + cc] = acc[cc];
-        }
+        for (int cc = 0; cc < NT; ++cc)
+          if (cc < nt) out[cc] = acc[cc];
       }
     };
     // Merges of 64 rows or more on the FP64 matrix cores.  Each wave takes 64 output rows of one
@@ -760,9 +719,9 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
       if (nt <= 20) transform_mfma(std::integral_constant<int, 1>{}, std::integral_constant<int, 4>{});
       else transform_mfma(std::integral_constant<int, 2>{}, std::integral_constant<int, kTrack - 32>{});
     } else if (nt <= 20) {
-      transform(std::integral_constant<int, 20>{});
+      transform_small(std::integral_constant<int, 20>{});
     } else {
-      transform(std::integral_constant<int, kTrack>{});
+      transform_small(std::integral_constant<int, kTrack>{});
     }
     __syncthreads();
   }
@@ -798,12 +757,12 @@ __global__ void __launch_bounds__(256, 3) stedc_kernel(int n_clusters, const int
 
 void launch_stedc(Plan &p) {
   const int dm = cur_dim(p);
-  const size_t lds = (size_t)dm * DcLds::kBytesPerRow + DcLds::kFixedBytes;
-  // above 64 KB (clusters of more than about 940 rows) the dynamic LDS limit must be raised
+  const size_t lds = (size_t)dm * DcLds::kBytesPerRow;
+  // above 64 KB the dynamic LDS limit must be raised (not reached below 1092 rows)
   if (lds > 64 * 1024)
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(stedc_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
-  // default three workgroups per CU (at most 168 VGPRs; the LDS of a 711-row cluster is 51 KB):
+  // default three workgroups per CU (at most 168 VGPRs; the LDS of a 711-row cluster is 42 KB):
   // more waves in flight for the latency-bound merges
   const int n = cur_count(p);
   const int grid = std::max(1, std::min(stage_grid(p, kTStedc, 3 * p.n_cu), n));
