@@ -259,29 +259,13 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
       S.zt[lo + pos] = S.nrm[q];
     }
     __syncthreads();
-    // Phase A2: one thread per merge -- normalise z, deflate (sequential chain on LDS data)
-    for (int mi = tid; mi < nmerge; mi += nthr) {
-      const int lo = mi * span, m = lo + size, hi = min(lo + span, n);
-      if (m >= hi) {
-        R.cnt[lo] = -1;
-        continue;
-      }
+    // Phase A2: normalise z and deflate.  The deflation is a sequential chain over the merge's
+    // sorted entries (one lane); around it, a merge of 64 rows or more takes a whole wave for
+    // the sums, the scaling and the kept copies, a smaller one a single thread.
+    // deflate: the chain of merge [lo, hi) (Ds, zs: its sorted poles and normalised z, in
+    // LDS); returns the kept count and the rotation count
+    auto deflate = [&](int lo, int hi, double *Ds, double *zs, double rho, double tol, int &kp_out, int &nrot_out) {
       const int k = hi - lo;
-      double rho = fabs(ee[m - 1]);
-      double *Ds = S.Ds + lo, *zs = S.zt + lo;
-      double zn2 = 0.0, dmaxabs = 0.0;
-      for (int p = 0; p < k; ++p) {
-        zn2 += zs[p] * zs[p];
-        dmaxabs = fmax(dmaxabs, fabs(Ds[p]));
-      }
-      const double zinv = 1.0 / sqrt(zn2);
-      double zmax = 0.0;
-      for (int p = 0; p < k; ++p) {
-        zs[p] *= zinv;
-        zmax = fmax(zmax, fabs(zs[p]));
-      }
-      rho *= zn2;
-      const double tol = 8.0 * kEps * fmax(dmaxabs, zmax);
       // the pending entry pj (the last one not deflated) is kept in registers with its z and
       // pole, so the chain from one j to the next is only the pair test; the test
       // |(d_j - d_pj) c s| <= tol of the rotation (c, s) = (z_j, -z_pj) / r, r^2 = z_pj^2 + z_j^2,
@@ -337,20 +321,101 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
         S.kpos[lo + kp] = pj;
         ++kp;
       }
-      R.cnt[lo] = kp;
-      R.cnt[lo + 1] = nrot;
-      ws.rhov[lo] = rho;
-      // kept poles and z in order; S.zt[lo + t] takes z^2 for the secular solver (position
-      // kpos[t] >= t, so no entry of zs is overwritten before it is read)
-      for (int t = 0; t < kp; ++t) {
-        const int pos = S.kpos[lo + t];
-        const double dv = Ds[pos], zv = zs[pos];
-        R.dK[lo + t] = dv;
-        S.d[lo + t] = dv;
-        S.z[lo + t] = zv;
-        S.zt[lo + t] = zv * zv;
+      kp_out = kp;
+      nrot_out = nrot;
+    };
+    if (span >= 64) {
+      const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+      for (int mi = wave; mi < nmerge; mi += nthr >> 6) {
+        const int lo = mi * span, m = lo + size, hi = min(lo + span, n);
+        if (m >= hi) {
+          if (lane == 0) R.cnt[lo] = -1;
+          continue;
+        }
+        const int k = hi - lo;
+        double *Ds = S.Ds + lo, *zs = S.zt + lo;
+        double a2 = 0.0, dm = 0.0;
+        for (int p = lane; p < k; p += 64) {
+          a2 += zs[p] * zs[p];
+          dm = fmax(dm, fabs(Ds[p]));
+        }
+        const double zn2 = wave_sum(a2), dmaxabs = wave_max(dm);
+        const double zinv = 1.0 / sqrt(zn2);
+        double zm = 0.0;
+        for (int p = lane; p < k; p += 64) {
+          const double v = zs[p] * zinv;
+          zs[p] = v;
+          zm = fmax(zm, fabs(v));
+        }
+        const double zmax = wave_max(zm);
+        const double rho = fabs(ee[m - 1]) * zn2;
+        const double tol = 8.0 * kEps * fmax(dmaxabs, zmax);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the scaled z of every lane
+        int kp = 0, nrot = 0;
+        if (lane == 0) deflate(lo, hi, Ds, zs, rho, tol, kp, nrot);
+        kp = __shfl(kp, 0);
+        nrot = __shfl(nrot, 0);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the chain's LDS writes
+        if (lane == 0) {
+          R.cnt[lo] = kp;
+          R.cnt[lo + 1] = nrot;
+          ws.rhov[lo] = rho;
+        }
+        for (int t = lane; t < kp; t += 64) {
+          const int pos = S.kpos[lo + t];
+          const double dv = Ds[pos];
+          R.dK[lo + t] = dv;
+          S.d[lo + t] = dv;
+          S.z[lo + t] = zs[pos];
+        }
+        for (int t = lane; t < k; t += 64) S.jinv[lo + S.kpos[lo + t]] = t;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // S.z complete before zs is reused
+        // S.zt[lo + t] takes z^2 for the secular solver (zs is no longer needed)
+        for (int t = lane; t < kp; t += 64) {
+          const double zv = S.z[lo + t];
+          S.zt[lo + t] = zv * zv;
+        }
       }
-      for (int t = 0; t < k; ++t) S.jinv[lo + S.kpos[lo + t]] = t;
+    } else {
+      for (int mi = tid; mi < nmerge; mi += nthr) {
+        const int lo = mi * span, m = lo + size, hi = min(lo + span, n);
+        if (m >= hi) {
+          R.cnt[lo] = -1;
+          continue;
+        }
+        const int k = hi - lo;
+        double rho = fabs(ee[m - 1]);
+        double *Ds = S.Ds + lo, *zs = S.zt + lo;
+        double zn2 = 0.0, dmaxabs = 0.0;
+        for (int p = 0; p < k; ++p) {
+          zn2 += zs[p] * zs[p];
+          dmaxabs = fmax(dmaxabs, fabs(Ds[p]));
+        }
+        const double zinv = 1.0 / sqrt(zn2);
+        double zmax = 0.0;
+        for (int p = 0; p < k; ++p) {
+          zs[p] *= zinv;
+          zmax = fmax(zmax, fabs(zs[p]));
+        }
+        rho *= zn2;
+        const double tol = 8.0 * kEps * fmax(dmaxabs, zmax);
+        int kp = 0, nrot = 0;
+        deflate(lo, hi, Ds, zs, rho, tol, kp, nrot);
+        R.cnt[lo] = kp;
+        R.cnt[lo + 1] = nrot;
+        ws.rhov[lo] = rho;
+        // kept poles and z in order; S.zt[lo + t] takes z^2 for the secular solver (position
+        // kpos[t] >= t, so no entry of zs is overwritten before it is read)
+        for (int t = 0; t < kp; ++t) {
+          const int pos = S.kpos[lo + t];
+          const double dv = Ds[pos], zv = zs[pos];
+          R.dK[lo + t] = dv;
+          S.d[lo + t] = dv;
+          S.z[lo + t] = zv;
+          S.zt[lo + t] = zv * zv;
+        }
+        for (int t = 0; t < k; ++t) S.jinv[lo + S.kpos[lo + t]] = t;
+      }
     }
     __syncthreads();
     // Phase A3: G1 = rows of G0 in sorted order; 32 lanes per row (lane c: columns c and
