@@ -94,71 +94,106 @@ __device__ inline double *dc_apply_nc(int n, int ny, DcWs ws, double *ya, double
     }
     __syncthreads();
     // T2: secular eigenvectors (and deflated identities) -> sorted-pole order.  Row j < kp of a
-    // merge is sum_t zt_j / ((d_j - d_orig(t) - tau_t) nrm_t) y_t; the y rows come through LDS
-    // kApplyChunk at a time (the threads of one merge read the same row: broadcast).
-    for (int qb = 0; qb < n; qb += nthr) {
-      const int q = qb + tid;
-      int lo = 0, kp = -1, j = 0;
-      double dj = 0.0, zj = 0.0;
-      if (q < n) {
-        lo = q - q % span;
-        kp = R.cnt[lo];
-        j = q - lo;
-        if (kp >= 0 && j < kp) {
-          dj = sdK[q];
-          zj = szt[q];
+    // merge is sum_t zt_j / ((d_j - d_orig(t) - tau_t) nrm_t) y_t, summed over t in order.
+    // Merges under 64 rows: one row per thread, the y rows read straight from memory (the
+    // threads of a merge load the same row together).  Larger merges: the y rows come through
+    // LDS kApplyChunk at a time (the threads of one merge read the same row: broadcast).
+    if (span < 64) {
+      for (int q = tid; q < n; q += nthr) {
+        const int lo = q & ~(span - 1);
+        const int kp = R.cnt[lo];
+        const int j = q - lo;
+        if (kp < 0) {
+          for (int cc = 0; cc < ny; ++cc) ya[(long long)q * kMaxOrb + cc] = yb[(long long)q * kMaxOrb + cc];
+          continue;
         }
-      }
-      const bool kept = q < n && kp >= 0 && j < kp;
-      double acc[NC];
+        double acc[NC];
+        if (j < kp) {
+          const double dj = sdK[q], zj = szt[q];
 #pragma unroll
-      for (int cc = 0; cc < NC; ++cc) acc[cc] = 0.0;
-      const int rlo = qb - qb % span, rhi = min(n, ((min(qb + nthr, n) - 1) / span + 1) * span);
-      // each chunk of y rows is fetched into registers while the previous one is used
-      constexpr int PER = (kApplyChunk * kMaxOrb + 255) / 256;
-      double pre[PER];
-      auto fetch_chunk = [&](int c0) {
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-          const int e = tid + u * nthr, r = e / ny, cc = e % ny;
-          pre[u] = (e < kApplyChunk * ny && c0 + r < n) ? yb[(long long)(c0 + r) * kMaxOrb + cc] : 0.0;
-        }
-      };
-      if (rlo < rhi) fetch_chunk(rlo);
-      for (int c0 = rlo; c0 < rhi; c0 += kApplyChunk) {
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-          const int e = tid + u * nthr;
-          if (e < kApplyChunk * ny) sy[(e / ny) * kMaxOrb + e % ny] = pre[u];
-        }
-        __syncthreads();
-        if (c0 + kApplyChunk < rhi) fetch_chunk(c0 + kApplyChunk);
-        if (kept) {
-          const int ta = max(c0, lo), tb = min(c0 + kApplyChunk, lo + kp);
-          for (int t = ta; t < tb; ++t) {
+          for (int cc = 0; cc < NC; ++cc) acc[cc] = 0.0;
+#pragma unroll 2
+          for (int t = lo; t < lo + kp; ++t) {
             const double u = zj * rcp_nr(((dj - sdK[lo + sorig[t]]) - stau[t]) * snrm[t]);
-            const double *y = sy + (t - c0) * kMaxOrb;
-            // all NC columns, unguarded (a guard per column would serialize the LDS reads);
-            // the entries past ny are never stored
+            const double *y = yb + (long long)t * kMaxOrb;
 #pragma unroll
             for (int cc = 0; cc < NC; ++cc) acc[cc] += u * y[cc];
           }
-        }
-      }
-      if (q < n) {
-        if (kp < 0) {
-          for (int cc = 0; cc < ny; ++cc) ya[(long long)q * kMaxOrb + cc] = yb[(long long)q * kMaxOrb + cc];
         } else {
-          if (!kept) {
-            const double *y = yb + (long long)(lo + j) * kMaxOrb;
+          const double *y = yb + (long long)q * kMaxOrb;
 #pragma unroll
-            for (int cc = 0; cc < NC; ++cc) acc[cc] = (cc < ny) ? y[cc] : 0.0;
+          for (int cc = 0; cc < NC; ++cc) acc[cc] = (cc < ny) ? y[cc] : 0.0;
+        }
+        const int pos = R.kpos[q];
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc)
+          if (cc < ny) ya[(long long)(lo + pos) * kMaxOrb + cc] = acc[cc];
+      }
+    } else {
+      for (int qb = 0; qb < n; qb += nthr) {
+        const int q = qb + tid;
+        int lo = 0, kp = -1, j = 0;
+        double dj = 0.0, zj = 0.0;
+        if (q < n) {
+          lo = q - q % span;
+          kp = R.cnt[lo];
+          j = q - lo;
+          if (kp >= 0 && j < kp) {
+            dj = sdK[q];
+            zj = szt[q];
           }
-          const int pos = R.kpos[lo + j];
+        }
+        const bool kept = q < n && kp >= 0 && j < kp;
+        double acc[NC];
 #pragma unroll
-          for (int cc = 0; cc < NC; ++cc)
-            if (cc < ny) ya[(long long)(lo + pos) * kMaxOrb + cc] = acc[cc];
+        for (int cc = 0; cc < NC; ++cc) acc[cc] = 0.0;
+        const int rlo = qb - qb % span, rhi = min(n, ((min(qb + nthr, n) - 1) / span + 1) * span);
+        // each chunk of y rows is fetched into registers while the previous one is used
+        constexpr int PER = (kApplyChunk * kMaxOrb + 255) / 256;
+        double pre[PER];
+        auto fetch_chunk = [&](int c0) {
+#pragma unroll
+          for (int u = 0; u < PER; ++u) {
+            const int e = tid + u * nthr, r = e / ny, cc = e % ny;
+            pre[u] = (e < kApplyChunk * ny && c0 + r < n) ? yb[(long long)(c0 + r) * kMaxOrb + cc] : 0.0;
+          }
+        };
+        if (rlo < rhi) fetch_chunk(rlo);
+        for (int c0 = rlo; c0 < rhi; c0 += kApplyChunk) {
+          __syncthreads();
+#pragma unroll
+          for (int u = 0; u < PER; ++u) {
+            const int e = tid + u * nthr;
+            if (e < kApplyChunk * ny) sy[(e / ny) * kMaxOrb + e % ny] = pre[u];
+          }
+          __syncthreads();
+          if (c0 + kApplyChunk < rhi) fetch_chunk(c0 + kApplyChunk);
+          if (kept) {
+            const int ta = max(c0, lo), tb = min(c0 + kApplyChunk, lo + kp);
+            for (int t = ta; t < tb; ++t) {
+              const double u = zj * rcp_nr(((dj - sdK[lo + sorig[t]]) - stau[t]) * snrm[t]);
+              const double *y = sy + (t - c0) * kMaxOrb;
+              // all NC columns, unguarded (a guard per column would serialize the LDS reads);
+              // the entries past ny are never stored
+#pragma unroll
+              for (int cc = 0; cc < NC; ++cc) acc[cc] += u * y[cc];
+            }
+          }
+        }
+        if (q < n) {
+          if (kp < 0) {
+            for (int cc = 0; cc < ny; ++cc) ya[(long long)q * kMaxOrb + cc] = yb[(long long)q * kMaxOrb + cc];
+          } else {
+            if (!kept) {
+              const double *y = yb + (long long)(lo + j) * kMaxOrb;
+#pragma unroll
+              for (int cc = 0; cc < NC; ++cc) acc[cc] = (cc < ny) ? y[cc] : 0.0;
+            }
+            const int pos = R.kpos[lo + j];
+#pragma unroll
+            for (int cc = 0; cc < NC; ++cc)
+              if (cc < ny) ya[(long long)(lo + pos) * kMaxOrb + cc] = acc[cc];
+          }
         }
       }
     }
