@@ -53,6 +53,41 @@ __device__ inline DcWs dc_ws(double *cv, int *ci, int nb) {
   return w;
 }
 
+// Row q of x (ny <= NC columns, row stride kMaxOrb) to row lo + idx[q] of y, lo the start of
+// q's merge (merges of span rows); rows of blocks that are not merged at this level
+// (cnt < 0) stay in place.  One thread of the 256 per row: every index of the level is loaded at once,
+// then every row, then the stores (two rounds of memory latency per level).
+template <int NC>
+__device__ inline void permute_rows(int n, int span, int ny, const int *__restrict__ idx, const double *x, double *y,
+                                    const int *__restrict__ cnt) {
+  constexpr int RPT = (kMaxDimTri + 255) / 256;
+  int dst[RPT];
+#pragma unroll
+  for (int u = 0; u < RPT; ++u) {
+    const int q = threadIdx.x + 256 * u;
+    dst[u] = -1;
+    if (q < n) {
+      const int lo = q & ~(span - 1);
+      const int c = cnt[lo], iq = idx[q];
+      dst[u] = c < 0 ? q : lo + iq;
+    }
+  }
+  double v[RPT][NC];
+#pragma unroll
+  for (int u = 0; u < RPT; ++u) {
+    const double *xr = x + (long long)min((int)threadIdx.x + 256 * u, n - 1) * kMaxOrb;
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) v[u][cc] = xr[cc];
+  }
+#pragma unroll
+  for (int u = 0; u < RPT; ++u)
+    if (dst[u] >= 0) {
+#pragma unroll
+      for (int cc = 0; cc < NC; ++cc)
+        if (cc < ny) y[(long long)dst[u] * kMaxOrb + cc] = v[u][cc];
+    }
+}
+
 // y (n rows, ny columns, row stride kMaxOrb) in final eigenvalue order -> Z y in the
 // tridiagonal index order.  ya/yb: ping-pong buffers; the result ends in the returned one.
 // lds: at least 4.5 n + kApplyChunk * kMaxOrb doubles: a level's secular data (poles, z,
@@ -73,15 +108,7 @@ __device__ inline double *dc_apply_nc(int n, int ny, DcWs ws, double *ya, double
     const DcRec R = dc_rec(ws.dcd, ws.dci, n, l);
     const int nmerge = (n + span - 1) / span;
     // T1: output order -> element order; stage the level's secular data
-    for (long long e = tid; e < (long long)n * ny; e += nthr) {
-      const int q = (int)(e / ny), cc = (int)(e % ny);
-      const int lo = q - q % span;
-      if (R.cnt[lo] < 0) {
-        yb[(long long)q * kMaxOrb + cc] = ya[(long long)q * kMaxOrb + cc];
-        continue;
-      }
-      yb[(long long)(lo + R.oo[q]) * kMaxOrb + cc] = ya[(long long)q * kMaxOrb + cc];
-    }
+    permute_rows<NC>(n, span, ny, R.oo, ya, yb, R.cnt);
     for (int q = tid; q < n; q += nthr) {
       const int lo = q - q % span;
       const int kp = R.cnt[lo];
@@ -215,15 +242,7 @@ __device__ inline double *dc_apply_nc(int n, int ny, DcWs ws, double *ya, double
     }
     __syncthreads();
     // T4: undo the sort
-    for (long long e = tid; e < (long long)n * ny; e += nthr) {
-      const int q = (int)(e / ny), cc = (int)(e % ny);
-      const int lo = q - q % span;
-      if (R.cnt[lo] < 0) {
-        yb[(long long)q * kMaxOrb + cc] = ya[(long long)q * kMaxOrb + cc];
-        continue;
-      }
-      yb[(long long)(lo + R.perm[q]) * kMaxOrb + cc] = ya[(long long)q * kMaxOrb + cc];
-    }
+    permute_rows<NC>(n, span, ny, R.perm, ya, yb, R.cnt);
     __syncthreads();
     double *t = ya;
     ya = yb;
