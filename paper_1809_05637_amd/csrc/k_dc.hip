@@ -418,35 +418,37 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
       }
     }
     __syncthreads();
-    // Phase A3: G1 = rows of G0 in sorted order; 32 lanes per row (lane c: columns c and
-    // c + 32), eight rows per thread in flight
+    // Phase A3: G1 = rows of G0 in sorted order.  One thread of the 256 per row: every source
+    // index of the level is loaded at once, then the rows eight columns at a time
     {
-      const int cq = tid & 31, rstep = nthr >> 5;
-      for (int q0 = tid >> 5; q0 < n; q0 += 8 * rstep) {
-        int src[8];
+      constexpr int RPT = (kMaxDimTri + 255) / 256;
+      int src[RPT];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int q = q0 + u * rstep;
-          src[u] = -1;
-          if (q < n) {
-            const int lo = q & ~(span - 1);
-            if (R.cnt[lo] >= 0) src[u] = lo + R.perm[q];
-          }
+      for (int u = 0; u < RPT; ++u) {
+        const int q = tid + 256 * u;
+        src[u] = -1;
+        if (q < n) {
+          const int lo = q & ~(span - 1);
+          const int c = R.cnt[lo], pq = R.perm[q];
+          src[u] = c < 0 ? -1 : lo + pq;
         }
-        double v0[8], v1[8];
+      }
+      for (int c0 = 0; c0 < nt; c0 += 8) {
+        double v[RPT][8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < RPT; ++u) {
           const double *g = G0 + (long long)max(src[u], 0) * kTrack;
-          v0[u] = g[cq];
-          v1[u] = cq + 32 < kTrack ? g[min(cq + 32, kTrack - 1)] : 0.0;
+#pragma unroll
+          for (int c = 0; c < 8; ++c) v[u][c] = g[min(c0 + c, kTrack - 1)];
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          if (src[u] < 0) continue;
-          double *o = G1 + (long long)(q0 + u * rstep) * kTrack;
-          if (cq < nt) o[cq] = v0[u];
-          if (cq + 32 < nt) o[cq + 32] = v1[u];
-        }
+        for (int u = 0; u < RPT; ++u)
+          if (src[u] >= 0) {
+            double *o = G1 + (long long)(tid + 256 * u) * kTrack;
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+              if (c0 + c < nt) o[c0 + c] = v[u][c];
+          }
       }
     }
     __syncthreads();
