@@ -32,6 +32,50 @@ __device__ __noinline__ void density_q1(const double *A, int n, const double *Tq
   wg_apply_q1(A, n, Tq, r, M, lds);
 }
 
+// x(g, a) = sum_{t >= g} Linv(t, g) r(t, a) for the rows g in [b0, n) on the FP64 matrix cores
+// (Linv column-major with leading dimension ld; r and x row-major with row stride kMaxOrb, M
+// columns).  Wave w takes the 16-row output tiles g0 = b0 + 16 i, i = w, w + 4, ...; K step k
+// covers the rows t = g0 + 4 k + l/16: lane l's A operand is Linv(t, g0 + l % 16) (zero for
+// t < g or t >= n), its B operand r(t, l % 16) (zero for t >= n); register j of the result
+// then holds x(g0 + l/16 + 4 j, l % 16).  Eight K steps per round, their loads issued together.
+// Columns M.. of r only reach columns M.. of the result, which are not stored.  Kept out of line
+// (inlined, it changes the register allocation of the merge product and slows it).
+__device__ __noinline__ void density_lt(const double *__restrict__ L, int ld, int n, int b0, const double *__restrict__ r,
+                                        double *__restrict__ x, int M) {
+  // the arguments are wave-uniform (out of line they arrive in vector registers)
+  L = uniform_ptr(L);
+  r = uniform_ptr(r);
+  x = uniform_ptr(x);
+  ld = __builtin_amdgcn_readfirstlane(ld);
+  n = __builtin_amdgcn_readfirstlane(n);
+  b0 = __builtin_amdgcn_readfirstlane(b0);
+  M = __builtin_amdgcn_readfirstlane(M);
+  const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int ntile = (n - b0 + 15) >> 4;
+  for (int i = wave; i < ntile; i += 4) {
+    const int g0 = b0 + 16 * i, g = g0 + li;
+    const double *lc = L + (long long)min(g, n - 1) * ld;
+    ldc_double4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int t0 = g0; t0 < n; t0 += 32) {
+      double av[8], bv[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int t = t0 + 4 * k + lg, tc = min(t, n - 1);
+        av[k] = (t >= g && t < n) ? lc[tc] : 0.0;
+        bv[k] = t < n ? r[(long long)tc * kMaxOrb + li] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[k], bv[k], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gr = g0 + lg + 4 * j;
+      if (gr < n && li < M) x[(long long)gr * kMaxOrb + li] = acc[j];
+    }
+  }
+}
+
 // state layout of Plan::d_mu
 enum { MU_LO = 0, MU_HI, MU_DONE, MU_IT, MU_SUMW, MU_NE, MU_KT, MU_G, MU_MU, MU_BAD };
 
@@ -270,24 +314,7 @@ __global__ void __launch_bounds__(256, 2) density_kernel(
     // x(g) = sum_{t >= g} Linv(t, g) r(t), written to the other buffer
     const int b0 = n - p;
     double *xo = (r == ya) ? yb : ya;
-    for (int e = tid; e < p * M; e += nthr) {
-      const int g = b0 + e / M, a = e % M;
-      const double *lc = L + (long long)g * ld;
-      double acc = 0.0;
-      // 8 rows per step, clamped past the end (their factor is zero): loads in flight together
-      for (int t0 = g; t0 < n; t0 += 8) {
-        double lv[8], rv[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int t = min(t0 + u, n - 1);
-          lv[u] = lc[t];
-          rv[u] = r[(long long)t * kMaxOrb + a];
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) acc += (t0 + u < n) ? lv[u] * rv[u] : 0.0;
-      }
-      xo[(long long)g * kMaxOrb + a] = acc;
-    }
+    density_lt(L, ld, n, b0, r, xo, M);
     __syncthreads();
     r = xo;
     // scatter D(i, j) for j in F_i (members F \ {i} then i, last in the member list)
