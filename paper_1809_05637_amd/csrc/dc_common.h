@@ -3,6 +3,7 @@
 #pragma once
 
 #include "dev_common.h"
+#include "wg_blas.h"
 
 namespace ldc {
 
@@ -88,19 +89,103 @@ __device__ inline void permute_rows(int n, int span, int ny, const int *__restri
     }
 }
 
+// The row sums of the merge product for merges of 64 rows or more, on the FP64 matrix cores.
+// Each wave takes 64 output rows j of one merge as four 16-row tiles; K step s covers the roots
+// t = lo + 4 s + l/16: lane l forms the weight u(j, t) = zt_j / (((d_j - d_orig(t)) - tau_t)
+// nrm_t) of row j = q0 + 16 c + l % 16 of every tile c (the A operands) and reads column l % 16
+// of y_t from memory (the B operand), so the waves need no barrier; register r of tile c's
+// result then holds row q0 + 16 c + l/16 + 4 r.  Weights of rows that are not kept, and of
+// roots past the last, are zero (selected, not multiplied); columns ny.. of y only reach columns
+// that are not stored.  Rows j >= kp are copies of their own y row, blocks that are not merged
+// (cnt < 0) copies in place.  Out of line (its registers apart from the kernel's); the LDS
+// arrays hold the level's secular data as staged by the caller.
+__device__ __noinline__ void dc_apply_rows_mfma(int n, int span, int ny, const int *__restrict__ cnt,
+                                                const int *__restrict__ kpos, const double *sdK_, const double *szt_,
+                                                const double *stau_, const double *snrm_, const int *sorig_,
+                                                const double *__restrict__ yb, double *__restrict__ ya) {
+  n = __builtin_amdgcn_readfirstlane(n);
+  span = __builtin_amdgcn_readfirstlane(span);
+  ny = __builtin_amdgcn_readfirstlane(ny);
+  // the secular data lives in LDS: address it as such (out of line the pointers are generic)
+  typedef __attribute__((address_space(3))) const double lds_double;
+  typedef __attribute__((address_space(3))) const int lds_int;
+  lds_double *sdK = (lds_double *)sdK_, *szt = (lds_double *)szt_, *stau = (lds_double *)stau_,
+             *snrm = (lds_double *)snrm_;
+  lds_int *sorig = (lds_int *)sorig_;
+  const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int q0 = 64 * wave; q0 < n; q0 += 256) {
+    const int lo = q0 & ~(span - 1);
+    const int kp = cnt[lo];
+    const int q = q0 + lane;
+    if (kp < 0) {
+      if (q < n)
+        for (int cc = 0; cc < ny; ++cc) ya[(long long)q * kMaxOrb + cc] = yb[(long long)q * kMaxOrb + cc];
+      continue;
+    }
+    double dj[4], zj[4];
+    bool kj[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int j = q0 + 16 * c + li;
+      kj[c] = j < n && j - lo < kp;
+      dj[c] = kj[c] ? sdK[j] : 0.0;
+      zj[c] = kj[c] ? szt[j] : 0.0;
+    }
+    ldc_double4 acc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = ldc_double4{0.0, 0.0, 0.0, 0.0};
+    const int tend = lo + kp;
+    for (int t0 = lo; t0 < tend; t0 += 4) {
+      const int t = t0 + lg;
+      const bool in = t < tend;
+      const int tc = in ? t : tend - 1;
+      const double dor = sdK[lo + sorig[tc]], ta = stau[tc], nr = snrm[tc];
+      const double yv = yb[(long long)tc * kMaxOrb + li];
+      double x[4], r[4], e[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) x[c] = ((dj[c] - dor) - ta) * nr;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) r[c] = __builtin_amdgcn_rcp(x[c]);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) e[c] = fma(-x[c], r[c], 1.0);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) r[c] = fma(r[c], e[c], r[c]);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) e[c] = fma(-x[c], r[c], 1.0);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) r[c] = fma(r[c], e[c], r[c]);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const double w = (in && kj[c]) ? zj[c] * r[c] : 0.0;
+        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(w, yv, acc[c], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int j = q0 + 16 * c + lg + 4 * rr;
+        if (j < n && j - lo < kp && li < ny) ya[(long long)(lo + kpos[j]) * kMaxOrb + li] = acc[c][rr];
+      }
+    if (q < n && q - lo >= kp) {
+      const int pos = kpos[q];
+      for (int cc = 0; cc < ny; ++cc) ya[(long long)(lo + pos) * kMaxOrb + cc] = yb[(long long)q * kMaxOrb + cc];
+    }
+  }
+}
+
 // y (n rows, ny columns, row stride kMaxOrb) in final eigenvalue order -> Z y in the
 // tridiagonal index order.  ya/yb: ping-pong buffers; the result ends in the returned one.
-// lds: at least 4.5 n + kApplyChunk * kMaxOrb doubles: a level's secular data (poles, z,
-// roots, norms, origins) and a chunk of y rows are staged there, so the row sums read LDS.
-constexpr int kApplyChunk = 32;
-__device__ inline int dc_apply_lds_doubles(int n) { return 4 * n + (n + 1) / 2 + kApplyChunk * kMaxOrb; }
+// lds: at least 4.5 n doubles: a level's secular data (poles, z, roots, norms, origins) is
+// staged there, so the row sums read it from LDS.
+__device__ inline int dc_apply_lds_doubles(int n) { return 4 * n + (n + 1) / 2; }
 
 template <int NC>
 __device__ inline double *dc_apply_nc(int n, int ny, DcWs ws, double *ya, double *yb, double *lds) {
   const int tid = threadIdx.x, nthr = blockDim.x;
   double *sdK = lds, *szt = lds + n, *stau = lds + 2 * n, *snrm = lds + 3 * n;
   int *sorig = reinterpret_cast<int *>(lds + 4 * n);
-  double *sy = lds + 4 * n + (n + 1) / 2;  // kApplyChunk x kMaxOrb
   int L = 0;
   while ((1 << L) < n) ++L;
   for (int l = L - 1; l >= 0; --l) {
@@ -123,8 +208,7 @@ __device__ inline double *dc_apply_nc(int n, int ny, DcWs ws, double *ya, double
     // T2: secular eigenvectors (and deflated identities) -> sorted-pole order.  Row j < kp of a
     // merge is sum_t zt_j / ((d_j - d_orig(t) - tau_t) nrm_t) y_t, summed over t in order.
     // Merges under 64 rows: one row per thread, the y rows read straight from memory (the
-    // threads of a merge load the same row together).  Larger merges: the y rows come through
-    // LDS kApplyChunk at a time (the threads of one merge read the same row: broadcast).
+    // threads of a merge load the same row together).  Larger merges: on the matrix cores.
     if (span < 64) {
       for (int q = tid; q < n; q += nthr) {
         const int lo = q & ~(span - 1);
@@ -157,72 +241,7 @@ __device__ inline double *dc_apply_nc(int n, int ny, DcWs ws, double *ya, double
           if (cc < ny) ya[(long long)(lo + pos) * kMaxOrb + cc] = acc[cc];
       }
     } else {
-      for (int qb = 0; qb < n; qb += nthr) {
-        const int q = qb + tid;
-        int lo = 0, kp = -1, j = 0;
-        double dj = 0.0, zj = 0.0;
-        if (q < n) {
-          lo = q - q % span;
-          kp = R.cnt[lo];
-          j = q - lo;
-          if (kp >= 0 && j < kp) {
-            dj = sdK[q];
-            zj = szt[q];
-          }
-        }
-        const bool kept = q < n && kp >= 0 && j < kp;
-        double acc[NC];
-#pragma unroll
-        for (int cc = 0; cc < NC; ++cc) acc[cc] = 0.0;
-        const int rlo = qb - qb % span, rhi = min(n, ((min(qb + nthr, n) - 1) / span + 1) * span);
-        // each chunk of y rows is fetched into registers while the previous one is used
-        constexpr int PER = (kApplyChunk * kMaxOrb + 255) / 256;
-        double pre[PER];
-        auto fetch_chunk = [&](int c0) {
-#pragma unroll
-          for (int u = 0; u < PER; ++u) {
-            const int e = tid + u * nthr, r = e / ny, cc = e % ny;
-            pre[u] = (e < kApplyChunk * ny && c0 + r < n) ? yb[(long long)(c0 + r) * kMaxOrb + cc] : 0.0;
-          }
-        };
-        if (rlo < rhi) fetch_chunk(rlo);
-        for (int c0 = rlo; c0 < rhi; c0 += kApplyChunk) {
-          __syncthreads();
-#pragma unroll
-          for (int u = 0; u < PER; ++u) {
-            const int e = tid + u * nthr;
-            if (e < kApplyChunk * ny) sy[(e / ny) * kMaxOrb + e % ny] = pre[u];
-          }
-          __syncthreads();
-          if (c0 + kApplyChunk < rhi) fetch_chunk(c0 + kApplyChunk);
-          if (kept) {
-            const int ta = max(c0, lo), tb = min(c0 + kApplyChunk, lo + kp);
-            for (int t = ta; t < tb; ++t) {
-              const double u = zj * rcp_nr(((dj - sdK[lo + sorig[t]]) - stau[t]) * snrm[t]);
-              const double *y = sy + (t - c0) * kMaxOrb;
-              // all NC columns, unguarded (a guard per column would serialize the LDS reads);
-              // the entries past ny are never stored
-#pragma unroll
-              for (int cc = 0; cc < NC; ++cc) acc[cc] += u * y[cc];
-            }
-          }
-        }
-        if (q < n) {
-          if (kp < 0) {
-            for (int cc = 0; cc < ny; ++cc) ya[(long long)q * kMaxOrb + cc] = yb[(long long)q * kMaxOrb + cc];
-          } else {
-            if (!kept) {
-              const double *y = yb + (long long)(lo + j) * kMaxOrb;
-#pragma unroll
-              for (int cc = 0; cc < NC; ++cc) acc[cc] = (cc < ny) ? y[cc] : 0.0;
-            }
-            const int pos = R.kpos[lo + j];
-#pragma unroll
-            for (int cc = 0; cc < NC; ++cc)
-              if (cc < ny) ya[(long long)(lo + pos) * kMaxOrb + cc] = acc[cc];
-          }
-        }
-      }
+      dc_apply_rows_mfma(n, span, ny, R.cnt, R.kpos, sdK, szt, stau, snrm, sorig, yb, ya);
     }
     __syncthreads();
     // T3: deflation rotations, reverse order

@@ -17,9 +17,9 @@
 
 namespace ldc {
 
-// dynamic LDS besides the Q2 product's: the staging of the product Z y and the partial
+// dynamic LDS besides the Q2 product's: the secular data of the product Z y and the partial
 // products of Q1 r
-constexpr int kDensityLds = std::max(4 * kMaxDimTri + (kMaxDimTri + 1) / 2 + kApplyChunk * kMaxOrb, kQ1Lds);
+constexpr int kDensityLds = std::max(4 * kMaxDimTri + (kMaxDimTri + 1) / 2, kQ1Lds);
 
 // Q2 r with r in LDS, kept out of line: inlined into the density kernel it raises the register
 // pressure of the whole kernel and spills (44.8 vs 94 ms per build on the 3920-atom slab)
