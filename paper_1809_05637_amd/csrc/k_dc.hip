@@ -196,7 +196,8 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
                            DcLds S, DevStatus *st, int cid) {
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int Fc = nx, Lc = nx + 1, nt = nx + 2;
-  __shared__ int qnext;  // the secular roots' work queue
+  __shared__ int qnext;                          // the secular roots' work queue
+  __shared__ int mono[(kMaxDimTri + 63) / 64];  // per merge of 64 rows or more: kept values in order
   double *lam = ws.lam, *G0 = ws.G0, *G1 = ws.G1;
   for (int i = tid; i < n; i += nthr) {
     double di = dd[i];
@@ -601,6 +602,21 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
       S.z[q] = x < kp ? S.d[lo + S.orig[lo + x]] + S.tau[lo + x] : S.Ds[lo + S.kpos[lo + x]];
     }
     __syncthreads();
+    // In a merge of 64 rows or more whose kept values (the secular roots, one per interval
+    // between poles) are non-decreasing, as they are unless rounding crossed a pole, the kept
+    // part is counted by bisection (its (key, index) pairs increase) and only the deflated part
+    // is scanned; otherwise every element of the merge is scanned.
+    const bool big = span >= 64;
+    if (big) {
+      if (tid < nmerge) mono[tid] = 1;
+      __syncthreads();
+      for (int q = tid; q < n; q += nthr) {
+        const int lo = q & ~(span - 1);
+        const int kp = R.cnt[lo];
+        if (kp >= 0 && q + 1 < lo + kp && dc_key(S.z[q]) > dc_key(S.z[q + 1])) mono[q / span] = 0;
+      }
+      __syncthreads();
+    }
     for (int q = tid; q < n; q += nthr) {
       const int lo = q - q % span;
       const int kp = R.cnt[lo];
@@ -609,8 +625,19 @@ __device__ void dc_forward(int n, const double *__restrict__ dd, const double *_
       const int e = q - lo;
       const double ve = S.z[q];
       const long long ke = dc_key(ve);
-      int rank = 0;
-      for (int x = lo; x < hi; ++x) {
+      int rank = 0, x0 = lo;
+      if (big && mono[lo / span]) {
+        int a = lo, b = lo + kp;
+        while (a < b) {
+          const int m = (a + b) >> 1;
+          const long long km = dc_key(S.z[m]);
+          if (km < ke || (km == ke && m < q)) a = m + 1;
+          else b = m;
+        }
+        rank = a - lo;
+        x0 = lo + kp;
+      }
+      for (int x = x0; x < hi; ++x) {
         const long long kx = dc_key(S.z[x]);
         rank += (kx < ke) || (kx == ke && x < q);
       }
