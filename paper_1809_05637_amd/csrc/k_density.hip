@@ -17,14 +17,16 @@
 
 namespace ldc {
 
-// dynamic LDS besides the Q2 product's: the secular data of the product Z y and the partial
-// products of Q1 r
+// dynamic LDS: the secular data of the product Z y, then the reflector runs and row exchange of
+// Q2 r, then the partial products of Q1 r
 constexpr int kDensityLds = std::max(4 * kMaxDimTri + (kMaxDimTri + 1) / 2, kQ1Lds);
+// the Q2 product's three reflector runs and its row exchange fit the same area
+static_assert(3 * ((kMaxDimTri + kBand) | 1) + 2 * 16 * 32 <= kDensityLds, "Q2 runs and exchange");
 
-// Q2 r with r in LDS, kept out of line: inlined into the density kernel it raises the register
-// pressure of the whole kernel and spills (44.8 vs 94 ms per build on the 3920-atom slab)
-__device__ __noinline__ void density_q2_lds(const double *A, int n, double *Xs, int nc, double *runs) {
-  wg_apply_q2_lds(A, n, Xs, nc, runs, false);
+// Q2 r with the rows of r held in registers, kept out of line: inlined into the density kernel it
+// raises the register pressure of the whole kernel and spills
+__device__ __noinline__ void density_q2(const double *A, int n, double *r, int nc, double *runs, double *ex) {
+  wg_apply_q2_regs(A, n, r, nc, runs, ex);
 }
 
 // Q1 r, kept out of line for the same reason: it holds r in registers
@@ -259,12 +261,12 @@ __global__ void __launch_bounds__(256, 2) density_kernel(
     const int *__restrict__ n_orb, const int *__restrict__ p_rows, const int *__restrict__ mem_ptr,
     const int *__restrict__ mem_atom, const int *__restrict__ fna_ptr, const int *__restrict__ fna_blk,
     const long long *__restrict__ blk_off, const double *__restrict__ state, const double *__restrict__ H,
-    const double *__restrict__ S, double *__restrict__ Dout, double *__restrict__ partial, int q2_lds, int max_dim) {
+    const double *__restrict__ S, double *__restrict__ Dout, double *__restrict__ partial, int max_dim) {
   __shared__ double red[16 * 17];
   __shared__ double sred[8];
   __shared__ int foff[kMaxMembers + 1];
-  // dynamic LDS: the compact-WY and merge staging area, which the Q2 product reuses to hold
-  // the n x M rows and the reflector runs when q2_lds is set
+  // dynamic LDS (kDensityLds doubles): the merge product's secular data, then Q2's reflector
+  // runs and row exchange, then Q1's partial products
   extern __shared__ double qlds[];
   const int tid = threadIdx.x, nthr = blockDim.x;
   const double mu = state[MU_MU], kT = state[MU_KT];
@@ -298,16 +300,10 @@ __global__ void __launch_bounds__(256, 2) density_kernel(
     double *r = dc_apply(n, M, ws, ya, yb, qlds);
     // r <- Q r = Q1 (Q2 r): the bulge-chasing reflectors, then the band reduction's compact-WY
     // panels (T factors stored by the band reduction)
-    if (q2_lds && n >= 3) {
-      __syncthreads();  // the merge staging in the same LDS is done
-      const int P = q2_lds_stride(n);
-      double *Xs = qlds, *runs = qlds + (long long)M * P;
-      for (int e = tid; e < n * M; e += nthr) Xs[(long long)(e % M) * P + e / M] = r[(long long)(e / M) * kMaxOrb + e % M];
-      density_q2_lds(A, n, Xs, M, runs);
-      for (int e = tid; e < n * M; e += nthr) r[(long long)(e / M) * kMaxOrb + e % M] = Xs[(long long)(e % M) * P + e / M];
-      __syncthreads();
-    } else {
-      wg_apply_q2(A, ld, n, r, kMaxOrb, M, false);
+    if (n >= 3) {
+      __syncthreads();  // the merge data in the same LDS is no longer read
+      double *runs = qlds, *ex = qlds + 3LL * q2_lds_stride(n);
+      density_q2(A, n, r, M, runs, ex);
     }
     density_q1(A, n, cv + vl.u, r, M, qlds);
     // x_P = L_PP^{-T} r_P = ((L^{-1})_PP)^T r_P (P = the last p rows; the S slot holds L^{-1}):
@@ -378,24 +374,14 @@ void launch_mu_step(Plan &p, double, double, double) {
 void launch_density(Plan &p, int mode, double *d_D, const double *d_H, const double *d_S, double w_lo, double w_hi,
                     double w_kT) {
   double *cl_partial = p.d_partial + kMuStride * p.workgroups;
-  // the Q2 product runs in LDS when the M padded columns and three reflector runs of the
-  // bucket's largest cluster still let two workgroups share a CU (72 KB each besides the 6 KB of
-  // static LDS)
   const int dm = cur_dim(p);
-  const size_t base = sizeof(double) * kDensityLds;
-  const size_t q2 = sizeof(double) * (size_t)q2_lds_stride(dm) * (size_t)(p.mmax + 3);
-  int q2_lds = q2 <= 72 * 1024;
-  if (q2_lds && q2 > 64 * 1024 &&
-      hipFuncSetAttribute(reinterpret_cast<const void *>(density_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)q2) != hipSuccess)
-    q2_lds = 0;
-  const size_t lds = q2_lds ? std::max(base, q2) : base;
+  const size_t lds = sizeof(double) * kDensityLds;
   const int n = cur_count(p);
   const int grid = std::max(1, std::min(stage_grid(p, kTDensity, p.workgroups), n));
   hipLaunchKernelGGL(density_kernel, dim3(grid), dim3(kWG), lds, p.stream, mode, w_lo, w_hi, w_kT, n, cur_order(p),
                      p.d_mat, p.d_mat_off, p.d_vec, p.d_vec_off, p.d_ivec, p.d_ivec_off, p.d_dmax, p.d_dim, p.d_n_orb,
                      p.d_p_rows, p.d_mem_ptr, p.d_mem_atom, p.d_fna_ptr, p.d_fna_blk, p.d_blk_off, p.d_mu, d_H, d_S,
-                     d_D, cl_partial, q2_lds, dm);
+                     d_D, cl_partial, dm);
 }
 
 void launch_density_sums(Plan &p, int mode) {

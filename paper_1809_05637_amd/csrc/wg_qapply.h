@@ -321,4 +321,111 @@ __device__ void wg_apply_q2_lds(const double *__restrict__ A, int n, double *Xs,
   }
 }
 
+// Q2 X (not transposed) with X held in registers: X (n rows, nc <= 16 columns, row-major with
+// row stride kMaxOrb) in memory, the reflector runs parked in LDS as in wg_apply_q2_lds (runs:
+// 3 P doubles), ex: 2 x 32 x 16 doubles of LDS.  The sweeps run backwards; at sweep s the rows
+// s + 1 .. of X are held in windows of 32 rows, window j = rows s + 1 + 32 j .. s + 32 j + 32
+// (rows past n zero), window j in lane q of group j mod 16 (two windows per lane, j and
+// j + 16).  Step j of sweep s acts on exactly window j, so the sweep reads the 32 reflector
+// entries from LDS and touches no other memory.  From sweep s + 1 to s every window moves up by
+// one row: its last row goes to window j + 1 (through ex, double-buffered by sweep parity),
+// window 0 takes row s + 1 of X, which no later sweep has touched (fetched a sweep ahead).  The
+// windows hold rows 1.. of Q2 X at the end and go back to X (row 0 is not touched).  One barrier
+// per sweep.  Whole workgroup (256 threads); ends with a barrier.
+__device__ void wg_apply_q2_regs(const double *__restrict__ A, int n, double *X, int nc, double *runs, double *ex) {
+  constexpr int b = kBand;
+  // the arguments are wave-uniform (out of line they arrive in vector registers)
+  A = uniform_ptr(A);
+  X = uniform_ptr(X);
+  n = __builtin_amdgcn_readfirstlane(n);
+  nc = __builtin_amdgcn_readfirstlane(nc);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int grp = tid >> 4, q = tid & 15;
+  const int P = q2_lds_stride(n);
+  const int nsw = n - 2;  // sweeps 0 .. n-3, run from the last
+  auto sweep = [&](int it) { return max(0, min(nsw - 1 - it, n - 3)); };
+  auto park = [&](double *dst, const double *nx, int it) {
+    const int nlen = n - 1 - sweep(it);
+#pragma unroll
+    for (int u = 0; u < kQ2Run; ++u) {
+      const int e = tid + u * nthr;
+      if (e < nlen + b) dst[e] = e < nlen ? nx[u] : 0.0;
+    }
+  };
+  const double *xc = X + min(q, nc - 1);
+  // the windows at the first sweep (s = n - 3: rows n - 2 ..)
+  double xw[2][b];
+#pragma unroll
+  for (int w = 0; w < 2; ++w)
+#pragma unroll
+    for (int i = 0; i < b; ++i) {
+      const int row = n - 2 + b * (grp + 16 * w) + i;
+      const double v = xc[(long long)min(row, n - 1) * kMaxOrb];
+      xw[w][i] = row < n ? v : 0.0;
+    }
+  double nx0[kQ2Run], nx1[kQ2Run];
+  q2_fetch_run(nx0, A, n, sweep(0), tid, nthr);
+  q2_fetch_run(nx1, A, n, sweep(1), tid, nthr);
+  park(runs, nx0, 0);
+  // row s + 1 of X for the next sweep's window 0
+  double top = xc[(long long)max(sweep(1) + 1, 0) * kMaxOrb];
+  __syncthreads();
+  for (int it = 0; it < nsw; ++it) {
+    const int s = sweep(it);
+    q2_fetch_run(nx0, A, n, sweep(it + 2), tid, nthr);
+    if (it > 0) {
+      // move every window up by one row
+      const double *exr = ex + ((it - 1) & 1) * (2 * 16 * 16);
+#pragma unroll
+      for (int w = 0; w < 2; ++w) {
+        const int j = grp + 16 * w;
+        const double in = j == 0 ? top : exr[(j - 1) * 16 + q];
+#pragma unroll
+        for (int i = b - 1; i > 0; --i) xw[w][i] = xw[w][i - 1];
+        xw[w][0] = in;
+      }
+      top = xc[(long long)max(sweep(it + 1) + 1, 0) * kMaxOrb];
+    }
+    const double *cur = runs + (it % 3) * P;
+    const int nst = (n - 3 - s) / b + 1;
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+      const int j = grp + 16 * w;
+      if (j < nst) {
+        const double *vp = cur + j * b;
+        double vv[b];
+#pragma unroll
+        for (int i = 0; i < b; ++i) vv[i] = vp[i];
+        const double tau = vv[0];
+        vv[0] = 1.0;
+        double d4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < b; ++i) d4[i & 3] += vv[i] * xw[w][i];
+        const double d = ((d4[0] + d4[1]) + (d4[2] + d4[3])) * tau;
+#pragma unroll
+        for (int i = 0; i < b; ++i) xw[w][i] -= d * vv[i];
+      }
+    }
+    // the last row of every window, for window j + 1 at the next sweep
+    double *exw = ex + (it & 1) * (2 * 16 * 16);
+#pragma unroll
+    for (int w = 0; w < 2; ++w) exw[(grp + 16 * w) * 16 + q] = xw[w][b - 1];
+    park(runs + ((it + 1) % 3) * P, nx1, it + 1);
+#pragma unroll
+    for (int u = 0; u < kQ2Run; ++u) nx1[u] = nx0[u];
+    __syncthreads();
+  }
+  // rows 1 + 32 j + i
+  if (q < nc) {
+#pragma unroll
+    for (int w = 0; w < 2; ++w)
+#pragma unroll
+      for (int i = 0; i < b; ++i) {
+        const int row = 1 + b * (grp + 16 * w) + i;
+        if (row < n) X[(long long)row * kMaxOrb + q] = xw[w][i];
+      }
+  }
+  __syncthreads();
+}
+
 }  // namespace ldc
