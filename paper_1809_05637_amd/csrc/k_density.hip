@@ -26,7 +26,7 @@ static_assert(3 * ((kMaxDimTri + kBand) | 1) + 2 * 16 * 32 <= kDensityLds, "Q2 r
 // Q2 r with the rows of r held in registers, kept out of line: inlined into the density kernel it
 // raises the register pressure of the whole kernel and spills
 __device__ __noinline__ void density_q2(const double *A, int n, double *r, int nc, double *runs, double *ex) {
-  wg_apply_q2_regs(A, n, r, nc, runs, ex);
+  wg_apply_q2_regs<false>(A, n, r, kMaxOrb, nc, runs, ex);
 }
 
 // Q1 r, kept out of line for the same reason: it holds r in registers

@@ -22,7 +22,7 @@
 // [r0, r0 + b) of the band (column s too for j = 0), so step j of sweep s + 1 (columns
 // [r0 + 1, r0 + 1 + b)) only needs steps j and j + 1 of sweep s, and at time t every sweep s with
 // j = t - 2 s in range is advanced at once, one wavefront per step.  The reflectors are kept in the strictly upper triangle of A
-// (sweep s in column n - 1 - s, rows j b..: tau first, then v(1:)); q2x_lds_kernel then
+// (sweep s in column n - 1 - s, rows j b..: tau first, then v(1:)); q2x_kernel then
 // forms X <- Q2^T X, sweep by sweep.
 #include "wg_blas.h"
 #include "wg_qapply.h"
@@ -612,49 +612,23 @@ __global__ void __launch_bounds__(64 * kChaseWaves, 4) sb2st_kernel(int n_cluste
   }
 }
 
-// Tracked columns X <- Q2^T X after the bulge chasing (sweep after sweep, each sweep's
-// reflectors on disjoint rows).  Each workgroup takes one half of a cluster's 2M tracked
-// columns (the [L^{-1} E_i] or the [L^T E_i] half), so two workgroups fit a CU.  That half
-// (n x M) stays in LDS for all sweeps: the only global traffic is X in and out once and every
-// reflector read once per half.
-__global__ void __launch_bounds__(256, 2) q2x_lds_kernel(int n_clusters, const int *__restrict__ order,
-                                                      const double *__restrict__ mat,
-                                                      const long long *__restrict__ mat_off,
-                                                      double *__restrict__ vec, const long long *__restrict__ vec_off,
-                                                      const int *__restrict__ dmax, const int *__restrict__ dim,
-                                                      const int *__restrict__ n_orb, int max_dim) {
-  extern __shared__ double q2l[];
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  for (int item = blockIdx.x; item < 2 * n_clusters; item += gridDim.x) {
-    const int c = order[item >> 1], half = item & 1;
-    const int n = dim[c], nc = n_orb[c];
-    const double *A = mat + mat_off[c];
-    const VecLayout vl = VecLayout::make(dmax[c]);
-    double *X = vec + vec_off[c] + vl.G0 + half * nc;  // n x nc of the n x kTrack row-major block
-    const int P = q2_lds_stride(n);
-    double *Xs = q2l;                                  // nc columns of P rows
-    double *runs = q2l + (long long)nc * P;            // 3 x P
-    __syncthreads();
-    if (n < 3) continue;
-    for (int e = tid; e < n * nc; e += nthr) Xs[(long long)(e % nc) * P + e / nc] = X[(e / nc) * kTrack + e % nc];
-    wg_apply_q2_lds(A, n, Xs, nc, runs, true);
-    for (int e = tid; e < n * nc; e += nthr) X[(e / nc) * kTrack + e % nc] = Xs[(long long)(e % nc) * P + e / nc];
-  }
-}
-
-// Global-memory variant for clusters whose X does not fit in LDS.
+// X <- Q2^T X for the tracked columns: one workgroup per half (M columns) of a cluster's 2M,
+// the rows held in register windows (wg_apply_q2_regs); dynamic LDS: the reflector runs
+// (3 q2_lds_stride(nmax) doubles) and the row exchange (2 x 32 x 16 doubles).
 __global__ void __launch_bounds__(256, 2) q2x_kernel(int n_clusters, const int *__restrict__ order,
                                                   const double *__restrict__ mat, const long long *__restrict__ mat_off,
                                                   double *__restrict__ vec, const long long *__restrict__ vec_off,
                                                   const int *__restrict__ dmax, const int *__restrict__ dim,
                                                   const int *__restrict__ n_orb) {
-  for (int sidx = blockIdx.x; sidx < n_clusters; sidx += gridDim.x) {
-    const int c = order[sidx];
-    const int n = dim[c];
+  extern __shared__ double q2l[];
+  for (int item = blockIdx.x; item < 2 * n_clusters; item += gridDim.x) {
+    const int c = order[item >> 1], half = item & 1;
+    const int n = dim[c], nc = n_orb[c];
     const VecLayout vl = VecLayout::make(dmax[c]);
-    double *X = vec + vec_off[c] + vl.G0;
+    double *X = vec + vec_off[c] + vl.G0 + half * nc;  // n x nc of the n x kTrack row-major block
     __syncthreads();
-    wg_apply_q2(mat + mat_off[c], n, n, X, kTrack, 2 * n_orb[c], true);
+    if (n < 3) continue;
+    wg_apply_q2_regs<true>(mat + mat_off[c], n, X, kTrack, nc, q2l, q2l + 3LL * q2_lds_stride(n));
   }
 }
 
@@ -679,24 +653,11 @@ void launch_sb2st(Plan &p) {
 }
 
 void launch_q2x(Plan &p) {
-  const int dm = cur_dim(p);
-  const size_t lds = sizeof(double) * (size_t)q2_lds_stride(dm) * (size_t)(p.mmax + 3);
-  int dev = 0, lds_max = 0;
-  const bool fits = hipGetDevice(&dev) == hipSuccess &&
-                    hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
-                    lds <= (size_t)lds_max &&
-                    hipFuncSetAttribute(reinterpret_cast<const void *>(q2x_lds_kernel),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess;
+  const size_t lds = sizeof(double) * (3 * (size_t)q2_lds_stride(cur_dim(p)) + 2 * 16 * 32);
   const int n = cur_count(p);
-  if (fits) {
-    const int grid = std::max(1, std::min(stage_grid(p, kTQ2x, 2 * p.n_cu), 2 * n));
-    hipLaunchKernelGGL(q2x_lds_kernel, dim3(grid), dim3(kWG), lds, p.stream, n, cur_order(p), p.d_mat, p.d_mat_off,
-                       p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb, dm);
-  } else {
-    const int grid = std::max(1, std::min(stage_grid(p, kTQ2x, p.workgroups), n));
-    hipLaunchKernelGGL(q2x_kernel, dim3(grid), dim3(kWG), 0, p.stream, n, cur_order(p), p.d_mat, p.d_mat_off, p.d_vec,
-                       p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb);
-  }
+  const int grid = std::max(1, std::min(stage_grid(p, kTQ2x, 2 * p.n_cu), 2 * n));
+  hipLaunchKernelGGL(q2x_kernel, dim3(grid), dim3(kWG), lds, p.stream, n, cur_order(p), p.d_mat, p.d_mat_off, p.d_vec,
+                     p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb);
 }
 
 }  // namespace ldc

@@ -192,66 +192,17 @@ __device__ void wg_apply_q1(const double *__restrict__ A, int n, const double *_
   __syncthreads();
 }
 
-// Q2, band to tridiagonal by bulge chasing.  X (n rows, ncol <= 32 columns, row-major, row stride
-// ldx) <- Q2^T X (transpose) or Q2 X for the bulge-chasing reflectors of the band-to-tridiagonal step: sweep s holds the reflectors
-// of rows [s + 1 + j b, s + 1 + j b + len), len = min(b, n - r0), b = kBand, stored in
-// column n - 1 - s of A above the diagonal at rows j b.. (tau first, then v(1:len)); the
-// steps of one sweep act on disjoint rows, so each sweep is one parallel step (16 or 32 lanes
-// per reflector, one column each), and Q2 = (sweep 0) (sweep 1) ... in that order.
-__device__ void wg_apply_q2(const double *__restrict__ A, int ld, int n, double *X, int ldx, int ncol,
-                            bool transpose) {
-  constexpr int b = kBand;
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int gsh = ncol > 16 ? 5 : 4;
-  const int grp = tid >> gsh, q = tid & ((1 << gsh) - 1), ngrp = nthr >> gsh;
-  const int nsw = n - 2;  // sweeps 0 .. n-3
-  for (int it = 0; it < nsw; ++it) {
-    const int s = transpose ? it : nsw - 1 - it;
-    const int nst = (n - 3 - s) / b + 1;
-    for (int j = grp; j < nst; j += ngrp) {
-      const int r0 = s + 1 + j * b, len = min(b, n - r0);
-      const double *vp = A + (long long)(n - 1 - s) * ld + j * b;
-      const double *xp = X + (long long)r0 * ldx + (q < ncol ? q : ncol - 1);
-      double vv[b], xv[b];
-      // clamped unconditional loads (all in flight together); entries past len are masked
-#pragma unroll
-      for (int i = 0; i < b; ++i) {
-        const int ii = min(i, len - 1);
-        const double t = vp[ii];
-        vv[i] = (i < len) ? t : 0.0;
-        xv[i] = xp[(long long)ii * ldx];
-      }
-      const double tau = vv[0];
-      vv[0] = 1.0;
-      double d = 0.0;
-#pragma unroll
-      for (int i = 0; i < b; ++i) d += vv[i] * xv[i];
-      d *= tau;
-      if (q < ncol) {
-#pragma unroll
-        for (int i = 0; i < b; ++i)
-          if (i < len) X[(long long)(r0 + i) * ldx + q] = xv[i] - d * vv[i];
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// The same product with X held in LDS (n >= 3; nc <= 16 columns, column-major: column q at
-// Xs + q P, P = q2_lds_stride(n)): the only global reads are the reflectors, one contiguous run
-// per sweep (n - 1 - s doubles of column n - 1 - s of A from row 0: per step tau, then v(1:len)),
-// fetched two sweeps ahead into registers and parked in a triple buffer of LDS (runs: 3 x P
-// doubles), one barrier per sweep.  Groups of 16 lanes take one reflector each, lane q one
-// column.  The rows n .. P - 1 of every column and the kBand entries past the end of every
-// parked run are zero, so every reflector, the last of a sweep too, runs over kBand rows with
-// no clamping or masking (its entries past the run are zero and its rows past n stay zero), and
-// every LDS offset is a lane base plus a constant.  Q2^T runs the sweeps forwards, Q2 backwards.
-// Zeroes the padding rows and starts with the run prefetch (so a fill of Xs needs no barrier of
-// its own before the call); ends with a barrier.
+// Q2, band to tridiagonal by bulge chasing: sweep s holds the reflectors of rows
+// [s + 1 + j b, s + 1 + j b + len), len = min(b, n - r0), b = kBand, stored in column n - 1 - s
+// of A above the diagonal at rows j b.. (tau first, then v(1:len)); the steps of one sweep act
+// on disjoint rows, and Q2 = (sweep 0) (sweep 1) ... in that order.  The only global reads of a
+// product with Q2 are the reflectors, one contiguous run per sweep (n - 1 - s doubles of column
+// n - 1 - s of A from row 0), fetched two sweeps ahead into registers and parked in a triple
+// buffer of LDS (3 P doubles, P = q2_lds_stride(n)) with kBand zeros past the end of every run,
+// so every reflector, the last of a sweep too, runs over kBand rows with no clamping or masking.
 constexpr int kQ2Run = (kMaxDimTri + kBand + kWG - 1) / kWG;  // run elements per thread
 
-// column stride of the LDS copy of X: at least n + kBand rows, odd (the columns of a group then
-// start in distinct banks)
+// stride of the parked runs: at least n + kBand entries
 __host__ __device__ inline int q2_lds_stride(int n) { return (n + kBand) | 1; }
 
 __device__ inline void q2_fetch_run(double *nx, const double *A, int n, int s, int tid, int nthr) {
@@ -262,88 +213,34 @@ __device__ inline void q2_fetch_run(double *nx, const double *A, int n, int s, i
   for (int u = 0; u < kQ2Run; ++u) nx[u] = src[min(tid + u * nthr, len - 1)];
 }
 
-__device__ void wg_apply_q2_lds(const double *__restrict__ A, int n, double *Xs, int nc, double *runs,
-                                bool transpose) {
-  constexpr int b = kBand;
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int grp = tid >> 4, q = tid & 15, ngrp = nthr >> 4;
-  const int P = q2_lds_stride(n);
-  const int qc = min(q, nc - 1);
-  double *xcol = Xs + (long long)qc * P;
-  const int nsw = n - 2;  // sweeps 0 .. n-3
-  auto sweep = [&](int it) { return max(0, min(transpose ? it : nsw - 1 - it, n - 3)); };
-  // a parked run: its n - 1 - s entries, then kBand zeros
-  auto park = [&](double *dst, const double *nx, int it) {
-    const int nlen = n - 1 - sweep(it);
-#pragma unroll
-    for (int u = 0; u < kQ2Run; ++u) {
-      const int e = tid + u * nthr;
-      if (e < nlen + b) dst[e] = e < nlen ? nx[u] : 0.0;
-    }
-  };
-  for (int e = tid; e < nc * (P - n); e += nthr) Xs[(long long)(e / (P - n)) * P + n + e % (P - n)] = 0.0;
-  double nx0[kQ2Run], nx1[kQ2Run];
-  q2_fetch_run(nx0, A, n, sweep(0), tid, nthr);
-  q2_fetch_run(nx1, A, n, sweep(1), tid, nthr);
-  park(runs, nx0, 0);
-  __syncthreads();
-  for (int it = 0; it < nsw; ++it) {
-    const int s = sweep(it);
-    // nx1 holds the run of the next sweep; fetch the one after
-    q2_fetch_run(nx0, A, n, sweep(it + 2), tid, nthr);
-    const double *cur = runs + (it % 3) * P;
-    const int nst = (n - 3 - s) / b + 1;
-    for (int j = grp; j < nst; j += ngrp) {
-      const int r0 = s + 1 + j * b;
-      const double *vp = cur + j * b;
-      double *xp = xcol + r0;
-      double vv[b], xv[b];
-#pragma unroll
-      for (int i = 0; i < b; ++i) {
-        vv[i] = vp[i];
-        xv[i] = xp[i];
-      }
-      const double tau = vv[0];
-      vv[0] = 1.0;
-      double d = 0.0;
-#pragma unroll
-      for (int i = 0; i < b; ++i) d += vv[i] * xv[i];
-      d *= tau;
-      if (q < nc) {
-#pragma unroll
-        for (int i = 0; i < b; ++i) xp[i] = xv[i] - d * vv[i];
-      }
-    }
-    park(runs + ((it + 1) % 3) * P, nx1, it + 1);
-#pragma unroll
-    for (int u = 0; u < kQ2Run; ++u) nx1[u] = nx0[u];
-    __syncthreads();
-  }
-}
-
-// Q2 X (not transposed) with X held in registers: X (n rows, nc <= 16 columns, row-major with
-// row stride kMaxOrb) in memory, the reflector runs parked in LDS as in wg_apply_q2_lds (runs:
-// 3 P doubles), ex: 2 x 32 x 16 doubles of LDS.  The sweeps run backwards; at sweep s the rows
+// Q2 X (FWD false) or Q2^T X (FWD true) with X held in registers: X (n >= 3 rows, nc <= 16
+// columns, row-major with row stride ldx) in memory, the reflector runs parked in LDS (runs:
+// 3 P doubles), ex: 2 x 32 x 16 doubles of LDS.  At sweep s the rows
 // s + 1 .. of X are held in windows of 32 rows, window j = rows s + 1 + 32 j .. s + 32 j + 32
-// (rows past n zero), window j in lane q of group j mod 16 (two windows per lane, j and
-// j + 16).  Step j of sweep s acts on exactly window j, so the sweep reads the 32 reflector
-// entries from LDS and touches no other memory.  From sweep s + 1 to s every window moves up by
-// one row: its last row goes to window j + 1 (through ex, double-buffered by sweep parity),
-// window 0 takes row s + 1 of X, which no later sweep has touched (fetched a sweep ahead).  The
-// windows hold rows 1.. of Q2 X at the end and go back to X (row 0 is not touched).  One barrier
-// per sweep.  Whole workgroup (256 threads); ends with a barrier.
-__device__ void wg_apply_q2_regs(const double *__restrict__ A, int n, double *X, int nc, double *runs, double *ex) {
+// (rows past n zero), window j in lane q of group j mod 16 (two windows per lane, j and j + 16).
+// Step j of sweep s acts on exactly window j, so a sweep reads its reflector entries from LDS
+// and touches no other memory.  Between sweeps every window moves by one row, and one row
+// passes from each window to its neighbour through ex (double-buffered by sweep parity): Q2^T
+// runs the sweeps forwards and the windows move down (window 0's first row is then final and
+// goes back to X), Q2 runs them backwards and the windows move up (window 0 takes row s + 1 of
+// X, which no later sweep has touched, fetched a sweep ahead).  At the end the windows go back
+// to X (row 0 is not touched).  One barrier per sweep.  Whole workgroup (256 threads); ends with
+// a barrier.
+template <bool FWD>
+__device__ void wg_apply_q2_regs(const double *__restrict__ A, int n, double *X, int ldx, int nc, double *runs,
+                                 double *ex) {
   constexpr int b = kBand;
   // the arguments are wave-uniform (out of line they arrive in vector registers)
   A = uniform_ptr(A);
   X = uniform_ptr(X);
   n = __builtin_amdgcn_readfirstlane(n);
+  ldx = __builtin_amdgcn_readfirstlane(ldx);
   nc = __builtin_amdgcn_readfirstlane(nc);
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int grp = tid >> 4, q = tid & 15;
   const int P = q2_lds_stride(n);
-  const int nsw = n - 2;  // sweeps 0 .. n-3, run from the last
-  auto sweep = [&](int it) { return max(0, min(nsw - 1 - it, n - 3)); };
+  const int nsw = n - 2;  // sweeps 0 .. n-3
+  auto sweep = [&](int it) { return max(0, min(FWD ? it : nsw - 1 - it, n - 3)); };
   auto park = [&](double *dst, const double *nx, int it) {
     const int nlen = n - 1 - sweep(it);
 #pragma unroll
@@ -352,39 +249,51 @@ __device__ void wg_apply_q2_regs(const double *__restrict__ A, int n, double *X,
       if (e < nlen + b) dst[e] = e < nlen ? nx[u] : 0.0;
     }
   };
-  const double *xc = X + min(q, nc - 1);
-  // the windows at the first sweep (s = n - 3: rows n - 2 ..)
+  double *xc = X + min(q, nc - 1);
+  const bool wr = q < nc;
+  // the windows at the first sweep
+  const int s0 = sweep(0);
   double xw[2][b];
 #pragma unroll
   for (int w = 0; w < 2; ++w)
 #pragma unroll
     for (int i = 0; i < b; ++i) {
-      const int row = n - 2 + b * (grp + 16 * w) + i;
-      const double v = xc[(long long)min(row, n - 1) * kMaxOrb];
+      const int row = s0 + 1 + b * (grp + 16 * w) + i;
+      const double v = xc[(long long)min(row, n - 1) * ldx];
       xw[w][i] = row < n ? v : 0.0;
     }
   double nx0[kQ2Run], nx1[kQ2Run];
   q2_fetch_run(nx0, A, n, sweep(0), tid, nthr);
   q2_fetch_run(nx1, A, n, sweep(1), tid, nthr);
   park(runs, nx0, 0);
-  // row s + 1 of X for the next sweep's window 0
-  double top = xc[(long long)max(sweep(1) + 1, 0) * kMaxOrb];
+  // backwards: row s + 1 of X for the next sweep's window 0
+  double top = FWD ? 0.0 : xc[(long long)(sweep(1) + 1) * ldx];
   __syncthreads();
   for (int it = 0; it < nsw; ++it) {
     const int s = sweep(it);
     q2_fetch_run(nx0, A, n, sweep(it + 2), tid, nthr);
     if (it > 0) {
-      // move every window up by one row
       const double *exr = ex + ((it - 1) & 1) * (2 * 16 * 16);
 #pragma unroll
       for (int w = 0; w < 2; ++w) {
         const int j = grp + 16 * w;
-        const double in = j == 0 ? top : exr[(j - 1) * 16 + q];
+        if (FWD) {
+          // down by one row: the first row leaves (window 0's is final: row s), the next
+          // window's first row arrives
+          if (j == 0 && wr) X[(long long)s * ldx + q] = xw[w][0];
+          const double in = j == 31 ? 0.0 : exr[(j + 1) * 16 + q];
 #pragma unroll
-        for (int i = b - 1; i > 0; --i) xw[w][i] = xw[w][i - 1];
-        xw[w][0] = in;
+          for (int i = 0; i < b - 1; ++i) xw[w][i] = xw[w][i + 1];
+          xw[w][b - 1] = in;
+        } else {
+          // up by one row: the previous window's last row arrives (window 0: row s + 1 of X)
+          const double in = j == 0 ? top : exr[(j - 1) * 16 + q];
+#pragma unroll
+          for (int i = b - 1; i > 0; --i) xw[w][i] = xw[w][i - 1];
+          xw[w][0] = in;
+        }
       }
-      top = xc[(long long)max(sweep(it + 1) + 1, 0) * kMaxOrb];
+      if (!FWD) top = xc[(long long)(sweep(it + 1) + 1) * ldx];
     }
     const double *cur = runs + (it % 3) * P;
     const int nst = (n - 3 - s) / b + 1;
@@ -406,23 +315,24 @@ __device__ void wg_apply_q2_regs(const double *__restrict__ A, int n, double *X,
         for (int i = 0; i < b; ++i) xw[w][i] -= d * vv[i];
       }
     }
-    // the last row of every window, for window j + 1 at the next sweep
+    // the row every window passes to its neighbour at the next sweep
     double *exw = ex + (it & 1) * (2 * 16 * 16);
 #pragma unroll
-    for (int w = 0; w < 2; ++w) exw[(grp + 16 * w) * 16 + q] = xw[w][b - 1];
+    for (int w = 0; w < 2; ++w) exw[(grp + 16 * w) * 16 + q] = FWD ? xw[w][0] : xw[w][b - 1];
     park(runs + ((it + 1) % 3) * P, nx1, it + 1);
 #pragma unroll
     for (int u = 0; u < kQ2Run; ++u) nx1[u] = nx0[u];
     __syncthreads();
   }
-  // rows 1 + 32 j + i
-  if (q < nc) {
+  // the windows of the last sweep
+  const int sl = sweep(nsw - 1);
+  if (wr) {
 #pragma unroll
     for (int w = 0; w < 2; ++w)
 #pragma unroll
       for (int i = 0; i < b; ++i) {
-        const int row = 1 + b * (grp + 16 * w) + i;
-        if (row < n) X[(long long)row * kMaxOrb + q] = xw[w][i];
+        const int row = sl + 1 + b * (grp + 16 * w) + i;
+        if (row < n) X[(long long)row * ldx + q] = xw[w][i];
       }
   }
   __syncthreads();
