@@ -31,7 +31,7 @@ __device__ __noinline__ void density_q2(const double *A, int n, double *r, int n
 
 // Q1 r, kept out of line for the same reason: it holds r in registers
 __device__ __noinline__ void density_q1(const double *A, int n, const double *Tq, double *r, int M, double *lds) {
-  wg_apply_q1(A, n, Tq, r, M, lds);
+  wg_apply_q1<false>(A, n, Tq, r, kMaxOrb, M, lds);
 }
 
 // x(g, a) = sum_{t >= g} Linv(t, g) r(t, a) for the rows g in [b0, n) on the FP64 matrix cores

@@ -9,8 +9,8 @@
 // All four products run on the FP64 matrix cores; only the QR of the tall-skinny panel is
 // vector code (leaves of 8 columns factored in LDS).  The reflectors stay below the band
 // (reflector k: unit at row k + b, the rest in A(k+b+1:, k)), tau in the tau vector and the
-// T factors in the compact-WY area, one b x b block per panel.  Each panel also applies its
-// block reflector to the tracked columns (X <- Q1^T X panel by panel).
+// T factors in the compact-WY area, one b x b block per panel; q2x_kernel applies Q1^T to the
+// tracked columns afterwards.
 //
 // Stage 2 (sb2st_kernel), band to tridiagonal by bulge chasing on a band array holding the
 // lower band and the bulge (2b + 1 diagonals).  Sweep s removes column s below its
@@ -23,7 +23,7 @@
 // [r0 + 1, r0 + 1 + b)) only needs steps j and j + 1 of sweep s, and at time t every sweep s with
 // j = t - 2 s in range is advanced at once, one wavefront per step.  The reflectors are kept in the strictly upper triangle of A
 // (sweep s in column n - 1 - s, rows j b..: tau first, then v(1:)); q2x_kernel then
-// forms X <- Q2^T X, sweep by sweep.
+// forms X <- Q2^T Q1^T X for the tracked columns.
 #include "wg_blas.h"
 #include "wg_qapply.h"
 
@@ -261,7 +261,7 @@ __device__ void panel_qr(double *__restrict__ A, int ld, int n, int j0, double *
 __device__ __noinline__ void band_panel(double *__restrict__ A, int ld, int n, int j0, double *__restrict__ tt,
                                         double *__restrict__ Tp, double *__restrict__ VW, double *__restrict__ VT,
                                         double *__restrict__ Kst, double *__restrict__ Gst, double *sh, double *sm,
-                                        double *red, double *__restrict__ X, int nx) {
+                                        double *red) {
   const int tid = threadIdx.x, nthr = blockDim.x;
   constexpr int b = kBand;
   const int r = j0 + b, m = n - r;
@@ -306,10 +306,6 @@ __device__ __noinline__ void band_panel(double *__restrict__ A, int ld, int n, i
   wg_gemm<G_A_RM | G_C_RM, 128, 32>(VW + b, 2 * b, VW, 2 * b, Kst, b, m, b, b, sh);
   // A22 -= V W^T + W V^T (lower triangle)
   wg_gemm<G_TRANS_B | G_LOWER | G_A_RM | G_B_RM | G_EARLY_C>(A22, ld, VW, 2 * b, VW, 2 * b, m, m, 2 * b, sh, -1, b);
-  // tracked columns, rows r..: X <- (I - V T V^T)^T X = X - V (T^T V^T X), with
-  // T^T V^T X = -(VT)^T X from the stored -V T (K free now holds it)
-  wg_atb32<true>(Kst, b, VT, b, X + (long long)r * kTrack, kTrack, m, nx, sh);
-  wg_gemm<G_A_RM | G_B_RM | G_C_RM, 128, 32>(X + (long long)r * kTrack, kTrack, VW, 2 * b, Kst, b, m, nx, b, sh);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -332,7 +328,7 @@ __global__ void __launch_bounds__(256, 2) sy2sb_kernel(int n_clusters, const int
     double *A = mat + mat_off[c];
     const VecLayout vl = VecLayout::make(dmax[c]);
     double *cv = vec + vec_off[c];
-    double *tt = cv + vl.tau, *Tq = cv + vl.u, *X = cv + vl.G0;
+    double *tt = cv + vl.tau, *Tq = cv + vl.u;
     double *VW = cv + vl.vw, *VT = cv + vl.vt, *Kst = cv + vl.kg, *Gst = Kst + b * b;
     int j0 = 0;
     for (; j0 + b < n; j0 += b) {
@@ -345,7 +341,7 @@ __global__ void __launch_bounds__(256, 2) sy2sb_kernel(int n_clusters, const int
         if (tid == 0) tt[j0] = 0.0;
         continue;
       }
-      band_panel(A, ld, n, j0, tt, Tp, VW, VT, Kst, Gst, sh, sm, red, X, 2 * M);
+      band_panel(A, ld, n, j0, tt, Tp, VW, VT, Kst, Gst, sh, sm, red);
     }
   }
 }
@@ -612,9 +608,19 @@ __global__ void __launch_bounds__(64 * kChaseWaves, 4) sb2st_kernel(int n_cluste
   }
 }
 
-// X <- Q2^T X for the tracked columns: one workgroup per half (M columns) of a cluster's 2M,
-// the rows held in register windows (wg_apply_q2_regs); dynamic LDS: the reflector runs
-// (3 q2_lds_stride(nmax) doubles) and the row exchange (2 x 32 x 16 doubles).
+// The two halves of the tracked-column product, out of line (each holds X in registers in its own
+// layout; inlined together they would share one register budget).
+__device__ __noinline__ void q1t_tracked(const double *A, int n, const double *Tq, double *X, int nc, double *lds) {
+  wg_apply_q1<true>(A, n, Tq, X, kTrack, nc, lds);
+}
+__device__ __noinline__ void q2t_tracked(const double *A, int n, double *X, int nc, double *runs, double *ex) {
+  wg_apply_q2_regs<true>(A, n, X, kTrack, nc, runs, ex);
+}
+
+// X <- Q^T X = Q2^T Q1^T X for the tracked columns: one workgroup per half (M columns) of a
+// cluster's 2M.  Q1^T on the matrix cores from the band reduction's panels and T factors
+// (wg_apply_q1), then Q2^T with the rows in register windows (wg_apply_q2_regs).  Dynamic LDS:
+// max(kQ1Lds, 3 q2_lds_stride(nmax) + 2 x 32 x 16) doubles.
 __global__ void __launch_bounds__(256, 2) q2x_kernel(int n_clusters, const int *__restrict__ order,
                                                   const double *__restrict__ mat, const long long *__restrict__ mat_off,
                                                   double *__restrict__ vec, const long long *__restrict__ vec_off,
@@ -625,10 +631,13 @@ __global__ void __launch_bounds__(256, 2) q2x_kernel(int n_clusters, const int *
     const int c = order[item >> 1], half = item & 1;
     const int n = dim[c], nc = n_orb[c];
     const VecLayout vl = VecLayout::make(dmax[c]);
-    double *X = vec + vec_off[c] + vl.G0 + half * nc;  // n x nc of the n x kTrack row-major block
+    double *cv = vec + vec_off[c];
+    double *X = cv + vl.G0 + half * nc;  // n x nc of the n x kTrack row-major block
+    const double *A = mat + mat_off[c];
     __syncthreads();
+    q1t_tracked(A, n, cv + vl.u, X, nc, q2l);
     if (n < 3) continue;
-    wg_apply_q2_regs<true>(mat + mat_off[c], n, X, kTrack, nc, q2l, q2l + 3LL * q2_lds_stride(n));
+    q2t_tracked(A, n, X, nc, q2l, q2l + 3LL * q2_lds_stride(n));
   }
 }
 
@@ -653,7 +662,7 @@ void launch_sb2st(Plan &p) {
 }
 
 void launch_q2x(Plan &p) {
-  const size_t lds = sizeof(double) * (3 * (size_t)q2_lds_stride(cur_dim(p)) + 2 * 16 * 32);
+  const size_t lds = sizeof(double) * std::max((size_t)kQ1Lds, 3 * (size_t)q2_lds_stride(cur_dim(p)) + 2 * 16 * 32);
   const int n = cur_count(p);
   const int grid = std::max(1, std::min(stage_grid(p, kTQ2x, 2 * p.n_cu), 2 * n));
   hipLaunchKernelGGL(q2x_kernel, dim3(grid), dim3(kWG), lds, p.stream, n, cur_order(p), p.d_mat, p.d_mat_off, p.d_vec,

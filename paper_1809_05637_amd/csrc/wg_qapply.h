@@ -33,8 +33,9 @@ __device__ inline T *uniform_ptr(T *p) {
   return reinterpret_cast<T *>(((unsigned long long)hi << 32) | lo);
 }
 
-// X (n rows, M <= kMaxOrb columns, row-major with row stride kMaxOrb) <- Q1 X on the FP64
-// matrix cores, panel by panel from the last:  Y = V^T X,  Y <- T Y,  X <- X - V Y.
+// X (n rows, M <= 16 columns, row-major with row stride ldx) <- Q1 X (TRANS false) or Q1^T X
+// (TRANS true) on the FP64 matrix cores, panel by panel (Q1: from the last, with T; Q1^T: from
+// the first, with T^T):  Y = V^T X,  Y <- T Y (T^T Y),  X <- X - V Y.
 // X stays in registers for the whole product: 16-row chunk c belongs to wave c mod 4 and is
 // held in the result layout of v_mfma_f64_16x16x4 (register r of lane l: X(16 c + l/16 + 4 r,
 // l % 16)).  The K steps of every product are ordered so that each operand already sits in
@@ -48,14 +49,16 @@ __device__ inline T *uniform_ptr(T *p) {
 // chunks, the chunk that holds row n - 1 and a short last panel.  The waves' partial Y meet in
 // LDS (two buffers, so one barrier per panel), and every wave forms T Y itself in the same
 // order.  Whole workgroup (4 waves); lds: kQ1Lds doubles; ends with a barrier.
-__device__ void wg_apply_q1(const double *__restrict__ A, int n, const double *__restrict__ Tq, double *X, int M,
-                            double *lds) {
+template <bool TRANS>
+__device__ void wg_apply_q1(const double *__restrict__ A, int n, const double *__restrict__ Tq, double *X, int ldx,
+                            int M, double *lds) {
   static_assert(kBand == 32 && kMaxOrb == 16, "panels of two 16-wide blocks, X one 16-wide block");
   // the arguments are wave-uniform (out of line they arrive in vector registers)
   A = uniform_ptr(A);
   Tq = uniform_ptr(Tq);
   X = uniform_ptr(X);
   n = __builtin_amdgcn_readfirstlane(n);
+  ldx = __builtin_amdgcn_readfirstlane(ldx);
   M = __builtin_amdgcn_readfirstlane(M);
   const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -64,18 +67,20 @@ __device__ void wg_apply_q1(const double *__restrict__ A, int n, const double *_
   const int nch = (n + 15) >> 4, npan = (nref + 31) >> 5;
   const unsigned n8 = 8u * (unsigned)n;
   const __amdgpu_buffer_rsrc_t av = __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(A), (short)0, (int)(n8 * n), 0x00020000);
-  const __amdgpu_buffer_rsrc_t xv = __builtin_amdgcn_make_buffer_rsrc(X, (short)0, (int)(n8 * kMaxOrb), 0x00020000);
+  const unsigned lx8 = 8u * (unsigned)ldx;
+  const __amdgpu_buffer_rsrc_t xv = __builtin_amdgcn_make_buffer_rsrc(X, (short)0, (int)(lx8 * n), 0x00020000);
   // X rows past n read zero (view size), columns M.. are sent past the view
-  const unsigned xo = li < M ? 8u * (unsigned)(kMaxOrb * lg + li) : 0x80000000u;
+  const unsigned xo = li < M ? 8u * (unsigned)(ldx * lg + li) : 0x80000000u;
   ldc_double4 x[kQ1Slots];
 #pragma unroll
   for (int j = 0; j < kQ1Slots; ++j)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) x[j][r] = view_load(xv, xo + 512u * r, 128u * 16u * (4 * j + wave));
+    for (int r = 0; r < 4; ++r) x[j][r] = view_load(xv, xo + 4u * lx8 * r, 16u * lx8 * (4 * j + wave));
   // lane offsets of the two operand layouts: V(row0 + lg + 4 r, 16 h + li) and
   // V(row0 + li, 16 h + lg + 4 r)
   const unsigned o1 = 8u * (unsigned)(li * n + lg), o2 = 8u * (unsigned)(lg * n + li);
-  for (int p = npan - 1; p >= 0; --p) {
+  for (int pi = 0; pi < npan; ++pi) {
+    const int p = TRANS ? pi : npan - 1 - pi;
     const int nbp = min(32, nref - 32 * p), cf = 2 * p + 2;
     const unsigned vb0 = 32u * p * n8;  // column 32 p
     // the wave's chunks of the panel, c = 4 j + wave in [cf, nch)
@@ -143,15 +148,18 @@ __device__ void wg_apply_q1(const double *__restrict__ A, int n, const double *_
         for (int u = 0; u < 8; ++u) va[u] = vb[u];
       }
     }
-    // T operands (T(16 g + li, 16 h + lg + 4 r); the block g = 1, h = 0 is zero)
+    // T operands of T Y: T(16 g + li, 16 h + lg + 4 r), the block g = 1, h = 0 zero; of T^T Y:
+    // T(16 h + lg + 4 r, 16 g + li), the block g = 0, h = 1 zero
     const double *Tp = Tq + (long long)p * 1024;
-    double ta[8], tb[4];
+    double ta[8], tb[8];
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) ta[4 * h + r] = Tp[li * 32 + 16 * h + lg + 4 * r];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) tb[r] = Tp[(16 + li) * 32 + 16 + lg + 4 * r];
+      for (int r = 0; r < 4; ++r) {
+        const int k = 16 * h + lg + 4 * r;
+        ta[4 * h + r] = TRANS ? (h == 0 ? Tp[k * 32 + li] : 0.0) : Tp[li * 32 + k];
+        tb[4 * h + r] = TRANS ? Tp[k * 32 + 16 + li] : (h == 1 ? Tp[(16 + li) * 32 + k] : 0.0);
+      }
     double *Yb = lds + (p & 1) * 2048;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -159,13 +167,13 @@ __device__ void wg_apply_q1(const double *__restrict__ A, int n, const double *_
       Yb[wave * 512 + (4 + r) * 64 + lane] = y1[r];
     }
     __syncthreads();
-    // Y summed over the waves in a fixed order, then T Y: z0 = rows 0..15, z1 = rows 16..31
+    // Y summed over the waves in a fixed order, then T Y (T^T Y): z0 = rows 0..15, z1 = rows 16..31
     ldc_double4 z0 = {0.0, 0.0, 0.0, 0.0}, z1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const double ys = ((Yb[u * 64 + lane] + Yb[512 + u * 64 + lane]) + Yb[1024 + u * 64 + lane]) + Yb[1536 + u * 64 + lane];
-      z0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ta[u], ys, z0, 0, 0, 0);
-      if (u >= 4) z1 = __builtin_amdgcn_mfma_f64_16x16x4f64(tb[u - 4], ys, z1, 0, 0, 0);
+      if (!TRANS || u < 4) z0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ta[u], ys, z0, 0, 0, 0);
+      if (TRANS || u >= 4) z1 = __builtin_amdgcn_mfma_f64_16x16x4f64(tb[u], ys, z1, 0, 0, 0);
     }
     // X <- X - V (T Y)
     if (jlo <= jhi) load2(va, 4 * jlo + wave);
@@ -188,7 +196,7 @@ __device__ void wg_apply_q1(const double *__restrict__ A, int n, const double *_
 #pragma unroll
   for (int j = 0; j < kQ1Slots; ++j)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) view_store(xv, x[j][r], xo + 512u * r, 128u * 16u * (4 * j + wave));
+    for (int r = 0; r < 4; ++r) view_store(xv, x[j][r], xo + 4u * lx8 * r, 16u * lx8 * (4 * j + wave));
   __syncthreads();
 }
 
