@@ -21,7 +21,7 @@ namespace ldc {
 // Q2 r, then the partial products of Q1 r
 constexpr int kDensityLds = std::max(4 * kMaxDimTri + (kMaxDimTri + 1) / 2, kQ1Lds);
 // the Q2 product's three reflector runs and its row exchange fit the same area
-static_assert(3 * ((kMaxDimTri + kBand) | 1) + 2 * 16 * 32 <= kDensityLds, "Q2 runs and exchange");
+static_assert(3 * ((kMaxDimTri + kBand + 1) & ~1) + 2 * 16 * 32 <= kDensityLds, "Q2 runs and exchange");
 
 // Q2 r with the rows of r held in registers, kept out of line: inlined into the density kernel it
 // raises the register pressure of the whole kernel and spills

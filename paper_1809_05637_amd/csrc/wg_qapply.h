@@ -210,8 +210,9 @@ __device__ void wg_apply_q1(const double *__restrict__ A, int n, const double *_
 // so every reflector, the last of a sweep too, runs over kBand rows with no clamping or masking.
 constexpr int kQ2Run = (kMaxDimTri + kBand + kWG - 1) / kWG;  // run elements per thread
 
-// stride of the parked runs: at least n + kBand entries
-__host__ __device__ inline int q2_lds_stride(int n) { return (n + kBand) | 1; }
+// stride of the parked runs: at least n + kBand entries, even (every run and every step's
+// reflector start on a 16-byte boundary, so the reflector entries are read in pairs)
+__host__ __device__ inline int q2_lds_stride(int n) { return (n + kBand + 1) & ~1; }
 
 __device__ inline void q2_fetch_run(double *nx, const double *A, int n, int s, int tid, int nthr) {
   // run of sweep s (clamped unconditional loads; a sweep outside 0..n-3 reads its nearest)
@@ -309,10 +310,15 @@ __device__ void wg_apply_q2_regs(const double *__restrict__ A, int n, double *X,
     for (int w = 0; w < 2; ++w) {
       const int j = grp + 16 * w;
       if (j < nst) {
-        const double *vp = cur + j * b;
+        typedef __attribute__((ext_vector_type(2))) double dpair;
+        const dpair *vp = reinterpret_cast<const dpair *>(cur + j * b);
         double vv[b];
 #pragma unroll
-        for (int i = 0; i < b; ++i) vv[i] = vp[i];
+        for (int i = 0; i < b / 2; ++i) {
+          const dpair t = vp[i];
+          vv[2 * i] = t.x;
+          vv[2 * i + 1] = t.y;
+        }
         const double tau = vv[0];
         vv[0] = 1.0;
         double d4[4] = {0.0, 0.0, 0.0, 0.0};
