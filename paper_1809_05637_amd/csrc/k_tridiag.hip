@@ -20,10 +20,12 @@
 // creates the next bulge), then forms the next reflector from that block and applies it from
 // the left to the rest of the block.  Everything step j reads or writes lies in the columns
 // [r0, r0 + b) of the band (column s too for j = 0), so step j of sweep s + 1 (columns
-// [r0 + 1, r0 + 1 + b)) only needs steps j and j + 1 of sweep s, and at time t every sweep s with
-// j = t - 2 s in range is advanced at once, one wavefront per step.  The reflectors are kept in the strictly upper triangle of A
-// (sweep s in column n - 1 - s, rows j b..: tau first, then v(1:)); q2x_kernel then
-// forms X <- Q2^T Q1^T X for the tracked columns.
+// [r0 + 1, r0 + 1 + b)) only needs steps j and j + 1 of sweep s.  One wavefront runs two sweeps
+// (2p, 2p + 1), step j of the second right after step j + 1 of the first, the second sweep's
+// window taken from the first's in registers (one window loaded and one stored per two steps);
+// pairs of sweeps are pipelined across the wavefronts of the workgroup.  The reflectors are kept
+// in the strictly upper triangle of A (sweep s in column n - 1 - s, rows j b..: tau first, then
+// v(1:)); q2x_kernel then forms X <- Q2^T Q1^T X for the tracked columns.
 #include "wg_blas.h"
 #include "wg_qapply.h"
 
@@ -389,10 +391,8 @@ constexpr unsigned kBandOob = 0x80000000u;
 // halves, the lane offset in a register and the window in a scalar register.  Only entries that
 // exist are fetched: D on and below the diagonal inside the window, R rows and columns inside the
 // matrix; the other lanes are sent past the end of the buffer and read zero (the D part above the
-// diagonal is taken from the tile later).  x is B(s + 1 + lane mod 32, s), column s below its
-// diagonal (used by step 0 only).
-__device__ inline void chase_fetch(__amdgpu_buffer_rsrc_t band, double (&row)[kBand], double &x, int n, int s,
-                                   int j) {
+// diagonal is taken from the tile later).
+__device__ inline void chase_fetch(__amdgpu_buffer_rsrc_t band, double (&row)[kBand], int n, int s, int j) {
   constexpr unsigned LB = kBandLd, LD1 = kBandLd - 1;
   const unsigned lane = threadIdx.x & 63u;
   const unsigned vl = lane * 8u;
@@ -401,13 +401,17 @@ __device__ inline void chase_fetch(__amdgpu_buffer_rsrc_t band, double (&row)[kB
   const unsigned in_win = len >= 32 ? 0xFFFFFFFFu : ((1u << len) - 1u);
   const unsigned in_r = nr >= 32 ? 0xFFFFFFFFu : ((1u << nr) - 1u);
   const unsigned base = (unsigned)r0 * LB * 8u;
-  const unsigned cs = __builtin_amdgcn_readfirstlane((unsigned)s * LB * 8u);
 #pragma unroll
   for (int k = 0; k < kBand; ++k) {
     const unsigned long long keep = lane_mask((0xFFFFFFFFu << k) & in_win, k < len ? in_r : 0u);
     row[k] = band_load(band, lane_select(keep, kBandOob, vl) + (unsigned)k * LD1 * 8u, base);
   }
-  x = band_load(band, (1u + (lane & 31u)) * 8u, cs);
+}
+
+// B(s + 1 + lane mod 32, s), column s below its diagonal (the input of step 0 of sweep s).
+__device__ inline double chase_column(__amdgpu_buffer_rsrc_t band, int s) {
+  const unsigned cs = __builtin_amdgcn_readfirstlane((unsigned)s * kBandLd * 8u);
+  return band_load(band, (1u + (threadIdx.x & 31u)) * 8u, cs);
 }
 
 // One bulge step (sweep s, step j) by one wavefront, on the rows chase_fetch loaded.  The
@@ -420,16 +424,15 @@ __device__ inline void chase_fetch(__amdgpu_buffer_rsrc_t band, double (&row)[kB
 //       beta e_0, stores it (A's upper triangle and the slot), and
 //   (b) applies H_{j+1} from the left to the other columns of R.
 // (a) and (b) belong to step j + 1 of the sweep; nothing else touches R between the two
-// steps, so they run here while R is still in registers and every step moves its window
-// through memory once.  The D rows take their part above the diagonal from the tile (wt:
-// kBand x (kBand + 1) doubles of the wave's LDS; wsv: kBand doubles; slot: kBand + 1 doubles of
-// the sweep).  Rows past the matrix hold zeros throughout (they read zeros, and v, w, p and v1
-// are zero on them).  D and R rows are stored together at the end, one store per k: the lanes
-// of entries above the diagonal or outside the matrix are sent past the end of the buffer.
+// steps, so they run here while R is still in registers.  The D rows take their part above the
+// diagonal from the tile (wt: kBand x (kBand + 1) doubles of the wave's LDS; wsv: kBand doubles;
+// slot: kBand + 1 doubles of the sweep) and leave the step as full symmetric rows.  Rows past
+// the matrix hold zeros throughout (they read zeros, and v, w, p and v1 are zero on them); so do
+// the columns past the matrix.  The caller stores the window (chase_store).
 __device__ void bulge_step(__amdgpu_buffer_rsrc_t band, double (&row)[kBand], double x, double *__restrict__ A,
                            int ld, int n, int s, int j, double *slot, double *wsv, double *wt) {
   constexpr int b = kBand, TS = kBand + 1;
-  constexpr unsigned LB = kBandLd, LD1 = kBandLd - 1;
+  constexpr unsigned LB = kBandLd;
   // the lane index and (s, j) through opaque moves: keeps the compiler from hoisting the
   // per-lane addresses of the fully unrolled loops below out of the time loop
   int tx;
@@ -443,8 +446,6 @@ __device__ void bulge_step(__amdgpu_buffer_rsrc_t band, double (&row)[kBand], do
   const int r0 = s + 1 + j * b, len = min(b, n - r0), r1 = r0 + len;
   const int nr = min(b, n - r1);  // rows of R (0 on the last step of a sweep)
   const bool isRow = lo && i < len, isR = !lo && i < nr;
-  const unsigned vl = (unsigned)lane * 8u;       // lane part of every byte offset
-  const unsigned base = (unsigned)r0 * LB * 8u;  // the step's window
   double *vs = slot + 1;
   double tau, v;
   if (j == 0) {
@@ -539,33 +540,131 @@ __device__ void bulge_step(__amdgpu_buffer_rsrc_t band, double (&row)[kBand], do
       for (int c = 1; c < b; ++c) row[c] -= v1 * wsv[c];
     }
   }
-  // D rows on and below the diagonal inside the window, and the R rows and columns inside the
-  // matrix, one store per k
+}
+
+// What chase_store writes of a step's window.
+enum ChaseStore {
+  kStoreAll = 0,      // D rows on and below the diagonal inside the window, R rows and columns inside the matrix
+  kStoreDiag = 1,     // only the diagonal entry of the window's first column
+  kStoreCol0Tail = 2, // only the first column's R entries past the first R row
+  kStoreAllButCol0 = 3  // every column but the first, and the first column's R entries past the first R row
+};
+
+// Stores the window of step (s, j) from the rows (D rows on lanes 0..31, R rows on lanes
+// 32..63), one store per column; the lanes of entries that are not written are sent past the end
+// of the buffer.
+__device__ inline void chase_store(__amdgpu_buffer_rsrc_t band, const double (&row)[kBand], int n, int s, int j,
+                                   int mode) {
+  constexpr unsigned LB = kBandLd, LD1 = kBandLd - 1;
+  const unsigned vl = (threadIdx.x & 63u) * 8u;
+  n = __builtin_amdgcn_readfirstlane(n);
+  mode = __builtin_amdgcn_readfirstlane(mode);
+  const int r0 = __builtin_amdgcn_readfirstlane(s + 1 + j * kBand);
+  const int len = min(kBand, n - r0), nr = max(0, min(kBand, n - r0 - len));
   const unsigned in_win = len >= 32 ? 0xFFFFFFFFu : ((1u << len) - 1u);
-  const unsigned in_r = nr >= 32 ? 0xFFFFFFFFu : ((1u << max(nr, 0)) - 1u);
+  const unsigned in_r = nr >= 32 ? 0xFFFFFFFFu : ((1u << nr) - 1u);
+  const unsigned base = (unsigned)r0 * LB * 8u;
+  const unsigned c0lo = __builtin_amdgcn_readfirstlane(mode == kStoreAll ? 0xFFFFFFFFu : (mode == kStoreDiag ? 1u : 0u));
+  const unsigned c0hi =
+      __builtin_amdgcn_readfirstlane(mode == kStoreAll ? 0xFFFFFFFFu : (mode == kStoreDiag ? 0u : 0xFFFFFFFEu));
+  const bool rest = mode == kStoreAll || mode == kStoreAllButCol0;
+  band_store(band, row[0], lane_select(lane_mask(in_win & c0lo, in_r & c0hi), kBandOob, vl), base);
+  if (rest) {
 #pragma unroll
-  for (int k = 0; k < b; ++k) {
-    const unsigned long long keep = lane_mask((0xFFFFFFFFu << k) & in_win, k < len ? in_r : 0u);
-    band_store(band, row[k], lane_select(keep, kBandOob, vl) + (unsigned)k * LD1 * 8u, base);
+    for (int k = 1; k < kBand; ++k) {
+      const unsigned long long keep = lane_mask((0xFFFFFFFFu << k) & in_win, k < len ? in_r : 0u);
+      band_store(band, row[k], lane_select(keep, kBandOob, vl) + (unsigned)k * LD1 * 8u, base);
+    }
   }
 }
 
-// Sweeps in flight at one time step: at most ceil(steps / 2) <= 15 (n <= kMaxDimTri), so 16
-// slots indexed by s mod 16 are never shared by two live sweeps.
-constexpr int kSweepSlots = 16;
-// Wavefronts per chase workgroup: about n / 64 sweeps are in flight at a time step, and more
-// waves per cluster hide the latency of each step without adding clusters in flight.
-constexpr int kChaseWaves = 8;
-static_assert(2 * kSweepSlots > (kMaxDimTri - 3) / kBand + 1, "sweep slots");
+// Wavefronts per chase workgroup, each running one pair of sweeps at a time, and waves per SIMD
+// (a wave holds two windows, 195 VGPRs).  Two waves per cluster and four clusters per CU beat
+// four or eight waves per cluster with fewer clusters in flight (the steps are latency-bound).
+#ifndef LDC_CHASE_WAVES
+#define LDC_CHASE_WAVES 2
+#endif
+constexpr int kChaseWaves = LDC_CHASE_WAVES;
+constexpr int kChaseOcc = 2;
+constexpr int kMaxPairs = (kMaxDimTri - 1) / 2;  // sweeps 0 .. n - 3 taken two at a time
 
-__global__ void __launch_bounds__(64 * kChaseWaves, 4) sb2st_kernel(int n_clusters, const int *__restrict__ order,
+// The last pair time of the pair of sweeps (2p, 2p + 1), counted from the pair's start: the
+// second sweep's step j runs at pair time j + 1; a lone last sweep ends at its own last step.
+__device__ inline int pair_last(int n, int p) {
+  const int s = 2 * p;
+  return s + 1 <= n - 3 ? sweep_steps(n, s + 1) : sweep_steps(n, s) - 1;
+}
+
+// Pair time tau of the sweeps s = 2p and s + 1 on one wavefront: step (s, tau), then step
+// (s + 1, tau - 1), which needs (s, tau) and nothing later.  The window of (s + 1, tau - 1) is
+// that of (s, tau - 1) moved down and right by one: its rows and columns 0 .. b - 2 are the
+// rows 1 .. and columns 1 .. of the first sweep's previous window (P, kept in registers), its
+// last column is the first column of (s, tau)'s window, and its last row is zero left of that
+// column (the sweeps before s annihilated those entries).  So only the first sweep's windows are
+// loaded and only the second sweep's are stored, except what no later step of the second sweep
+// covers: the diagonal entry of column s + 1 (tau = 0), the first column's entries past the
+// first R row (zeros after the annihilation), and the whole last window of the first sweep when
+// the second ends a step earlier.  A lone last sweep stores its windows itself.
+__device__ inline void chase_pair(__amdgpu_buffer_rsrc_t band, double (&P)[kBand], double *__restrict__ A, int ld,
+                                  int n, int p, int tau, double *slot0, double *slot1, double *wsv, double *wt) {
+  constexpr unsigned LB = kBandLd;
+  const int lane = threadIdx.x & 63;
+  n = __builtin_amdgcn_readfirstlane(n);
+  p = __builtin_amdgcn_readfirstlane(p);
+  tau = __builtin_amdgcn_readfirstlane(tau);
+  const int s = 2 * p;
+  const bool solo = s + 1 > n - 3;
+  const int J0 = sweep_steps(n, s), J1 = solo ? 0 : sweep_steps(n, s + 1);
+  const bool first = tau < J0;
+  double C[kBand];
+  if (first) {
+    chase_fetch(band, C, n, s, tau);
+    const double x = tau == 0 ? chase_column(band, s) : 0.0;
+    bulge_step(band, C, x, A, ld, n, s, tau, slot0, wsv, wt);
+    chase_store(band, C, n, s, tau,
+                solo ? kStoreAll : (tau == 0 ? kStoreDiag : (tau == J0 - 1 && J1 <= tau ? kStoreAllButCol0 : kStoreCol0Tail)));
+  }
+  if (tau >= 1 && tau - 1 < J1) {
+    // column r0c = s + 1 + tau b from its diagonal down, on lanes 0 .. b
+    const int r0c = s + 1 + tau * kBand;
+    double c0 = 0.0;
+    if (first)
+      c0 = C[0];
+    else if (r0c <= n - 1)
+      c0 = band_load(band, lane <= kBand ? (unsigned)lane * 8u : kBandOob, (unsigned)r0c * LB * 8u);
+    // step 0 of sweep s + 1 takes column s + 1 below its diagonal: P's first column, one row down
+    const double x1 = __shfl_down(P[0], 1, 64);
+#pragma unroll
+    for (int k = 0; k < kBand - 1; ++k) {
+      const double v = __shfl_down(P[k + 1], 1, 64);
+      P[k] = lane == 63 ? 0.0 : v;
+    }
+    const double v = __shfl(c0, max(lane - (kBand - 1), 0), 64);
+    P[kBand - 1] = lane >= kBand - 1 ? v : 0.0;
+    bulge_step(band, P, x1, A, ld, n, s + 1, tau - 1, slot1, wsv, wt);
+    chase_store(band, P, n, s + 1, tau - 1, kStoreAll);
+  }
+  if (first) {
+#pragma unroll
+    for (int k = 0; k < kBand; ++k) P[k] = C[k];
+  }
+}
+
+// Bulge chasing of one cluster per workgroup.  Sweeps go in pairs (2p, 2p + 1), pair p on wave
+// p mod nw; pair p starts at pair time T_p = max(T_{p-1} + 3, T_{p-nw} + last(p - nw) + 1): step
+// (2p, tau) needs (2p - 1, tau + 1), which the previous pair runs at its pair time tau + 2, and a
+// wave takes its next pair only after the last one ends.  Every step of pair time T then touches
+// columns no other step of T touches, and a barrier ends each pair time.
+__global__ void __launch_bounds__(64 * kChaseWaves, kChaseOcc) sb2st_kernel(int n_clusters, const int *__restrict__ order,
                                                     double *__restrict__ mat, const long long *__restrict__ mat_off,
                                                     double *__restrict__ vec, const long long *__restrict__ vec_off,
                                                     const int *__restrict__ dmax, const int *__restrict__ dim) {
   __shared__ double wsv[kChaseWaves][kBand];
   __shared__ double wtile[kChaseWaves][kBand * (kBand + 1)];
-  __shared__ double slots[kSweepSlots][kBand + 1];
-  // the wave index in a scalar register: the sweep numbers and band offsets derived from it are
+  __shared__ double slots[kChaseWaves][2][kBand + 1];
+  __shared__ int tstart[kMaxPairs];
+  __shared__ int tlast;
+  // the wave index in a scalar register: the pair numbers and band offsets derived from it are
   // wave-uniform (buffer offsets in vector registers would need a loop over lanes)
   const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), nthr = blockDim.x, nw = nthr >> 6;
   constexpr int LB = kBandLd;
@@ -580,24 +679,37 @@ __global__ void __launch_bounds__(64 * kChaseWaves, 4) sb2st_kernel(int n_cluste
     // <= 3 kBand dmax doubles)
     double *Bd = cv + vl.vw;
     Bd += (16 - (int)((reinterpret_cast<unsigned long long>(Bd) >> 3) & 15)) & 15;
+    const int npairs = n >= 3 ? (n - 1) / 2 : 0;
     __syncthreads();
     for (long long e = tid; e < (long long)n * LB; e += nthr) {
       const int cc = (int)(e / LB), d = (int)(e % LB);
       Bd[e] = (d <= kBand && cc + d < n) ? A[(long long)cc * ld + cc + d] : 0.0;
     }
+    if (tid == 0) {
+      int tl = -1;
+      for (int q = 0; q < npairs; ++q) {
+        int t = q == 0 ? 0 : tstart[q - 1] + 3;
+        if (q >= nw) t = max(t, tstart[q - nw] + pair_last(n, q - nw) + 1);
+        tstart[q] = t;
+        tl = max(tl, t + pair_last(n, q));
+      }
+      tlast = tl;
+    }
     __syncthreads();
     // raw buffer view of the band array (word 3: the gfx9 buffer format for untyped access)
     const __amdgpu_buffer_rsrc_t band = __builtin_amdgcn_make_buffer_rsrc(Bd, (short)0, n * LB * 8, 0x00020000);
-    // time step t advances every sweep s with j = t - 2 s in range; sweep s runs on wave s mod nw
-    const int tend = 2 * (n - 3);
+    const int tend = tlast;
+    int p = wave;
+    double P[kBand];
+#pragma unroll
+    for (int k = 0; k < kBand; ++k) P[k] = 0.0;
     for (int t = 0; t <= tend; ++t) {
-      const int shi = min(t / 2, n - 3);
-      for (int s = shi >= wave ? wave + (shi - wave) / nw * nw : -1; s >= 0; s -= nw) {
-        const int j = t - 2 * s;
-        if (j >= sweep_steps(n, s)) break;
-        double row[kBand], x;
-        chase_fetch(band, row, x, n, s, j);
-        bulge_step(band, row, x, A, ld, n, s, j, slots[s % kSweepSlots], wsv[wave], wtile[wave]);
+      if (p < npairs) {
+        const int tau = t - __builtin_amdgcn_readfirstlane(tstart[p]);
+        if (tau >= 0) {
+          chase_pair(band, P, A, ld, n, p, tau, slots[wave][0], slots[wave][1], wsv[wave], wtile[wave]);
+          if (tau == pair_last(n, p)) p += nw;
+        }
       }
       __syncthreads();
     }
@@ -652,11 +764,9 @@ void launch_sy2sb(Plan &p) {
 }
 
 void launch_sb2st(Plan &p) {
-  // default two workgroups per compute unit: more clusters in flight push the bands out of the
-  // caches (measured with four waves per workgroup: 1, 1.5, 2 and 4 per CU give 190, 154, 133
-  // and 149 ms on the 3920-atom slab; eight waves at 2 per CU: 122 ms)
+  // default: as many workgroups as are resident (kChaseOcc waves per SIMD)
   const int n = cur_count(p);
-  const int grid = std::max(1, std::min(stage_grid(p, kTSb2st, p.workgroups), n));
+  const int grid = std::max(1, std::min(stage_grid(p, kTSb2st, p.n_cu * 4 * kChaseOcc / kChaseWaves), n));
   hipLaunchKernelGGL(sb2st_kernel, dim3(grid), dim3(64 * kChaseWaves), 0, p.stream, n, cur_order(p), p.d_mat,
                      p.d_mat_off, p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim);
 }
