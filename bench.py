@@ -69,21 +69,54 @@ def sb2st_min_bytes(dims, b=32):
 
 
 def sb2st_design_bytes(dims, b=32):
-    """Bytes this design's chase moves when every window goes through memory: every step of
-    every sweep reads and writes its window once (the lower triangle of the len x len diagonal
-    block and the nr x len block below it) and writes its reflector (len doubles).  Sweep s,
-    step j: r0 = s + 1 + j b, len = min(b, d - r0), nr = min(b, d - r0 - len), steps while
-    r0 <= d - 2."""
+    """Bytes this design's chase moves through memory.  Sweeps go in pairs (s, s + 1), s even, on
+    one wavefront: the first sweep's steps read their windows (the lower triangle of the len x len
+    diagonal block and the nr x len block below it), the second sweep's steps write theirs (its
+    windows are formed in registers from the first sweep's), and every step writes its reflector
+    (len doubles).  The first sweep also writes the diagonal entry of column s + 1 (step 0), the
+    first column's entries past the first R row (nr - 1, later steps) and, when the second sweep has
+    one step fewer, its last window but the first column; the second sweep reads the first column
+    of a window the first sweep does not reach (at most b + 1 doubles).  A lone last sweep reads
+    and writes its windows.  Sweep s, step j: r0 = s + 1 + j b, len = min(b, d - r0),
+    nr = min(b, d - r0 - len), steps while r0 <= d - 2.  Step 0's column s (32 doubles read, 32
+    written) is left out."""
+    def steps(n, s):
+        return 0 if s > n - 3 else (n - 3 - s) // b + 1
+
+    def window(n, s, j):
+        r0 = s + 1 + j * b
+        ln = min(b, n - r0)
+        nr = max(0, min(b, n - r0 - ln))
+        return ln, nr, ln * (ln + 1) // 2 + nr * ln
+
     total = 0.0
     for n in np.unique(dims):
+        n = int(n)
         cnt = int(np.sum(dims == n))
-        per = 0.0
-        for s in range(0, n - 2):
-            r0 = np.arange(s + 1, n - 1, b, dtype=np.float64)
-            ln = np.minimum(b, n - r0)
-            nr = np.clip(n - r0 - ln, 0, b)
-            per += float(np.sum(8.0 * (ln * (ln + 1) + 2.0 * nr * ln + ln)))
-        total += cnt * per
+        per = 0
+        for s in range(0, n - 2, 2):
+            J0, J1 = steps(n, s), steps(n, s + 1)
+            if s + 1 > n - 3:
+                for j in range(J0):
+                    ln, nr, win = window(n, s, j)
+                    per += 2 * win + ln
+                continue
+            for j in range(J0):
+                ln, nr, win = window(n, s, j)
+                per += win + ln
+                if j == 0:
+                    per += 1
+                elif j == J0 - 1 and J1 <= j:
+                    per += win - (ln + nr) + max(nr - 1, 0)
+                else:
+                    per += max(nr - 1, 0)
+            for j in range(J1):
+                ln, nr, win = window(n, s + 1, j)
+                per += win + ln
+                r0c = s + 1 + (j + 1) * b
+                if j + 1 >= J0 and r0c <= n - 1:
+                    per += min(b + 1, n - r0c)
+        total += cnt * 8.0 * per
     return total
 
 
@@ -680,7 +713,8 @@ def build_bench(s, args, log, H, S, plan, stream, rule, use_lno):
                 "ms_per_launch": round(per_stage[dom], 3), "algorithmic_bytes": alg,
                 "algorithmic": "lower band read once + reflectors, diagonal and off-diagonal written once",
                 "design_traffic": sb2st_design_bytes(dims),
-                "design_traffic_note": "every bulge window read and written once per step (this design's chase)"}
+                "design_traffic_note": "sweeps in pairs on one wavefront: the first sweep's windows read, the "
+                                       "second's written, reflectors written (this design's chase)"}
     elif dom in work:
         achieved = work[dom] / (per_stage[dom] * 1e-3) / 1e12
         roof = {"kernel": kern, "bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
@@ -691,6 +725,15 @@ def build_bench(s, args, log, H, S, plan, stream, rule, use_lno):
         roof = {"kernel": kern, "bound": "alu", "achieved": None, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": None, "traffic": None, "ms_per_launch": round(per_stage[dom], 3)}
     roof["measured"] = "HIP events around the kernel on the plan's stream, eager builds of the same work"
+    # the bulge chase against HBM whichever stage dominates: the method's minimum bytes and this
+    # design's window traffic, per launch
+    chase = None
+    if per_stage.get("sb2st", 0.0) > 0:
+        cmin, cdes = sb2st_min_bytes(dims), sb2st_design_bytes(dims)
+        chase = {"kernel": "sb2st_kernel", "ms_per_launch": round(per_stage["sb2st"], 3), "min_bytes": cmin,
+                 "min_gbs": round(cmin / (per_stage["sb2st"] * 1e-3) / 1e9, 2), "design_bytes": cdes,
+                 "design_gbs": round(cdes / (per_stage["sb2st"] * 1e-3) / 1e9, 2),
+                 "traffic": stored_traffic("sb2st_kernel", s["name"])}
     # the eigensolve as a whole (Cholesky .. divide-and-conquer) against the FP64 peak: executed
     # flops, and the tridiagonalization (band reduction + chase) against its LAPACK count
     eig_ms = sum(per_stage.get(k, 0.0) for k in ("potrf", "sygst", "sy2sb", "sb2st", "q2x", "stedc"))
@@ -734,6 +777,7 @@ def build_bench(s, args, log, H, S, plan, stream, rule, use_lno):
         },
         "stage_ms": {k: round(v, 3) for k, v in per_stage.items()},
         "roofline": roof,
+        "bulge_chase": chase,
         "eigensolve": eig,
         "accuracy": {"n_e_from_D": ne_b, "n_electrons": s["n_electrons"], "mu": mu_b,
                      "e_band_per_atom": eb_b / s["n_atoms"]},
