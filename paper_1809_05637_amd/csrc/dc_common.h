@@ -106,6 +106,10 @@ __device__ __noinline__ void dc_apply_rows_mfma(int n, int span, int ny, const i
   n = __builtin_amdgcn_readfirstlane(n);
   span = __builtin_amdgcn_readfirstlane(span);
   ny = __builtin_amdgcn_readfirstlane(ny);
+  cnt = global_ptr(cnt);
+  kpos = global_ptr(kpos);
+  yb = global_ptr(yb);
+  ya = global_ptr(ya);
   // the secular data lives in LDS: address it as such (out of line the pointers are generic)
   typedef __attribute__((address_space(3))) const double lds_double;
   typedef __attribute__((address_space(3))) const int lds_int;

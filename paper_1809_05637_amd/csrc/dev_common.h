@@ -7,6 +7,24 @@
 
 namespace ldc {
 
+// Out of line, a device function receives generic pointers and addresses them with flat
+// instructions, which also count against the LDS counter (so a wait for an LDS read waits for
+// outstanding memory loads too).  These restate where a pointer points (global memory or LDS), so
+// that its accesses compile to global or ds instructions.  Only for pointers known to point there.
+// The typed pointer is rebuilt from the address (an LDS pointer's flat address holds its LDS
+// offset in the low half), so that only one cast, to generic, remains for the compiler to see
+// through.
+template <typename T>
+__device__ inline T *global_ptr(T *p) {
+  typedef __attribute__((address_space(1))) T gT;
+  return (T *)(gT *)reinterpret_cast<unsigned long long>(p);
+}
+template <typename T>
+__device__ inline T *lds_ptr(T *p) {
+  typedef __attribute__((address_space(3))) T lT;
+  return (T *)(lT *)(unsigned)reinterpret_cast<unsigned long long>(p);
+}
+
 // First error wins; later errors are dropped.
 __device__ inline void report(DevStatus *st, int code, int where) {
   if (atomicCAS(&st->code, 0, code) == 0) atomicExch(&st->where, where);

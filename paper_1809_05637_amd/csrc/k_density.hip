@@ -45,9 +45,9 @@ __device__ __noinline__ void density_q1(const double *A, int n, const double *Tq
 __device__ __noinline__ void density_lt(const double *__restrict__ L, int ld, int n, int b0, const double *__restrict__ r,
                                         double *__restrict__ x, int M) {
   // the arguments are wave-uniform (out of line they arrive in vector registers)
-  L = uniform_ptr(L);
-  r = uniform_ptr(r);
-  x = uniform_ptr(x);
+  L = global_ptr(uniform_ptr(L));
+  r = global_ptr(uniform_ptr(r));
+  x = global_ptr(uniform_ptr(x));
   ld = __builtin_amdgcn_readfirstlane(ld);
   n = __builtin_amdgcn_readfirstlane(n);
   b0 = __builtin_amdgcn_readfirstlane(b0);

@@ -264,6 +264,21 @@ __device__ __noinline__ void band_panel(double *__restrict__ A, int ld, int n, i
                                         double *__restrict__ Tp, double *__restrict__ VW, double *__restrict__ VT,
                                         double *__restrict__ Kst, double *__restrict__ Gst, double *sh, double *sm,
                                         double *red) {
+  // out of line: the matrix and workspace pointers are wave-uniform and point to global memory,
+  // sh, sm and red to LDS
+  A = global_ptr(uniform_ptr(A));
+  tt = global_ptr(uniform_ptr(tt));
+  Tp = global_ptr(uniform_ptr(Tp));
+  VW = global_ptr(uniform_ptr(VW));
+  VT = global_ptr(uniform_ptr(VT));
+  Kst = global_ptr(uniform_ptr(Kst));
+  Gst = global_ptr(uniform_ptr(Gst));
+  sh = lds_ptr(sh);
+  sm = lds_ptr(sm);
+  red = lds_ptr(red);
+  ld = __builtin_amdgcn_readfirstlane(ld);
+  n = __builtin_amdgcn_readfirstlane(n);
+  j0 = __builtin_amdgcn_readfirstlane(j0);
   const int tid = threadIdx.x, nthr = blockDim.x;
   constexpr int b = kBand;
   const int r = j0 + b, m = n - r;

@@ -54,9 +54,10 @@ __device__ void wg_apply_q1(const double *__restrict__ A, int n, const double *_
                             int M, double *lds) {
   static_assert(kBand == 32 && kMaxOrb == 16, "panels of two 16-wide blocks, X one 16-wide block");
   // the arguments are wave-uniform (out of line they arrive in vector registers)
-  A = uniform_ptr(A);
-  Tq = uniform_ptr(Tq);
-  X = uniform_ptr(X);
+  A = global_ptr(uniform_ptr(A));
+  Tq = global_ptr(uniform_ptr(Tq));
+  X = global_ptr(uniform_ptr(X));
+  lds = lds_ptr(lds);
   n = __builtin_amdgcn_readfirstlane(n);
   ldx = __builtin_amdgcn_readfirstlane(ldx);
   M = __builtin_amdgcn_readfirstlane(M);
@@ -240,8 +241,10 @@ __device__ void wg_apply_q2_regs(const double *__restrict__ A, int n, double *X,
                                  double *ex) {
   constexpr int b = kBand;
   // the arguments are wave-uniform (out of line they arrive in vector registers)
-  A = uniform_ptr(A);
-  X = uniform_ptr(X);
+  A = global_ptr(uniform_ptr(A));
+  X = global_ptr(uniform_ptr(X));
+  runs = lds_ptr(runs);
+  ex = lds_ptr(ex);
   n = __builtin_amdgcn_readfirstlane(n);
   ldx = __builtin_amdgcn_readfirstlane(ldx);
   nc = __builtin_amdgcn_readfirstlane(nc);
