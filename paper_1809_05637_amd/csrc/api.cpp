@@ -53,7 +53,7 @@ void free_all(Plan &p) {
                   p.d_pair_ptr, p.d_pair_ab,  p.d_pair_blk, p.d_fna_ptr, p.d_fna_blk, p.d_p_rows,   p.d_dmax,
                   p.d_order,    p.d_mat_off,  p.d_vec_off,  p.d_ivec_off, p.d_mat,    p.d_vec,      p.d_ivec,
                   p.d_dim,      p.d_rank,     p.d_U,        p.d_lambda,  p.d_fixed,   p.d_mu,       p.d_partial,
-                  p.d_counter,  p.d_status,   p.d_lno_blk,  p.d_row_elem};
+                  p.d_counter,  p.d_status,   p.d_lno_blk,  p.d_row_elem, p.d_queue};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   for (int s = 0; s < LDC_NUM_STAGES; ++s) {
@@ -525,11 +525,12 @@ ldc_status ldc_plan_create(ldc_plan_t *out, int n_atoms, const double *pos, cons
   TRY(dev_alloc(p, &p.d_mu, 32));
   TRY(dev_alloc(p, &p.d_partial, (size_t)(16 * p.workgroups + 2 * n_atoms)));  // mu tree partials, cluster pairs
   TRY(dev_alloc(p, &p.d_counter, 4));
+  TRY(dev_alloc(p, &p.d_queue, 2));
   TRY(dev_alloc(p, &p.d_status, 1));
 #undef TRY
   if (hipMemset(p.d_status, 0, sizeof(ldc::DevStatus)) != hipSuccess || hipMemset(p.d_mu, 0, 32 * sizeof(double)) !=
                                                                                hipSuccess ||
-      hipMemset(p.d_counter, 0, 4 * sizeof(int)) != hipSuccess ||
+      hipMemset(p.d_counter, 0, 4 * sizeof(int)) != hipSuccess || hipMemset(p.d_queue, 0, 2 * sizeof(int)) != hipSuccess ||
       hipHostMalloc((void **)&p.h_fixed, sizeof(int) * (size_t)n_atoms, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void **)&p.h_out, sizeof(double) * 40, hipHostMallocDefault) != hipSuccess ||
       hipEventCreateWithFlags(&p.ev_fixed, hipEventDisableTiming) != hipSuccess) {

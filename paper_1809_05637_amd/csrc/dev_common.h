@@ -25,6 +25,30 @@ __device__ inline T *lds_ptr(T *p) {
   return (T *)(lT *)(unsigned)reinterpret_cast<unsigned long long>(p);
 }
 
+// Clusters handed to workgroups as they become free: each workgroup takes the next index of the
+// processing order (largest clusters first), so the last, smallest clusters go to whichever
+// workgroups finish first instead of to a fixed stride.  q[0] is the next index, q[1] the number of
+// workgroups that have left the loop; the last to leave resets both, so the queue reads zero at the
+// next launch (the plan zeroes it once, when it is created).  Every workgroup calls queue_next
+// until it returns an index past the end, then queue_leave once.  The result does not depend on
+// which workgroup takes which cluster (each cluster's work is its workgroup's alone).
+__device__ inline int queue_next(int *q) {
+  __shared__ int next;
+  __syncthreads();
+  if (threadIdx.x == 0) next = atomicAdd(&q[0], 1);
+  __syncthreads();
+  return next;
+}
+__device__ inline void queue_leave(int *q) {
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(&q[1], 1) == (int)gridDim.x - 1) {
+      atomicExch(&q[0], 0);
+      atomicExch(&q[1], 0);
+    }
+  }
+}
+
 // First error wins; later errors are dropped.
 __device__ inline void report(DevStatus *st, int code, int where) {
   if (atomicCAS(&st->code, 0, code) == 0) atomicExch(&st->where, where);

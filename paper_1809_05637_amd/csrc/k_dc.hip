@@ -825,10 +825,10 @@ __global__ void __launch_bounds__(256, 3) stedc_kernel(int n_clusters, const int
                                                     double *__restrict__ vec, const long long *__restrict__ vec_off,
                                                     int *__restrict__ ivec, const long long *__restrict__ ivec_off,
                                                     const int *__restrict__ dmax, const int *__restrict__ dim,
-                                                    const int *__restrict__ n_orb, DevStatus *st, int nmax) {
-  extern __shared__ double dsh[];
+                                                    const int *__restrict__ n_orb, DevStatus *st, int nmax, int *__restrict__ queue) {
+  extern __shared__ __attribute__((aligned(16))) double dsh[];
   const DcLds S = dc_lds(dsh, nmax);
-  for (int s = blockIdx.x; s < n_clusters; s += gridDim.x) {
+  for (int s = queue_next(queue); s < n_clusters; s = queue_next(queue)) {
     const int c = order[s];
     const int n = dim[c];
     const int M = n_orb[c];
@@ -847,6 +847,7 @@ __global__ void __launch_bounds__(256, 3) stedc_kernel(int n_clusters, const int
     }
     __syncthreads();
   }
+  queue_leave(queue);
 }
 
 void launch_stedc(Plan &p) {
@@ -861,7 +862,7 @@ void launch_stedc(Plan &p) {
   const int n = cur_count(p);
   const int grid = std::max(1, std::min(stage_grid(p, kTStedc, 3 * p.n_cu), n));
   hipLaunchKernelGGL(stedc_kernel, dim3(grid), dim3(kWG), lds, p.stream, n, cur_order(p), p.d_vec, p.d_vec_off,
-                     p.d_ivec, p.d_ivec_off, p.d_dmax, p.d_dim, p.d_n_orb, p.d_status, dm);
+                     p.d_ivec, p.d_ivec_off, p.d_dmax, p.d_dim, p.d_n_orb, p.d_status, dm, p.d_queue);
 }
 
 }  // namespace ldc

@@ -261,16 +261,16 @@ __global__ void __launch_bounds__(256, 2) density_kernel(
     const int *__restrict__ n_orb, const int *__restrict__ p_rows, const int *__restrict__ mem_ptr,
     const int *__restrict__ mem_atom, const int *__restrict__ fna_ptr, const int *__restrict__ fna_blk,
     const long long *__restrict__ blk_off, const double *__restrict__ state, const double *__restrict__ H,
-    const double *__restrict__ S, double *__restrict__ Dout, double *__restrict__ partial, int max_dim) {
+    const double *__restrict__ S, double *__restrict__ Dout, double *__restrict__ partial, int max_dim, int *__restrict__ queue) {
   __shared__ double red[16 * 17];
   __shared__ double sred[8];
   __shared__ int foff[kMaxMembers + 1];
   // dynamic LDS (kDensityLds doubles): the merge product's secular data, then Q2's reflector
   // runs and row exchange, then Q1's partial products
-  extern __shared__ double qlds[];
+  extern __shared__ __attribute__((aligned(16))) double qlds[];
   const int tid = threadIdx.x, nthr = blockDim.x;
   const double mu = state[MU_MU], kT = state[MU_KT];
-  for (int s = blockIdx.x; s < n_clusters; s += gridDim.x) {
+  for (int s = queue_next(queue); s < n_clusters; s = queue_next(queue)) {
     const int c = order[s];
     const int n = dim[c], ld = n;
     const int M = n_orb[c];
@@ -342,6 +342,7 @@ __global__ void __launch_bounds__(256, 2) density_kernel(
       partial[2 * c + 1] = es;
     }
   }
+  queue_leave(queue);
 }
 
 __global__ void sum_pairs_kernel(int n, const double *__restrict__ partial, double *__restrict__ out) {
@@ -381,7 +382,7 @@ void launch_density(Plan &p, int mode, double *d_D, const double *d_H, const dou
   hipLaunchKernelGGL(density_kernel, dim3(grid), dim3(kWG), lds, p.stream, mode, w_lo, w_hi, w_kT, n, cur_order(p),
                      p.d_mat, p.d_mat_off, p.d_vec, p.d_vec_off, p.d_ivec, p.d_ivec_off, p.d_dmax, p.d_dim, p.d_n_orb,
                      p.d_p_rows, p.d_mem_ptr, p.d_mem_atom, p.d_fna_ptr, p.d_fna_blk, p.d_blk_off, p.d_mu, d_H, d_S,
-                     d_D, cl_partial, dm);
+                     d_D, cl_partial, dm, p.d_queue);
 }
 
 void launch_density_sums(Plan &p, int mode) {

@@ -112,15 +112,15 @@ __global__ void __launch_bounds__(256) gather_kernel(int n_clusters, const int *
                                                      const double *__restrict__ lno_blk, long long total,
                                                      double *__restrict__ mat,
                                                      const long long *__restrict__ mat_off, const int *__restrict__ dmax,
-                                                     int *__restrict__ dim, int round32) {
-  extern __shared__ unsigned short rowmem[];
+                                                     int *__restrict__ dim, int round32, int *__restrict__ queue) {
+  extern __shared__ __attribute__((aligned(16))) unsigned short rowmem[];
   __shared__ int off[kMaxMembers + 1];
   __shared__ int dm[kMaxMembers];
   __shared__ unsigned char lng[kMaxMembers];
   __shared__ int rs[kMaxMembers], re[kMaxMembers];  // pairs of member row a: [rs[a], re[a])
   __shared__ long long pbo[kMaxMembers];            // block offset of (b, a) for the current b, or -1
   const int tid = threadIdx.x;
-  for (int s = blockIdx.x; s < n_clusters; s += gridDim.x) {
+  for (int s = queue_next(queue); s < n_clusters; s = queue_next(queue)) {
     const int c = order[s];
     const int mb = mem_ptr[c], nm = mem_ptr[c + 1] - mb;
     const int p0 = pair_ptr[c], p1 = pair_ptr[c + 1];
@@ -195,6 +195,7 @@ __global__ void __launch_bounds__(256) gather_kernel(int n_clusters, const int *
       }
     }
   }
+  queue_leave(queue);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -275,13 +276,13 @@ __device__ inline void lds_tri_inverse(double (*L11)[NB + 1], double (*Li)[NB + 
 __global__ void __launch_bounds__(256, 2) potrf_kernel(int n_clusters, const int *__restrict__ order,
                                                        double *__restrict__ mat, const long long *__restrict__ mat_off,
                                                        const int *__restrict__ dmax, const int *__restrict__ dim,
-                                                       DevStatus *st) {
+                                                       DevStatus *st, int *__restrict__ queue) {
   __shared__ double L11[NB][NB + 1];
   __shared__ double Li[NB][NB + 1];
   __shared__ double gl[kGemmLds];
   __shared__ int bad;
   const int tid = threadIdx.x;
-  for (int s = blockIdx.x; s < n_clusters; s += gridDim.x) {
+  for (int s = queue_next(queue); s < n_clusters; s = queue_next(queue)) {
     const int c = order[s];
     const int n = dim[c], ld = n;
     double *S = mat + mat_off[c] + (long long)dmax[c] * dmax[c];
@@ -356,6 +357,7 @@ __global__ void __launch_bounds__(256, 2) potrf_kernel(int n_clusters, const int
     __syncthreads();
     if (bad && tid == 0) report(st, LDC_ERR_NOT_SPD, c);
   }
+  queue_leave(queue);
 }
 
 // Standard form (Sec. II.C (iii) via Cholesky): with S = L L^T and H = H_L + H_L^T (H_L the lower
@@ -382,7 +384,7 @@ __global__ void __launch_bounds__(256, 2) sygst_kernel(int n_clusters, const int
                                                     double *__restrict__ mat, const long long *__restrict__ mat_off,
                                                     double *__restrict__ vec, const long long *__restrict__ vec_off,
                                                     const int *__restrict__ dmax, const int *__restrict__ dim,
-                                                    const int *__restrict__ n_orb) {
+                                                    const int *__restrict__ n_orb, int *__restrict__ queue) {
   // GEMM staging; the four NB x NB blocks of the inversion share it (they are dead whenever
   // a product runs)
   constexpr int kInvLds = 4 * NB * (NB + 1);
@@ -392,7 +394,7 @@ __global__ void __launch_bounds__(256, 2) sygst_kernel(int n_clusters, const int
   double(*Pi)[NB + 1] = Li + NB;
   double(*Bq)[NB + 1] = Pi + NB;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  for (int s = blockIdx.x; s < n_clusters; s += gridDim.x) {
+  for (int s = queue_next(queue); s < n_clusters; s = queue_next(queue)) {
     const int c = order[s];
     const int n = dim[c], ld = n;
     const int M = n_orb[c];
@@ -496,6 +498,7 @@ __global__ void __launch_bounds__(256, 2) sygst_kernel(int n_clusters, const int
                                                                                r1, gl, -1, 0, H + r0, L);
     }
   }
+  queue_leave(queue);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -518,14 +521,14 @@ void launch_gather(Plan &p, const double *d_H, const double *d_S) {
   hipLaunchKernelGGL(gather_kernel, dim3(grid), dim3(kWG), sizeof(unsigned short) * cur_dim(p), p.stream, n,
                      cur_order(p), p.d_mem_ptr, p.d_mem_atom, p.d_mem_long, p.d_pair_ptr, p.d_pair_ab, p.d_pair_blk,
                      p.d_n_orb, p.d_blk_off, d_H, d_S, p.lno_mode, p.d_rank, p.d_lno_blk, p.blk_total, p.d_mat,
-                     p.d_mat_off, p.d_dmax, p.d_dim, p.opt.prec == LDC_MIXED_FP32 ? 1 : 0);
+                     p.d_mat_off, p.d_dmax, p.d_dim, p.opt.prec == LDC_MIXED_FP32 ? 1 : 0, p.d_queue);
 }
 
 void launch_potrf(Plan &p) {
   const int n = cur_count(p);
   const int grid = std::max(1, std::min(stage_grid(p, kTPotrf, p.workgroups), n));
   hipLaunchKernelGGL(potrf_kernel, dim3(grid), dim3(kWG), 0, p.stream, n, cur_order(p), p.d_mat, p.d_mat_off, p.d_dmax,
-                     p.d_dim, p.d_status);
+                     p.d_dim, p.d_status, p.d_queue);
 }
 
 void launch_sygst(Plan &p) {
@@ -533,10 +536,10 @@ void launch_sygst(Plan &p) {
   const int grid = std::max(1, std::min(stage_grid(p, kTSygst, p.workgroups), n));
   if (p.opt.prec == LDC_MIXED_FP32)
     hipLaunchKernelGGL(sygst_kernel<float>, dim3(grid), dim3(kWG), 0, p.stream, n, cur_order(p), p.d_mat,
-                       p.d_mat_off, p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb);
+                       p.d_mat_off, p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb, p.d_queue);
   else
     hipLaunchKernelGGL(sygst_kernel<double>, dim3(grid), dim3(kWG), 0, p.stream, n, cur_order(p), p.d_mat,
-                       p.d_mat_off, p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb);
+                       p.d_mat_off, p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb, p.d_queue);
 }
 
 }  // namespace ldc

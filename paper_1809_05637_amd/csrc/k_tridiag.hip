@@ -332,13 +332,13 @@ __global__ void __launch_bounds__(256, 2) sy2sb_kernel(int n_clusters, const int
                                                        double *__restrict__ mat, const long long *__restrict__ mat_off,
                                                        double *__restrict__ vec, const long long *__restrict__ vec_off,
                                                        const int *__restrict__ dmax, const int *__restrict__ dim,
-                                                       const int *__restrict__ n_orb) {
-  extern __shared__ double sh[];
+                                                       const int *__restrict__ n_orb, int *__restrict__ queue) {
+  extern __shared__ __attribute__((aligned(16))) double sh[];
   __shared__ double sm[2 * LEAF * LEAF + 4 * LEAF];
   __shared__ double red[10 * LEAF];
   const int tid = threadIdx.x, nthr = blockDim.x;
   constexpr int b = kBand;
-  for (int s = blockIdx.x; s < n_clusters; s += gridDim.x) {
+  for (int s = queue_next(queue); s < n_clusters; s = queue_next(queue)) {
     const int c = order[s];
     const int n = dim[c], ld = n;
     const int M = n_orb[c];
@@ -361,6 +361,7 @@ __global__ void __launch_bounds__(256, 2) sy2sb_kernel(int n_clusters, const int
       band_panel(A, ld, n, j0, tt, Tp, VW, VT, Kst, Gst, sh, sm, red);
     }
   }
+  queue_leave(queue);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -673,7 +674,7 @@ __device__ inline void chase_pair(__amdgpu_buffer_rsrc_t band, double (&P)[kBand
 __global__ void __launch_bounds__(64 * kChaseWaves, kChaseOcc) sb2st_kernel(int n_clusters, const int *__restrict__ order,
                                                     double *__restrict__ mat, const long long *__restrict__ mat_off,
                                                     double *__restrict__ vec, const long long *__restrict__ vec_off,
-                                                    const int *__restrict__ dmax, const int *__restrict__ dim) {
+                                                    const int *__restrict__ dmax, const int *__restrict__ dim, int *__restrict__ queue) {
   __shared__ double wsv[kChaseWaves][kBand];
   __shared__ double wtile[kChaseWaves][kBand * (kBand + 1)];
   __shared__ double slots[kChaseWaves][2][kBand + 1];
@@ -683,7 +684,7 @@ __global__ void __launch_bounds__(64 * kChaseWaves, kChaseOcc) sb2st_kernel(int 
   // wave-uniform (buffer offsets in vector registers would need a loop over lanes)
   const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), nthr = blockDim.x, nw = nthr >> 6;
   constexpr int LB = kBandLd;
-  for (int sidx = blockIdx.x; sidx < n_clusters; sidx += gridDim.x) {
+  for (int sidx = queue_next(queue); sidx < n_clusters; sidx = queue_next(queue)) {
     const int c = order[sidx];
     const int n = dim[c], ld = n;
     double *A = mat + mat_off[c];
@@ -733,6 +734,7 @@ __global__ void __launch_bounds__(64 * kChaseWaves, kChaseOcc) sb2st_kernel(int 
       ee[i] = (i < n - 1) ? Bd[(long long)i * LB + 1] : 0.0;
     }
   }
+  queue_leave(queue);
 }
 
 // The two halves of the tracked-column product, out of line (each holds X in registers in its own
@@ -752,9 +754,9 @@ __global__ void __launch_bounds__(256, 2) q2x_kernel(int n_clusters, const int *
                                                   const double *__restrict__ mat, const long long *__restrict__ mat_off,
                                                   double *__restrict__ vec, const long long *__restrict__ vec_off,
                                                   const int *__restrict__ dmax, const int *__restrict__ dim,
-                                                  const int *__restrict__ n_orb) {
-  extern __shared__ double q2l[];
-  for (int item = blockIdx.x; item < 2 * n_clusters; item += gridDim.x) {
+                                                  const int *__restrict__ n_orb, int *__restrict__ queue) {
+  extern __shared__ __attribute__((aligned(16))) double q2l[];
+  for (int item = queue_next(queue); item < 2 * n_clusters; item = queue_next(queue)) {
     const int c = order[item >> 1], half = item & 1;
     const int n = dim[c], nc = n_orb[c];
     const VecLayout vl = VecLayout::make(dmax[c]);
@@ -766,6 +768,7 @@ __global__ void __launch_bounds__(256, 2) q2x_kernel(int n_clusters, const int *
     if (n < 3) continue;
     q2t_tracked(A, n, X, nc, q2l, q2l + 3LL * q2_lds_stride(n));
   }
+  queue_leave(queue);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -775,7 +778,7 @@ void launch_sy2sb(Plan &p) {
   const int n = cur_count(p);
   const int grid = std::max(1, std::min(stage_grid(p, kTSy2sb, p.workgroups), n));
   hipLaunchKernelGGL(sy2sb_kernel, dim3(grid), dim3(kWG), lds, p.stream, n, cur_order(p), p.d_mat, p.d_mat_off,
-                     p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb);
+                     p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb, p.d_queue);
 }
 
 void launch_sb2st(Plan &p) {
@@ -783,7 +786,7 @@ void launch_sb2st(Plan &p) {
   const int n = cur_count(p);
   const int grid = std::max(1, std::min(stage_grid(p, kTSb2st, p.n_cu * 4 * kChaseOcc / kChaseWaves), n));
   hipLaunchKernelGGL(sb2st_kernel, dim3(grid), dim3(64 * kChaseWaves), 0, p.stream, n, cur_order(p), p.d_mat,
-                     p.d_mat_off, p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim);
+                     p.d_mat_off, p.d_vec, p.d_vec_off, p.d_dmax, p.d_dim, p.d_queue);
 }
 
 void launch_q2x(Plan &p) {
@@ -791,7 +794,7 @@ void launch_q2x(Plan &p) {
   const int n = cur_count(p);
   const int grid = std::max(1, std::min(stage_grid(p, kTQ2x, 2 * p.n_cu), 2 * n));
   hipLaunchKernelGGL(q2x_kernel, dim3(grid), dim3(kWG), lds, p.stream, n, cur_order(p), p.d_mat, p.d_mat_off, p.d_vec,
-                     p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb);
+                     p.d_vec_off, p.d_dmax, p.d_dim, p.d_n_orb, p.d_queue);
 }
 
 }  // namespace ldc

@@ -115,6 +115,7 @@ struct Plan {
   double *d_mu = nullptr;           // [lo, hi, mid, done, n_at_mid, bracket checks...]
   double *d_partial = nullptr;      // per-workgroup partial sums
   int *d_counter = nullptr;
+  int *d_queue = nullptr;           // cluster work queue of the per-cluster kernels (2 ints)
   DevStatus *d_status = nullptr;
 
   // stage timing (HIP events on the plan's stream)
