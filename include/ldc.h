@@ -200,8 +200,10 @@ ldc_status ldc_tune(ldc_plan_t plan, const double *d_H, const double *d_S, const
  * buffers; mu, E_band and N_e go to d_result (device, 3 doubles, in that order).  The density
  * rows, mu, E_band and N_e equal ldc_density's for the same solve.  Limits: at most 65536
  * atoms and 2048 workgroups per plan, else LDC_ERR_LIMIT with a message.  All calls on one GPU
- * share the array: calls that overlap in time on one GPU (two streams, two threads) race.
- * Errors inside kernels are reported by the next call that synchronizes. */
+ * share the array: calls that overlap in time on one GPU (two streams, two threads) race.  The
+ * density kernel's cluster work queue is the plan's own (allocated with the plan), so calls on
+ * one plan must not overlap either.  Errors inside kernels are reported by the next call that
+ * synchronizes. */
 ldc_status ldc_density_noalloc(ldc_plan_t plan, double n_electrons, double kT, double *d_D_out, double *d_result);
 
 /* Density rows at a given chemical potential (no bisection); otherwise as ldc_density. */
